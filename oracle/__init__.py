@@ -1,0 +1,26 @@
+"""CPU oracle for the HPS hot path — TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously correct fp64 NumPy/SciPy implementation of what the
+GPU library computes, written from the paper (arXiv 2503.17535, Sections 3.1-3.3,
+Appendices A and C).  It shares no code with the HIP library and neither
+imports the other; only the seeded input generators in ``workloads`` serve
+both.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import or execute anything in this package.  The product
+path (``paper_2503_17535_amd``) never falls back to it.
+
+Modules:
+
+* ``spectral`` — Chebyshev--Lobatto nodes, Gauss--Legendre rule (Golub--Welsch),
+  barycentric interpolation, spectral differentiation.
+* ``hps``      — leaf discretization (P, Q), local solves, 2D/3D merges, downward
+  pass, source-split upward pass.
+* ``dense``    — the composite collocation system assembled densely (tiny trees),
+  an independent check of ``hps``.
+* ``adjoint``  — transposed solve and the misfit gradient.
+
+Parity status: every function is pinned by the ``-m "not gpu"`` tests against
+closed forms, library routines, the dense system or values printed in the
+paper, except where a docstring says "parity unpinned".
+"""

@@ -1,0 +1,174 @@
+/*
+ * hps.h - C ABI of the MI355X (gfx950) hierarchical Poincare-Steklov (HPS)
+ * fast direct solver: batched leaf solves, level-by-level DtN merges and the
+ * downward solve of arXiv 2503.17535 (Sections 3.1-3.4, Appendices A and C).
+ *
+ * Problem (Section 1, eqs. elliptic_BVP / dirichlet_data):
+ *     L u = f  in  Omega = [lo, hi]^d,   u = g  on the boundary,
+ *     L u = sum_t c_t(x) d_t u   (second-order, variable coefficients).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Uniform tree of depth L: n_leaves = 2^(d L) leaves, numbered depth first
+ *   (the 2^d children of a node are contiguous; child order a,b,c,d =
+ *   SW,SE,NE,NW, and in 3D e..h directly above a..d).
+ * - Leaf points: p^d Chebyshev-Lobatto points (ascending -cos(pi j/(p-1))),
+ *   point index ix + p*iy (+ p^2*iz).  hps_leaf_points() returns them.
+ * - Coefficient terms (t): 2D  c_xx, c_xy, c_yy, c_x, c_y, c_0      (6);
+ *                          3D  c_xx, c_yy, c_zz, c_xy, c_xz, c_yz,
+ *                              c_x, c_y, c_z, c_0                    (10).
+ * - Boundary data g lives at the q = p-2 Gauss-Legendre points of every leaf
+ *   face on the domain boundary, in the order hps_boundary_points() returns
+ *   (faces x-,x+,y-,y+,z-,z+ / sides S,E,N,W; each face the concatenation of
+ *   its sub-faces in quadrant order).
+ * - Arrays are fp64, C order, as documented per argument.  "dev" arrays are
+ *   device (HBM) pointers, "host" arrays host pointers.  All array arguments
+ *   are owned by the caller and only borrowed for the call (for dev arrays:
+ *   until the work queued on the given stream has completed).
+ * - Streams are hipStream_t passed as void* (NULL = default stream).
+ * - Every int-returning function returns HPS_OK or an error code and never
+ *   throws; hps_last_error() describes the last failure of the calling thread.
+ */
+#ifndef HPS_H_
+#define HPS_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HPS_OK = 0,
+  HPS_EINVAL = 1,        /* bad argument (null pointer, p or depth out of range) */
+  HPS_ENOMEM = 2,        /* device or host allocation failed                      */
+  HPS_ESINGULAR = 3,     /* zero pivot in a leaf (L_ii) or merge (D) factorization */
+  HPS_EDEVICE = 4,       /* HIP runtime error (message has the HIP error string)  */
+  HPS_EUNSUPPORTED = 5   /* valid request outside what this build implements      */
+};
+
+/* build flags */
+enum {
+  HPS_FLAG_ROOT_T = 1,     /* also form the root DtN matrix (unused by Dirichlet solves) */
+  HPS_FLAG_NO_CHECK = 2,   /* do not synchronize at the end of hps_build to check pivots */
+  HPS_FLAG_TIMING = 4,     /* record per-stage HIP events (read with hps_stage_times)   */
+  HPS_FLAG_FP32_COPY = 8   /* keep fp32 copies of the solve operators (mixed precision) */
+};
+
+/* solve precision */
+enum { HPS_FP64 = 0, HPS_FP32_REFINED = 1 };
+
+typedef struct {
+  int dim;        /* 2 or 3 */
+  int depth;      /* L >= 1 (2D: L <= 12, 3D: L <= 5) */
+  double lo;      /* domain [lo, hi]^dim */
+  double hi;
+} hps_tree_t;
+
+typedef struct {
+  long long n_leaves;     /* 2^(dim*depth)                           */
+  int pts_per_leaf;       /* p^dim                                   */
+  int n_terms;            /* 6 (2D) or 10 (3D)                       */
+  long long n_root_bdry;  /* Gauss points on the domain boundary     */
+  int n_interior;         /* (p-2)^dim interior points per leaf      */
+  int n_leaf_bdry;        /* 2*dim*(p-2)^(dim-1) Gauss points / leaf */
+  int n_levels;           /* merge levels = depth                    */
+  long long root_D;       /* size of the root merge's D              */
+} hps_sizes_t;
+
+typedef struct hps_op hps_op_t;   /* opaque; owned by the library until hps_free */
+
+/* Sizes of the discretization (host only, no device work). */
+int hps_sizes(const hps_tree_t* tree, int p, hps_sizes_t* out);
+
+/* Leaf Chebyshev points, host array xyz[n_leaves][p^dim][dim] (caller-allocated).
+ * Callers sample coefficients and sources at these points (Section 1: the
+ * method evaluates L, f, g at points of its choosing). */
+int hps_leaf_points(const hps_tree_t* tree, int p, double* xyz);
+
+/* Root-boundary Gauss points, host array xyz[n_root_bdry][dim]; the order in
+ * which hps_solve reads boundary data. */
+int hps_boundary_points(const hps_tree_t* tree, int p, double* xyz);
+
+/* Device bytes an operator built with these arguments keeps resident
+ * (excluding the transient build workspace), for admission control. */
+size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags);
+
+/* Build stage (Algorithm local_solve, Algorithm merge; App. A.1-A.2, C.1-C.2):
+ * per leaf LU of L(I_i,I_i), Y = -L_ii^{-1} L_ie P, T = Q Y; per merge
+ * D^{-1}, S = -D^{-1} C and the parent T = A - B D^{-1} C, for all levels.
+ *   coeffs  dev  [n_leaves][n_terms][p^dim] coefficient samples
+ *   flags   HPS_FLAG_*
+ *   stream  hipStream_t the build is queued on
+ *   out     receives the operator handle (NULL on error)
+ * Device memory for the operator is allocated by the library.  Unless
+ * HPS_FLAG_NO_CHECK is set the call synchronizes the stream once at its end
+ * and returns HPS_ESINGULAR if a pivot was exactly zero or not finite. */
+int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
+              void* stream, hps_op_t** out);
+
+/* Solve stage (Algorithm down_pass, with the source entering through the
+ * linear upward pass of the particular solution, Section 3):
+ *   bdry  dev  [nrhs][n_root_bdry]        Dirichlet data g at the root Gauss points
+ *   src   dev  [nrhs][n_leaves][p^dim]    f at the leaf points, or NULL for f = 0
+ *   u     dev  [nrhs][n_leaves][p^dim]    output: solution at every leaf point
+ *   nrhs  >= 1; precision HPS_FP64 (HPS_FP32_REFINED needs HPS_FLAG_FP32_COPY)
+ * Asynchronous on `stream`; errors from earlier device work surface as
+ * HPS_EDEVICE on a later call. */
+int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u,
+              int nrhs, int precision, void* stream);
+
+/* Adjoint (transposed) solve: for w dev [nrhs][n_leaves][p^dim] returns the
+ * source-space adjoint lam_src dev [nrhs][n_leaves][p^dim] (zero at leaf
+ * boundary points) and the boundary-space adjoint lam_bdry dev
+ * [nrhs][n_root_bdry] (may be NULL), i.e. G^T w for the linear map
+ * G: (f, g) -> u of hps_solve.  Asynchronous like hps_solve. */
+int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src,
+                      double* lam_bdry, int nrhs, void* stream);
+
+/* Per-stage device times (ms) of the last build/solve queued with
+ * HPS_FLAG_TIMING: names[i] (static strings) and ms[i], up to cap entries.
+ * Synchronizes the op's stream.  Returns the number of entries, or < 0. */
+int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap);
+
+/* Resident device bytes of a built operator. */
+size_t hps_op_bytes(const hps_op_t* op);
+
+/* Release the operator and its device memory (after its queued work). */
+void hps_free(hps_op_t* op);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* hps_last_error(void);
+
+/* Operator inspection, for tests: copies an internal device buffer of a
+ * built operator to host memory (synchronizes the op's stream).  which:
+ *   0 leaf LU factors   [n_leaves][n_i*n_i]  (rows in original order)
+ *   1 leaf pivot order  [n_leaves][n_i]      (as doubles)
+ *   2 leaf Y_int        [n_leaves][n_i*n_b]  (column-major)
+ *   3 leaf T            [n_leaves][n_b*n_b]
+ *   4 merge D^{-1} of tree level `level`   [merges][m*m]
+ *   5 merge S of tree level `level`        [merges][m*n_parent]
+ *   6 merge parent T of tree level `level` [merges][n_parent^2]
+ * Returns the number of doubles written, or a negative error code. */
+long long hps_debug_download(const hps_op_t* op, int which, int level, double* out, long long cap);
+
+/* Kernel check, for tests: the library's grouped MFMA GEMM on one product,
+ *   C = alpha op(A) op(B) + beta C   (column-major, dev pointers, fp64),
+ * op(X) = X or X^T per trans_a / trans_b.  Asynchronous on `stream`. */
+int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, int trans_a,
+                   const double* b, int ldb, int trans_b, double beta, double* c, int ldc,
+                   void* stream);
+
+/* Host precompute inspection, for tests (no device work).  which:
+ *   0 Chebyshev nodes (p), 1 Gauss nodes (q), 2 Gauss weights (q),
+ *   3 D (p x p), 4 P (n_e x n_b), 5 Q on [-1,1]^dim (n_b x p^dim),
+ *   6 interior index list I_i (n_i), 7 exterior index list I_e (n_e)
+ * Writes row-major into out (capacity cap doubles) and the shape into
+ * rows/cols. */
+int hps_precompute_matrix(int dim, int p, int which, double* out, long long cap,
+                          int* rows, int* cols);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H_ */

@@ -1,0 +1,230 @@
+"""MI355X-native hierarchical Poincare-Steklov (HPS) fast direct solver.
+
+Thin Python binding over the C ABI of ``libhps.so`` (declared in
+``include/hps.h``): argument marshalling only, every step of the build and the
+solve runs in the library's HIP kernels.  PyTorch supplies device memory and
+streams.  Importing this package does not need a GPU; building or solving
+does, and fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhps.so")
+
+HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_ESINGULAR, HPS_EDEVICE, HPS_EUNSUPPORTED = range(6)
+FLAG_ROOT_T, FLAG_NO_CHECK, FLAG_TIMING, FLAG_FP32_COPY = 1, 2, 4, 8
+FP64, FP32_REFINED = 0, 1
+
+# every entry point include/hps.h declares
+EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footprint",
+           "hps_build", "hps_solve", "hps_solve_adjoint", "hps_stage_times",
+           "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
+           "hps_debug_download", "hps_debug_gemm")
+
+
+class HPSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"HPS error {code}: {msg}")
+        self.code = code
+
+
+class Tree(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("depth", ctypes.c_int),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_longlong), ("pts_per_leaf", ctypes.c_int),
+                ("n_terms", ctypes.c_int), ("n_root_bdry", ctypes.c_longlong),
+                ("n_interior", ctypes.c_int), ("n_leaf_bdry", ctypes.c_int),
+                ("n_levels", ctypes.c_int), ("root_D", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2503_17535_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, LL, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
+        TP = ctypes.POINTER(Tree)
+        L.hps_sizes.argtypes = [TP, I, ctypes.POINTER(Sizes)]
+        L.hps_leaf_points.argtypes = [TP, I, P]
+        L.hps_boundary_points.argtypes = [TP, I, P]
+        L.hps_op_footprint.argtypes = [TP, I, I]
+        L.hps_op_footprint.restype = S
+        L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
+        L.hps_solve.argtypes = [P, P, P, P, I, I, P]
+        L.hps_solve_adjoint.argtypes = [P, P, P, P, I, P]
+        L.hps_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D), I]
+        L.hps_op_bytes.argtypes = [P]
+        L.hps_op_bytes.restype = S
+        L.hps_free.argtypes = [P]
+        L.hps_free.restype = None
+        L.hps_last_error.restype = ctypes.c_char_p
+        L.hps_debug_download.argtypes = [P, I, I, P, LL]
+        L.hps_debug_download.restype = LL
+        L.hps_debug_gemm.argtypes = [I, I, I, D, P, I, I, P, I, I, D, P, I, P]
+        L.hps_precompute_matrix.argtypes = [I, I, I, P, LL, ctypes.POINTER(I), ctypes.POINTER(I)]
+        for name in EXPORTS:
+            if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error",
+                            "hps_debug_download", "hps_debug_gemm"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != HPS_OK:
+        raise HPSError(rc, lib().hps_last_error().decode())
+
+
+def tree(dim: int, depth: int, lo: float = -1.0, hi: float = 1.0) -> Tree:
+    return Tree(dim, depth, lo, hi)
+
+
+def sizes(t: Tree, p: int) -> Sizes:
+    s = Sizes()
+    _check(lib().hps_sizes(ctypes.byref(t), p, ctypes.byref(s)))
+    return s
+
+
+def leaf_points(t: Tree, p: int) -> np.ndarray:
+    s = sizes(t, p)
+    out = np.empty((s.n_leaves, s.pts_per_leaf, t.dim))
+    _check(lib().hps_leaf_points(ctypes.byref(t), p, out.ctypes.data))
+    return out
+
+
+def boundary_points(t: Tree, p: int) -> np.ndarray:
+    s = sizes(t, p)
+    out = np.empty((s.n_root_bdry, t.dim))
+    _check(lib().hps_boundary_points(ctypes.byref(t), p, out.ctypes.data))
+    return out
+
+
+def footprint(t: Tree, p: int, flags: int = 0) -> int:
+    return int(lib().hps_op_footprint(ctypes.byref(t), p, flags))
+
+
+def precompute_matrix(dim: int, p: int, which: int) -> np.ndarray:
+    cap = max(p ** dim * 6 * (p - 2) ** (dim - 1), p * p) * 2
+    buf = np.empty(cap)
+    r, c = ctypes.c_int(), ctypes.c_int()
+    _check(lib().hps_precompute_matrix(dim, p, which, buf.ctypes.data, cap, ctypes.byref(r), ctypes.byref(c)))
+    return buf[: r.value * c.value].reshape(r.value, c.value).copy()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A built HPS solution operator, resident in device memory."""
+
+    def __init__(self, t: Tree, p: int, coeffs, flags: int = 0, stream=None):
+        self.tree, self.p, self.flags = t, p, flags
+        self.sizes = sizes(t, p)
+        s = self.sizes
+        ptr = _dev_ptr(coeffs, "coeffs", (s.n_leaves, s.n_terms, s.pts_per_leaf))
+        h = ctypes.c_void_p()
+        _check(lib().hps_build(ctypes.byref(t), p, ptr, flags, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, bdry, src=None, out=None, stream=None, precision: int = FP64):
+        import torch
+        s = self.sizes
+        nrhs = bdry.shape[0]
+        bptr = _dev_ptr(bdry, "bdry", (nrhs, s.n_root_bdry))
+        sptr = None if src is None else _dev_ptr(src, "src", (nrhs, s.n_leaves, s.pts_per_leaf))
+        if out is None:
+            out = torch.empty((nrhs, s.n_leaves, s.pts_per_leaf), dtype=torch.float64, device=bdry.device)
+        uptr = _dev_ptr(out, "u", (nrhs, s.n_leaves, s.pts_per_leaf))
+        _check(lib().hps_solve(self._h, bptr, sptr, uptr, nrhs, precision, _stream_ptr(stream)))
+        return out
+
+    def solve_adjoint(self, w, lam_src=None, lam_bdry=None, stream=None):
+        import torch
+        s = self.sizes
+        nrhs = w.shape[0]
+        wptr = _dev_ptr(w, "w", (nrhs, s.n_leaves, s.pts_per_leaf))
+        if lam_src is None:
+            lam_src = torch.empty_like(w)
+        lptr = _dev_ptr(lam_src, "lam_src", (nrhs, s.n_leaves, s.pts_per_leaf))
+        bptr = None if lam_bdry is None else _dev_ptr(lam_bdry, "lam_bdry", (nrhs, s.n_root_bdry))
+        _check(lib().hps_solve_adjoint(self._h, wptr, lptr, bptr, nrhs, _stream_ptr(stream)))
+        return lam_src, lam_bdry
+
+    def stage_times(self):
+        names = (ctypes.c_char_p * 64)()
+        ms = (ctypes.c_double * 64)()
+        n = lib().hps_stage_times(self._h, names, ms, 64)
+        if n < 0:
+            _check(-n)
+        return [(names[i].decode(), ms[i]) for i in range(n)]
+
+    def download(self, which: int, level: int = 0, cap: int = 1 << 28) -> np.ndarray:
+        """Copy of an internal device buffer (see hps_debug_download)."""
+        out = np.empty(cap)
+        n = lib().hps_debug_download(self._h, which, level, out.ctypes.data, cap)
+        if n < 0:
+            _check(-n)
+        return out[:n].copy()
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().hps_op_bytes(self._h))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def debug_gemm(A, B, C, alpha=1.0, beta=0.0, trans_a=False, trans_b=False, stream=None):
+    """C = alpha op(A) op(B) + beta C with the library's MFMA GEMM (test hook).
+    Tensors are CUDA float64, column-major views (pass X.T.contiguous().T or
+    Fortran-ordered data via .t())."""
+    m, n = C.shape
+    k = A.shape[0] if trans_a else A.shape[1]
+    for X, nm in ((A, "A"), (B, "B"), (C, "C")):
+        if X.stride(0) != 1:
+            raise ValueError(f"{nm} must be column-major (stride(0) == 1)")
+    _check(lib().hps_debug_gemm(m, n, k, alpha, ctypes.c_void_p(A.data_ptr()), A.stride(1), int(trans_a),
+                                ctypes.c_void_p(B.data_ptr()), B.stride(1), int(trans_b), beta,
+                                ctypes.c_void_p(C.data_ptr()), C.stride(1), _stream_ptr(stream)))
+    return C
+
+
+def build(t: Tree, p: int, coeffs, flags: int = 0, stream=None) -> Operator:
+    return Operator(t, p, coeffs, flags, stream)

@@ -1,0 +1,910 @@
+// C ABI of the HPS solver: host orchestration of the build and solve stages.
+//
+// Build (Algorithm "Local solve stage" + Algorithm "Merge stage"):
+//   leaves   fused factor kernel -> LU(L_ii), Y_int;  T = Q_e P + Q_i Y_int (GEMM)
+//   level l  (l = L-1 .. 0, parents on tree level l)
+//            D   = sum of child DtN blocks on shared interfaces (gather)
+//            Z   = D^{-1}                      (register GJ or blocked GJ)
+//            S   = -Z C                        (grouped GEMM, C's zero blocks skipped)
+//            Bnz = nonzero blocks of B         (gather; kept for the solve)
+//            T   = A + B S                     (gather of A + grouped GEMM; not at the root)
+// Solve (source split of Section 3 + Algorithm "Downward pass"):
+//   up       v = L_ii^{-1} f, h = Q_i v; per level gt = -Z h_int, h = h_ext + B gt
+//   down     per level g_int = S g + gt, children g cut from [g; g_int]
+//   leaves   u = [P g; Y_int g + v]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hps.h"
+#include "common.hpp"
+#include "precompute.hpp"
+
+namespace hps {
+
+// launchers (kernels in the .hip files)
+long long gemm_prepare(std::vector<GemmGroup>& groups);
+int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
+                int n_override);
+int leaf2d_launch(int p, const double* coeffs, const double* D1, const double* D2, const double* Mt, double* LU,
+                  int* perm, int* pos, double* Y, int* flag, long long nl, hipStream_t st);
+int gj_small_max();
+int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batch, hipStream_t st);
+int gj_panel_width(int m);
+int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
+                    long long batch, hipStream_t st);
+int gj_init_launch(int* pos, long long n, hipStream_t st);
+int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
+                         hipStream_t st);
+int block_copy_launch(const BlockOp* dev_ops, int nops, int max_cols, int ncols_rt, double* dst, long long dst_stride,
+                      const double* src0, long long s0_stride, const double* src1, long long s1_stride,
+                      long long batch, int max_rows, hipStream_t st);
+int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
+                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st);
+int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
+                    int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st);
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define HPS_TRY(expr)            \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != HPS_OK) return _rc; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory: a size-keyed cache of freed blocks, so repeated builds of the
+// same shape reuse their allocations instead of calling hipMalloc again.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void*> g_pool_free;
+
+size_t round_size(size_t b) { return (b + 4095) & ~(size_t)4095; }
+
+void* dalloc(size_t bytes) {
+  bytes = round_size(bytes ? bytes : 1);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool_free.find(bytes);
+    if (it != g_pool_free.end()) {
+      void* p = it->second;
+      g_pool_free.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // release cached blocks and retry once
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& kv : g_pool_free) (void)hipFree(kv.second);
+    g_pool_free.clear();
+    (void)hipGetLastError();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  return p;
+}
+
+void dfree(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_free.emplace(round_size(bytes ? bytes : 1), p);
+}
+
+// device copies of the precomputed leaf operators, per (d, p, leaf half-width)
+struct DevConsts {
+  double *D1 = nullptr, *D2 = nullptr, *Mt = nullptr, *QeP = nullptr, *Qi = nullptr, *P = nullptr;
+  int *Ii = nullptr, *Ie = nullptr;
+};
+std::mutex g_cst_mu;
+std::map<std::tuple<int, int, double>, DevConsts> g_cst;
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& host) {
+  *dst = (T*)dalloc(host.size() * sizeof(T));
+  if (!*dst) { set_error("device allocation failed (constants)"); return HPS_ENOMEM; }
+  HPS_HIP_TRY(hipMemcpy(*dst, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HPS_OK;
+}
+
+int get_consts(int d, int p, double r, DevConsts** out) {
+  std::lock_guard<std::mutex> lk(g_cst_mu);
+  auto key = std::make_tuple(d, p, r);
+  auto it = g_cst.find(key);
+  if (it != g_cst.end()) { *out = &it->second; return HPS_OK; }
+  const LeafOps& o = leaf_ops(d, p);
+  DevConsts c;
+  const int n_i = o.n_i, n_e = o.n_e, n_b = o.n_b, np = o.npts;
+  // 1D derivative matrices on the leaf (row-major)
+  std::vector<double> D1((size_t)p * p), D2((size_t)p * p, 0.0);
+  for (int i = 0; i < p * p; ++i) D1[i] = o.D[i] / r;
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += D1[(size_t)i * p + k] * D1[(size_t)k * p + j];
+      D2[(size_t)i * p + j] = s;
+    }
+  // Q on the leaf, split into interior / exterior columns (column-major)
+  std::vector<double> Qi((size_t)n_b * n_i), Qe((size_t)n_b * n_e);
+  for (int b = 0; b < n_b; ++b) {
+    for (int k = 0; k < n_i; ++k) Qi[b + (size_t)k * n_b] = o.Qref[(size_t)b * np + o.Ii[k]] / r;
+    for (int k = 0; k < n_e; ++k) Qe[b + (size_t)k * n_b] = o.Qref[(size_t)b * np + o.Ie[k]] / r;
+  }
+  std::vector<double> QeP((size_t)n_b * n_b, 0.0), Pc((size_t)n_e * n_b);
+  for (int e = 0; e < n_e; ++e)
+    for (int b = 0; b < n_b; ++b) Pc[e + (size_t)b * n_e] = o.P[(size_t)e * n_b + b];
+  for (int a = 0; a < n_b; ++a)
+    for (int b = 0; b < n_b; ++b) {
+      double s = 0.0;
+      for (int e = 0; e < n_e; ++e) s += Qe[a + (size_t)e * n_b] * Pc[e + (size_t)b * n_e];
+      QeP[a + (size_t)b * n_b] = s;
+    }
+  // M_t = D_t(I_i, I_e) P for every term, column-major n_i x n_b
+  const int nt = n_terms(d);
+  std::vector<double> Mt((size_t)nt * n_i * n_b, 0.0), blk;
+  for (int t = 0; t < nt; ++t) {
+    term_block(o, t, r, o.Ii, o.Ie, blk);  // n_i x n_e row-major
+    for (int i = 0; i < n_i; ++i)
+      for (int b = 0; b < n_b; ++b) {
+        double s = 0.0;
+        for (int e = 0; e < n_e; ++e) s += blk[(size_t)i * n_e + e] * Pc[e + (size_t)b * n_e];
+        Mt[(size_t)t * n_i * n_b + i + (size_t)b * n_i] = s;
+      }
+  }
+  HPS_TRY(upload(&c.D1, D1));
+  HPS_TRY(upload(&c.D2, D2));
+  HPS_TRY(upload(&c.Mt, Mt));
+  HPS_TRY(upload(&c.QeP, QeP));
+  HPS_TRY(upload(&c.Qi, Qi));
+  HPS_TRY(upload(&c.P, Pc));
+  HPS_TRY(upload(&c.Ii, o.Ii));
+  HPS_TRY(upload(&c.Ie, o.Ie));
+  auto res = g_cst.emplace(key, c);
+  *out = &res.first->second;
+  return HPS_OK;
+}
+
+struct GemmCall {
+  int first = 0, count = 0;
+  long long nblocks = 0;
+  bool ta = false, tb = false;
+};
+struct CopyCall {
+  int first = 0, count = 0;
+  int max_rows = 0, max_cols = 0;  // max_cols 0 = runtime column count
+};
+
+struct LevelPlan {
+  int lev = 0;
+  long long nm = 0;
+  int n = 0, m = 0, nbc = 0, nbp = 0, dn = 0;
+  double *Z = nullptr, *S = nullptr, *Bnz = nullptr, *Tp = nullptr, *Dbuf = nullptr;
+  int *gj_pos = nullptr, *gj_piv = nullptr;
+  double *gj_W = nullptr, *gj_snap = nullptr;
+  int gj_nb = 0;
+  bool small = true;
+  CopyCall copyD, fillT, copyB;
+  std::vector<GemmCall> gj_upd;
+  GemmCall gemmS, gemmT;
+  // solve
+  double *hint = nullptr, *gt = nullptr, *gint = nullptr;
+  CopyCall copyHint, copyGchild;
+  GemmCall gemmGt, gemmHp, gemmDown;
+};
+
+struct Alloc {
+  void* p;
+  size_t bytes;
+};
+
+struct TimedStage {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+}  // namespace hps
+
+struct hps_op {
+  hps_tree_t tree{};
+  int p = 0, d = 0, flags = 0, nd = 0;
+  long long nl = 0;
+  int npts = 0, ni = 0, ne = 0, nb = 0;
+  double r = 0.0;
+  hps::DevConsts* cst = nullptr;
+  hipStream_t stream = nullptr;
+  double *LU = nullptr, *Y = nullptr, *Tleaf = nullptr;
+  int *perm = nullptr, *pos = nullptr, *flag = nullptr;
+  std::vector<hps::LevelPlan> levels;  // index = tree level of the parents
+  std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
+  std::vector<int> nbl;                // boundary size per tree level
+  double* v = nullptr;                 // [nl][NR][ni]
+  int NR = 16;
+  std::vector<hps::GemmGroup> hgroups;
+  hps::GemmGroup* dgroups = nullptr;
+  std::vector<hps::BlockOp> hops;
+  hps::BlockOp* dops = nullptr;
+  hps::GemmCall gemmTleaf, gemmHleaf;
+  hps::CopyCall copyRoot;
+  std::vector<hps::Alloc> allocs;
+  size_t resident = 0;
+  std::vector<hps::TimedStage> stages;
+};
+
+namespace hps {
+namespace {
+
+void* op_alloc(hps_op* op, size_t bytes, bool resident = true) {
+  void* p = dalloc(bytes);
+  if (p) {
+    op->allocs.push_back({p, bytes});
+    if (resident) op->resident += round_size(bytes);
+  }
+  return p;
+}
+
+int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta = false, bool tb = false) {
+  call->first = (int)op->hgroups.size();
+  call->count = (int)groups.size();
+  call->nblocks = gemm_prepare(groups);
+  call->ta = ta;
+  call->tb = tb;
+  op->hgroups.insert(op->hgroups.end(), groups.begin(), groups.end());
+  return HPS_OK;
+}
+
+void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
+  call->first = (int)op->hops.size();
+  call->count = (int)ops.size();
+  call->max_rows = 0;
+  call->max_cols = 0;
+  bool runtime_cols = false;
+  for (auto& o : ops) {
+    call->max_rows = std::max(call->max_rows, o.rows);
+    if (o.cols <= 0) runtime_cols = true;
+    call->max_cols = std::max(call->max_cols, o.cols);
+  }
+  if (runtime_cols) call->max_cols = 0;
+  op->hops.insert(op->hops.end(), ops.begin(), ops.end());
+}
+
+GemmGroup make_group(const double* A, long long sA, int lda, const double* B, long long sB, int ldb, double* C,
+                     long long sC, int ldc, int M, int N, int K, double alpha, double beta, long long batch,
+                     const double* C0 = nullptr, long long sC0 = 0, int ldc0 = 0) {
+  GemmGroup g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.B = B; g.C = C; g.C0 = C0;
+  g.sA = sA; g.sB = sB; g.sC = sC; g.sC0 = sC0;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc; g.ldc0 = ldc0 ? ldc0 : ldc;
+  g.M = M; g.N = N; g.K = K; g.nseg = 1;
+  g.alpha = alpha; g.beta = beta;
+  g.batch = (int)batch;
+  return g;
+}
+
+BlockOp make_op(long long dst_off, int dst_ld, int rows, int cols) {
+  BlockOp o;
+  std::memset(&o, 0, sizeof(o));
+  o.dst_off = dst_off;
+  o.dst_ld = dst_ld;
+  o.rows = rows;
+  o.cols = cols;
+  return o;
+}
+
+void op_src(BlockOp& o, int buf, long long off, int ld) {
+  o.src_buf[o.nsrc] = buf;
+  o.src_off[o.nsrc] = off;
+  o.src_ld[o.nsrc] = ld;
+  o.nsrc++;
+}
+
+int run_gemm(hps_op* op, const GemmCall& c, hipStream_t st, int n_override = 0) {
+  return gemm_launch(op->dgroups + c.first, c.count, c.nblocks, c.ta, c.tb, st, n_override);
+}
+
+int run_copy(hps_op* op, const CopyCall& c, int ncols_rt, double* dst, long long dst_stride, const double* s0,
+             long long s0_stride, const double* s1, long long s1_stride, long long batch, hipStream_t st) {
+  return block_copy_launch(op->dops + c.first, c.count, c.max_cols, ncols_rt, dst, dst_stride, s0, s0_stride, s1,
+                           s1_stride, batch, c.max_rows, st);
+}
+
+void stage_begin(hps_op* op, const char* name, hipStream_t st) {
+  if (!(op->flags & HPS_FLAG_TIMING)) return;
+  TimedStage t;
+  t.name = name;
+  hipEventCreate(&t.a);
+  hipEventCreate(&t.b);
+  hipEventRecord(t.a, st);
+  op->stages.push_back(t);
+}
+void stage_end(hps_op* op, hipStream_t st) {
+  if (!(op->flags & HPS_FLAG_TIMING) || op->stages.empty()) return;
+  hipEventRecord(op->stages.back().b, st);
+}
+void clear_stages(hps_op* op) {
+  for (auto& s : op->stages) {
+    hipEventDestroy(s.a);
+    hipEventDestroy(s.b);
+  }
+  op->stages.clear();
+}
+
+// ---------------------------------------------------------------------------
+// plan: allocations + every descriptor table
+// ---------------------------------------------------------------------------
+int plan_op(hps_op* op) {
+  const int d = op->d, L = op->tree.depth, nd = op->nd;
+  const MergeGeom& G = merge_geom(d);
+  const int ni = op->ni, nb = op->nb, NR = op->NR;
+  const long long nl = op->nl;
+  // leaf storage
+  op->LU = (double*)op_alloc(op, sizeof(double) * nl * ni * ni);
+  op->Y = (double*)op_alloc(op, sizeof(double) * nl * ni * nb);
+  op->perm = (int*)op_alloc(op, sizeof(int) * nl * ni);
+  op->pos = (int*)op_alloc(op, sizeof(int) * nl * ni);
+  op->Tleaf = (double*)op_alloc(op, sizeof(double) * nl * nb * nb, false);
+  op->flag = (int*)op_alloc(op, sizeof(int) * 4, false);
+  if (!op->LU || !op->Y || !op->perm || !op->pos || !op->Tleaf || !op->flag) {
+    set_error("device allocation failed (leaf operators)");
+    return HPS_ENOMEM;
+  }
+  // solve buffers per tree level
+  op->g.assign(L + 1, nullptr);
+  op->h.assign(L + 1, nullptr);
+  op->nbl.assign(L + 1, 0);
+  for (int l = 0; l <= L; ++l) {
+    const long long nodes = 1LL << (d * l);
+    const long long side = d == 2 ? (long long)(op->p - 2) << (L - l) : (long long)(op->p - 2) * (op->p - 2) << (2 * (L - l));
+    op->nbl[l] = (int)(2 * d * side);
+    op->g[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
+    op->h[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
+    if (!op->g[l] || !op->h[l]) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+  }
+  op->v = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
+  if (!op->v) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+
+  // leaf T = Q_e P + Q_i Y_int
+  add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->Y, (long long)ni * nb, ni, op->Tleaf, (long long)nb * nb, nb, nb,
+                           nb, ni, 1.0, 1.0, nl, op->cst->QeP, 0, nb)},
+           &op->gemmTleaf);
+  // h = Q_i v (solve)
+  add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->v, (long long)NR * ni, ni, op->h[L], (long long)NR * nb, nb, nb, NR,
+                           ni, 1.0, 0.0, nl)},
+           &op->gemmHleaf);
+  // root data: bdry -> g[0]
+  {
+    BlockOp o = make_op(0, op->nbl[0], op->nbl[0], 0);
+    op_src(o, 0, 0, op->nbl[0]);
+    add_copy(op, {o}, &op->copyRoot);
+  }
+
+  op->levels.assign(L, LevelPlan());
+  for (int lev = L - 1; lev >= 0; --lev) {
+    LevelPlan& P = op->levels[lev];
+    P.lev = lev;
+    P.nm = 1LL << (d * lev);
+    P.nbc = op->nbl[lev + 1];
+    P.nbp = op->nbl[lev];
+    P.n = P.nbc / (2 * d);
+    P.m = G.nint * P.n;
+    P.dn = d * P.n;
+    const int n = P.n, m = P.m, nbc = P.nbc, nbp = P.nbp, dn = P.dn;
+    const long long nm = P.nm;
+    const long long childT = (long long)nbc * nbc;  // per child
+    const double* Tchild = lev == L - 1 ? op->Tleaf : op->levels[lev + 1].Tp;
+    P.Z = (double*)op_alloc(op, sizeof(double) * nm * m * m);
+    P.S = (double*)op_alloc(op, sizeof(double) * nm * m * nbp);
+    P.Bnz = (double*)op_alloc(op, sizeof(double) * nm * nd * dn * dn);
+    P.Dbuf = (double*)op_alloc(op, sizeof(double) * nm * m * m, false);
+    const bool formT = lev > 0 || (op->flags & HPS_FLAG_ROOT_T);
+    if (formT) P.Tp = (double*)op_alloc(op, sizeof(double) * nm * nbp * nbp, lev == 0);
+    P.hint = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
+    P.gt = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
+    P.gint = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
+    if (!P.Z || !P.S || !P.Bnz || !P.Dbuf || (formT && !P.Tp) || !P.hint || !P.gt || !P.gint) {
+      set_error("device allocation failed (merge level)");
+      return HPS_ENOMEM;
+    }
+    P.small = m <= gj_small_max();
+    if (!P.small) {
+      P.gj_nb = gj_panel_width(m);
+      if (P.gj_nb == 0) {
+        set_error("merge matrix D of size " + std::to_string(m) + " exceeds the blocked Gauss-Jordan limit");
+        return HPS_EUNSUPPORTED;
+      }
+      P.gj_pos = (int*)op_alloc(op, sizeof(int) * nm * m, false);
+      P.gj_piv = (int*)op_alloc(op, sizeof(int) * nm * m, false);
+      P.gj_W = (double*)op_alloc(op, sizeof(double) * nm * m * P.gj_nb, false);
+      P.gj_snap = (double*)op_alloc(op, sizeof(double) * nm * m * P.gj_nb, false);
+      if (!P.gj_pos || !P.gj_piv || !P.gj_W || !P.gj_snap) {
+        set_error("device allocation failed (Gauss-Jordan workspace)");
+        return HPS_ENOMEM;
+      }
+      for (int j0 = 0; j0 < m; j0 += P.gj_nb) {
+        const int w = std::min(P.gj_nb, m - j0);
+        std::vector<GemmGroup> gs;
+        if (j0 > 0)
+          gs.push_back(make_group(P.gj_W, (long long)m * P.gj_nb, m, P.gj_snap, (long long)m * P.gj_nb, P.gj_nb, P.Dbuf,
+                                  (long long)m * m, m, m, j0, w, 1.0, 1.0, nm, P.Dbuf, (long long)m * m, m));
+        if (j0 + w < m)
+          gs.push_back(make_group(P.gj_W, (long long)m * P.gj_nb, m, P.gj_snap + (long long)(j0 + w) * P.gj_nb,
+                                  (long long)m * P.gj_nb, P.gj_nb, P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m,
+                                  m, m - j0 - w, w, 1.0, 1.0, nm, P.Dbuf + (long long)(j0 + w) * m, (long long)m * m,
+                                  m));
+        GemmCall c;
+        add_gemm(op, gs, &c);
+        P.gj_upd.push_back(c);
+      }
+    }
+    // --- D = sum over children touching interfaces i and j of T_c(face_i, face_j)
+    {
+      std::vector<BlockOp> ops;
+      for (int i = 0; i < G.nint; ++i)
+        for (int j = 0; j < G.nint; ++j) {
+          BlockOp o = make_op((long long)i * n + (long long)j * n * m, m, n, n);
+          for (int c = 0; c < nd; ++c) {
+            const int fi = G.face_on_iface[c][i], fj = G.face_on_iface[c][j];
+            if (fi < 0 || fj < 0) continue;
+            op_src(o, 0, c * childT + (long long)fi * n + (long long)fj * n * nbc, nbc);
+          }
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.copyD);
+    }
+    // --- S = -Z C, one group per parent boundary group (child c, face F)
+    {
+      std::vector<GemmGroup> gs;
+      const int ngrp = 2 * d * G.sub_per_face;
+      for (int gi = 0; gi < ngrp; ++gi) {
+        const int c = G.group_child[gi], F = G.group_face[gi];
+        GemmGroup g = make_group(P.Z, (long long)m * m, m, Tchild, nd * childT, nbc, P.S + (long long)gi * n * m,
+                                 (long long)m * nbp, m, m, n, n, -1.0, 0.0, nm);
+        g.nseg = d;
+        for (int k = 0; k < d; ++k) {
+          const int i = G.int_list[c][k];
+          g.aseg[k] = (long long)i * n * m;
+          g.bseg[k] = c * childT + (long long)G.face_on_iface[c][i] * n + (long long)F * n * nbc;
+        }
+        gs.push_back(g);
+      }
+      add_gemm(op, gs, &P.gemmS);
+    }
+    // --- Bnz[c] = T_c(exterior faces, interface faces)
+    {
+      std::vector<BlockOp> ops;
+      for (int c = 0; c < nd; ++c)
+        for (int e = 0; e < d; ++e)
+          for (int k = 0; k < d; ++k) {
+            BlockOp o = make_op((long long)c * dn * dn + (long long)e * n + (long long)k * n * dn, dn, n, n);
+            const int Fe = G.ext_face[c][e], Fk = G.face_on_iface[c][G.int_list[c][k]];
+            op_src(o, 0, c * childT + (long long)Fe * n + (long long)Fk * n * nbc, nbc);
+            ops.push_back(o);
+          }
+      add_copy(op, ops, &P.copyB);
+    }
+    // --- parent T = A + B S
+    if (formT) {
+      const int ngrp = 2 * d * G.sub_per_face;
+      std::vector<BlockOp> ops;
+      for (int gr = 0; gr < ngrp; ++gr)
+        for (int gc = 0; gc < ngrp; ++gc) {
+          BlockOp o = make_op((long long)gr * n + (long long)gc * n * nbp, nbp, n, n);
+          const int c = G.group_child[gr];
+          if (G.group_child[gc] == c)
+            op_src(o, 0, c * childT + (long long)G.group_face[gr] * n + (long long)G.group_face[gc] * n * nbc, nbc);
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.fillT);
+      std::vector<GemmGroup> gs;
+      for (int gr = 0; gr < ngrp; ++gr) {
+        const int c = G.group_child[gr], F = G.group_face[gr];
+        GemmGroup g = make_group(Tchild, nd * childT, nbc, P.S, (long long)m * nbp, m, P.Tp + (long long)gr * n,
+                                 (long long)nbp * nbp, nbp, n, nbp, n, 1.0, 1.0, nm, P.Tp + (long long)gr * n,
+                                 (long long)nbp * nbp, nbp);
+        g.nseg = d;
+        for (int k = 0; k < d; ++k) {
+          const int i = G.int_list[c][k];
+          g.aseg[k] = c * childT + (long long)F * n + (long long)G.face_on_iface[c][i] * n * nbc;
+          g.bseg[k] = (long long)i * n;
+        }
+        gs.push_back(g);
+      }
+      add_gemm(op, gs, &P.gemmT);
+    }
+    // --- solve: h_int(i) = h_c1(face) + h_c2(face)
+    const double* hchild = op->h[lev + 1];
+    const long long hstride_c = (long long)NR * nbc;
+    {
+      std::vector<BlockOp> ops;
+      for (int i = 0; i < G.nint; ++i) {
+        BlockOp o = make_op((long long)i * n, m, n, 0);
+        op_src(o, 0, G.iface[i][0] * hstride_c + (long long)G.iface[i][1] * n, nbc);
+        op_src(o, 0, G.iface[i][2] * hstride_c + (long long)G.iface[i][3] * n, nbc);
+        ops.push_back(o);
+      }
+      add_copy(op, ops, &P.copyHint);
+    }
+    // gt = -Z h_int
+    add_gemm(op, {make_group(P.Z, (long long)m * m, m, P.hint, (long long)NR * m, m, P.gt, (long long)NR * m, m, m,
+                             NR, m, -1.0, 0.0, nm)},
+             &P.gemmGt);
+    // h_parent(c, F) = h_c(F) + Bnz_c(F, :) gt(interfaces of c)
+    if (lev > 0) {
+      std::vector<GemmGroup> gs;
+      const int ngrp = 2 * d * G.sub_per_face;
+      for (int gi = 0; gi < ngrp; ++gi) {
+        const int c = G.group_child[gi], F = G.group_face[gi];
+        int e = 0;
+        while (G.ext_face[c][e] != F) ++e;
+        GemmGroup g = make_group(P.Bnz, (long long)nd * dn * dn, dn, P.gt, (long long)NR * m, m,
+                                 op->h[lev] + (long long)gi * n, (long long)NR * nbp, nbp, n, NR, n, 1.0, 1.0, nm,
+                                 hchild + c * hstride_c + (long long)F * n, nd * hstride_c, nbc);
+        g.nseg = d;
+        for (int k = 0; k < d; ++k) {
+          g.aseg[k] = (long long)c * dn * dn + (long long)e * n + (long long)k * n * dn;
+          g.bseg[k] = (long long)G.int_list[c][k] * n;
+        }
+        gs.push_back(g);
+      }
+      add_gemm(op, gs, &P.gemmHp);
+    }
+    // down: g_int = S g + gt
+    add_gemm(op, {make_group(P.S, (long long)m * nbp, m, op->g[lev], (long long)NR * nbp, nbp, P.gint,
+                             (long long)NR * m, m, m, NR, nbp, 1.0, 1.0, nm, P.gt, (long long)NR * m, m)},
+             &P.gemmDown);
+    // children g: exterior faces from the parent's g, interface faces from g_int
+    {
+      std::vector<BlockOp> ops;
+      for (int c = 0; c < nd; ++c)
+        for (int f = 0; f < 2 * d; ++f) {
+          BlockOp o = make_op(c * hstride_c + (long long)f * n, nbc, n, 0);
+          if (G.group_of[c][f] >= 0) {
+            op_src(o, 0, (long long)G.group_of[c][f] * n, nbp);
+          } else {
+            int i = 0;
+            while (G.face_on_iface[c][i] != f) ++i;
+            op_src(o, 1, (long long)i * n, m);
+          }
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.copyGchild);
+    }
+  }
+  // upload descriptor tables
+  op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
+  op->dops = (BlockOp*)op_alloc(op, sizeof(BlockOp) * std::max<size_t>(1, op->hops.size()), false);
+  if (!op->dgroups || !op->dops) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
+  HPS_HIP_TRY(hipMemcpy(op->dgroups, op->hgroups.data(), sizeof(GemmGroup) * op->hgroups.size(), hipMemcpyHostToDevice));
+  HPS_HIP_TRY(hipMemcpy(op->dops, op->hops.data(), sizeof(BlockOp) * op->hops.size(), hipMemcpyHostToDevice));
+  return HPS_OK;
+}
+
+int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd;
+  HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
+  stage_begin(op, "leaf_factor", st);
+  if (op->d == 2) {
+    HPS_TRY(leaf2d_launch(op->p, coeffs, op->cst->D1, op->cst->D2, op->cst->Mt, op->LU, op->perm, op->pos, op->Y,
+                          op->flag, op->nl, st));
+  } else {
+    set_error("3D leaf stage not available in this build");
+    return HPS_EUNSUPPORTED;
+  }
+  stage_end(op, st);
+  stage_begin(op, "leaf_T", st);
+  HPS_TRY(run_gemm(op, op->gemmTleaf, st));
+  stage_end(op, st);
+  static const char* names[] = {"merge_l0", "merge_l1", "merge_l2", "merge_l3", "merge_l4", "merge_l5",
+                                "merge_l6", "merge_l7", "merge_l8", "merge_l9", "merge_l10", "merge_l11"};
+  for (int lev = L - 1; lev >= 0; --lev) {
+    LevelPlan& P = op->levels[lev];
+    const double* Tchild = lev == L - 1 ? op->Tleaf : op->levels[lev + 1].Tp;
+    const long long childstride = (long long)nd * P.nbc * P.nbc;
+    stage_begin(op, names[lev < 12 ? lev : 11], st);
+    HPS_TRY(run_copy(op, P.copyD, 0, P.Dbuf, (long long)P.m * P.m, Tchild, childstride, nullptr, 0, P.nm, st));
+    if (P.small) {
+      HPS_TRY(gj_small_launch(P.Dbuf, P.Z, P.m, op->flag, P.nm, st));
+    } else {
+      HPS_TRY(gj_init_launch(P.gj_pos, P.nm * P.m, st));
+      int step = 0;
+      for (int j0 = 0; j0 < P.m; j0 += P.gj_nb, ++step) {
+        const int w = std::min(P.gj_nb, P.m - j0);
+        HPS_TRY(gj_panel_launch(P.Dbuf, P.m, j0, w, P.gj_pos, P.gj_piv, P.gj_W, P.gj_snap, op->flag, P.nm, st));
+        HPS_TRY(run_gemm(op, P.gj_upd[step], st));
+      }
+      HPS_TRY(gj_unscramble_launch(P.Dbuf, P.Z, P.m, P.gj_pos, P.gj_piv, P.nm, st));
+    }
+    HPS_TRY(run_gemm(op, P.gemmS, st));
+    HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)nd * P.dn * P.dn, Tchild, childstride, nullptr, 0, P.nm, st));
+    if (P.Tp) {
+      HPS_TRY(run_copy(op, P.fillT, 0, P.Tp, (long long)P.nbp * P.nbp, Tchild, childstride, nullptr, 0, P.nm, st));
+      HPS_TRY(run_gemm(op, P.gemmT, st));
+    }
+    stage_end(op, st);
+  }
+  return HPS_OK;
+}
+
+int run_solve_chunk(hps_op* op, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd, NR = op->NR;
+  stage_begin(op, "solve", st);
+  // root data
+  HPS_TRY(run_copy(op, op->copyRoot, nrhs, op->g[0], 0, bdry, 0, nullptr, 0, 1, st));
+  if (src) {
+    HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, op->v, NR, st));
+    HPS_TRY(run_gemm(op, op->gemmHleaf, st, nrhs));
+    for (int lev = L - 1; lev >= 0; --lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_TRY(run_copy(op, P.copyHint, nrhs, P.hint, (long long)NR * P.m, op->h[lev + 1], (long long)nd * NR * P.nbc,
+                       nullptr, 0, P.nm, st));
+      HPS_TRY(run_gemm(op, P.gemmGt, st, nrhs));
+      if (lev > 0) HPS_TRY(run_gemm(op, P.gemmHp, st, nrhs));
+    }
+  } else {
+    for (int lev = 0; lev < L; ++lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_HIP_TRY(hipMemsetAsync(P.gt, 0, sizeof(double) * P.nm * NR * P.m, st));
+    }
+  }
+  for (int lev = 0; lev < L; ++lev) {
+    LevelPlan& P = op->levels[lev];
+    HPS_TRY(run_gemm(op, P.gemmDown, st, nrhs));
+    HPS_TRY(run_copy(op, P.copyGchild, nrhs, op->g[lev + 1], (long long)nd * NR * P.nbc, op->g[lev],
+                     (long long)NR * P.nbp, P.gint, (long long)NR * P.m, P.nm, st));
+  }
+  HPS_TRY(leaf_out_launch(op->Y, op->cst->P, op->g[L], src ? op->v : nullptr, op->cst->Ii, op->cst->Ie, op->ni,
+                          op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st));
+  stage_end(op, st);
+  return HPS_OK;
+}
+
+int check_tree(const hps_tree_t* t, int p) {
+  if (!t) { set_error("tree is NULL"); return HPS_EINVAL; }
+  if (t->dim != 2 && t->dim != 3) { set_error("dim must be 2 or 3"); return HPS_EINVAL; }
+  if (t->depth < 1 || (t->dim == 2 && t->depth > 12) || (t->dim == 3 && t->depth > 5)) {
+    set_error("depth out of range");
+    return HPS_EINVAL;
+  }
+  if (!(t->hi > t->lo) || !std::isfinite(t->lo) || !std::isfinite(t->hi)) {
+    set_error("domain must satisfy lo < hi");
+    return HPS_EINVAL;
+  }
+  if (p < 4 || p > 16) { set_error("p must be in [4, 16]"); return HPS_EINVAL; }
+  return HPS_OK;
+}
+
+}  // namespace
+}  // namespace hps
+
+using namespace hps;
+
+extern "C" {
+
+const char* hps_last_error(void) { return g_err.c_str(); }
+
+int hps_sizes(const hps_tree_t* tree, int p, hps_sizes_t* out) {
+  HPS_TRY(check_tree(tree, p));
+  if (!out) { set_error("out is NULL"); return HPS_EINVAL; }
+  const int d = tree->dim, q = p - 2;
+  out->n_leaves = 1LL << (d * tree->depth);
+  out->pts_per_leaf = d == 2 ? p * p : p * p * p;
+  out->n_terms = n_terms(d);
+  out->n_root_bdry = n_root_bdry(d, tree->depth, p);
+  out->n_interior = d == 2 ? q * q : q * q * q;
+  out->n_leaf_bdry = d == 2 ? 4 * q : 6 * q * q;
+  out->n_levels = tree->depth;
+  const long long nface = d == 2 ? (long long)q << (tree->depth - 1) : (long long)q * q << (2 * (tree->depth - 1));
+  out->root_D = (d == 2 ? 4 : 12) * nface;
+  return HPS_OK;
+}
+
+int hps_leaf_points(const hps_tree_t* tree, int p, double* xyz) {
+  HPS_TRY(check_tree(tree, p));
+  if (!xyz) { set_error("xyz is NULL"); return HPS_EINVAL; }
+  leaf_points(tree->dim, tree->depth, tree->lo, tree->hi, p, xyz);
+  return HPS_OK;
+}
+
+int hps_boundary_points(const hps_tree_t* tree, int p, double* xyz) {
+  HPS_TRY(check_tree(tree, p));
+  if (!xyz) { set_error("xyz is NULL"); return HPS_EINVAL; }
+  boundary_points(tree->dim, tree->depth, tree->lo, tree->hi, p, xyz);
+  return HPS_OK;
+}
+
+size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags) {
+  if (check_tree(tree, p) != HPS_OK) return 0;
+  const int d = tree->dim, L = tree->depth, q = p - 2;
+  const long long nl = 1LL << (d * L);
+  const long long ni = d == 2 ? q * q : q * q * q, nb = d == 2 ? 4 * q : 6 * q * q;
+  size_t bytes = (size_t)nl * (ni * ni + ni * nb) * 8 + (size_t)nl * ni * 8;  // LU, Y, perm+pos
+  long long n = d == 2 ? q : q * q;
+  for (int lev = L - 1; lev >= 0; --lev) {
+    const long long nm = 1LL << (d * lev);
+    const long long m = (d == 2 ? 4 : 12) * n, nbp = 2 * d * n * (1 << (d - 1)), dn = d * n;
+    bytes += (size_t)nm * (m * m + m * nbp + (1 << d) * dn * dn) * 8;
+    if (lev == 0 && (flags & HPS_FLAG_ROOT_T)) bytes += (size_t)nbp * nbp * 8;
+    n *= (1 << (d - 1));
+  }
+  return bytes;
+}
+
+size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident : 0; }
+
+int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, void* stream, hps_op_t** out) {
+  if (out) *out = nullptr;
+  HPS_TRY(check_tree(tree, p));
+  if (!coeffs || !out) { set_error("coeffs and out must not be NULL"); return HPS_EINVAL; }
+  hps_op* op = new hps_op();
+  op->tree = *tree;
+  op->p = p;
+  op->d = tree->dim;
+  op->nd = 1 << op->d;
+  op->flags = flags;
+  op->nl = 1LL << (op->d * tree->depth);
+  const LeafOps& o = leaf_ops(op->d, p);
+  op->npts = o.npts;
+  op->ni = o.n_i;
+  op->ne = o.n_e;
+  op->nb = o.n_b;
+  op->r = (tree->hi - tree->lo) / 2.0 / (double)(1LL << tree->depth);
+  op->stream = (hipStream_t)stream;
+  int rc = get_consts(op->d, p, op->r, &op->cst);
+  if (rc == HPS_OK) rc = plan_op(op);
+  if (rc == HPS_OK) rc = run_build(op, coeffs, op->stream);
+  if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) {
+    int hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+    if (e != hipSuccess) {
+      set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
+      rc = HPS_EDEVICE;
+    } else if (hflag[0]) {
+      set_error(std::string("zero or non-finite pivot in ") +
+                ((hflag[0] & 1) ? "a leaf factorization (L_ii)" : "a merge matrix D"));
+      rc = HPS_ESINGULAR;
+    }
+  }
+  if (rc != HPS_OK) {
+    if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(op->stream);
+    hps_free(op);
+    return rc;
+  }
+  *out = op;
+  return HPS_OK;
+}
+
+int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, int precision, void* stream) {
+  if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
+  if (precision != HPS_FP64) { set_error("only HPS_FP64 solves are available in this build"); return HPS_EUNSUPPORTED; }
+  hipError_t pending = hipGetLastError();
+  if (pending != hipSuccess) {
+    set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
+    return HPS_EDEVICE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  clear_stages(op);
+  const long long nbr = op->nbl[0], field = op->nl * op->npts;
+  for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
+    const int k = std::min(op->NR, nrhs - r0);
+    HPS_TRY(run_solve_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+  }
+  return HPS_OK;
+}
+
+int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, void* stream) {
+  (void)op; (void)w; (void)lam_src; (void)lam_bdry; (void)nrhs; (void)stream;
+  set_error("adjoint solve not available in this build");
+  return HPS_EUNSUPPORTED;
+}
+
+int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap) {
+  if (!op) { set_error("op is NULL"); return -HPS_EINVAL; }
+  int n = 0;
+  for (auto& s : op->stages) {
+    if (n >= cap) break;
+    if (hipEventSynchronize(s.b) != hipSuccess) { set_error("event sync failed"); return -HPS_EDEVICE; }
+    float t = 0.f;
+    hipEventElapsedTime(&t, s.a, s.b);
+    if (names) names[n] = s.name;
+    if (ms) ms[n] = t;
+    ++n;
+  }
+  return n;
+}
+
+void hps_free(hps_op_t* op) {
+  if (!op) return;
+  (void)hipStreamSynchronize(op->stream);
+  clear_stages(op);
+  for (auto& a : op->allocs) dfree(a.p, a.bytes);
+  delete op;
+}
+
+int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, int trans_a, const double* b, int ldb,
+                   int trans_b, double beta, double* c, int ldc, void* stream) {
+  if (m < 0 || n < 0 || k < 0 || !a || !b || !c) { set_error("bad GEMM arguments"); return HPS_EINVAL; }
+  std::vector<GemmGroup> gs = {make_group(a, 0, lda, b, 0, ldb, c, 0, ldc, m, n, k, alpha, beta, 1, c, 0, ldc)};
+  const long long nblocks = gemm_prepare(gs);
+  GemmGroup* dg = nullptr;
+  HPS_HIP_TRY(hipMalloc(&dg, sizeof(GemmGroup)));
+  hipStream_t st = (hipStream_t)stream;
+  HPS_HIP_TRY(hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroup), hipMemcpyHostToDevice, st));
+  int rc = gemm_launch(dg, 1, nblocks, trans_a != 0, trans_b != 0, st, 0);
+  HPS_HIP_TRY(hipStreamSynchronize(st));
+  HPS_HIP_TRY(hipFree(dg));
+  return rc;
+}
+
+long long hps_debug_download(const hps_op_t* op, int which, int level, double* out, long long cap) {
+  if (!op || !out) { set_error("op and out must not be NULL"); return -HPS_EINVAL; }
+  if (hipStreamSynchronize(op->stream) != hipSuccess) { set_error("stream sync failed"); return -HPS_EDEVICE; }
+  const void* src = nullptr;
+  long long n = 0;
+  bool ints = false;
+  const int L = op->tree.depth;
+  if (which >= 4 && (level < 0 || level >= L)) { set_error("level out of range"); return -HPS_EINVAL; }
+  switch (which) {
+    case 0: src = op->LU; n = op->nl * op->ni * op->ni; break;
+    case 1: src = op->perm; n = op->nl * op->ni; ints = true; break;
+    case 2: src = op->Y; n = op->nl * op->ni * op->nb; break;
+    case 3: src = op->Tleaf; n = op->nl * op->nb * op->nb; break;
+    case 4: src = op->levels[level].Z; n = op->levels[level].nm * op->levels[level].m * op->levels[level].m; break;
+    case 5: src = op->levels[level].S; n = op->levels[level].nm * op->levels[level].m * op->levels[level].nbp; break;
+    case 6:
+      src = op->levels[level].Tp;
+      n = op->levels[level].nm * op->levels[level].nbp * op->levels[level].nbp;
+      break;
+    default: set_error("unknown buffer id"); return -HPS_EINVAL;
+  }
+  if (!src) { set_error("buffer not formed"); return -HPS_EINVAL; }
+  if (n > cap) { set_error("output capacity too small"); return -HPS_EINVAL; }
+  if (ints) {
+    std::vector<int> tmp(n);
+    if (hipMemcpy(tmp.data(), src, n * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return -HPS_EDEVICE;
+    for (long long i = 0; i < n; ++i) out[i] = tmp[i];
+  } else if (hipMemcpy(out, src, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("copy failed");
+    return -HPS_EDEVICE;
+  }
+  return n;
+}
+
+int hps_precompute_matrix(int dim, int p, int which, double* out, long long cap, int* rows, int* cols) {
+  if ((dim != 2 && dim != 3) || p < 4 || p > 16 || !out || !rows || !cols) {
+    set_error("bad arguments");
+    return HPS_EINVAL;
+  }
+  const LeafOps& o = leaf_ops(dim, p);
+  std::vector<double> v;
+  int r = 0, c = 0;
+  switch (which) {
+    case 0: v = o.cheb; r = 1; c = p; break;
+    case 1: v = o.gl; r = 1; c = o.q; break;
+    case 2: v = o.glw; r = 1; c = o.q; break;
+    case 3: v = o.D; r = p; c = p; break;
+    case 4: v = o.P; r = o.n_e; c = o.n_b; break;
+    case 5: v = o.Qref; r = o.n_b; c = o.npts; break;
+    case 6: v.assign(o.Ii.begin(), o.Ii.end()); r = 1; c = o.n_i; break;
+    case 7: v.assign(o.Ie.begin(), o.Ie.end()); r = 1; c = o.n_e; break;
+    default: set_error("unknown matrix id"); return HPS_EINVAL;
+  }
+  if ((long long)v.size() > cap) { set_error("output capacity too small"); return HPS_EINVAL; }
+  std::memcpy(out, v.data(), v.size() * sizeof(double));
+  *rows = r;
+  *cols = c;
+  return HPS_OK;
+}
+
+}  // extern "C"

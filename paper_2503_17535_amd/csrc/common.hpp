@@ -1,0 +1,78 @@
+// Shared definitions of the HPS HIP library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace hps {
+
+// ---------------------------------------------------------------------------
+// Grouped, strided-batched fp64 GEMM descriptor.
+//   C[b] = alpha * sum_{s < nseg} op(A)[b, s] op(B)[b, s] + beta * C0[b]
+// op(A)[b,s] is M x K starting at A + b*sA + aseg[s] (leading dim lda),
+// op(B)[b,s] is K x N starting at B + b*sB + bseg[s] (leading dim ldb),
+// all column-major.  beta == 0 never reads C0.
+// ---------------------------------------------------------------------------
+constexpr int kMaxSeg = 3;
+struct GemmGroup {
+  const double* A;
+  const double* B;
+  double* C;
+  const double* C0;
+  long long sA, sB, sC, sC0;
+  long long aseg[kMaxSeg], bseg[kMaxSeg];
+  int lda, ldb, ldc, ldc0;
+  int M, N, K, nseg;
+  double alpha, beta;
+  int batch;
+  // filled by the launcher
+  int tiles_m, tiles_n;
+  long long first_block;
+};
+
+// Same for fp32 operands with fp32 accumulation (mixed-precision solve).
+struct GemmGroupF32 {
+  const float* A;
+  const float* B;
+  float* C;
+  const float* C0;
+  long long sA, sB, sC, sC0;
+  long long aseg[kMaxSeg], bseg[kMaxSeg];
+  int lda, ldb, ldc, ldc0;
+  int M, N, K, nseg;
+  float alpha, beta;
+  int batch;
+  int tiles_m, tiles_n;
+  long long first_block;
+};
+
+// ---------------------------------------------------------------------------
+// Block copy/add: dst block (rows x cols, column-major, ld dst_ld) =
+//   sum of up to two source blocks (or zero).  Sources come from one of two
+//   base buffers (src_buf 0 / 1).  Offsets are relative to the batch item's
+//   base (base + b * stride).
+// ---------------------------------------------------------------------------
+struct BlockOp {
+  long long dst_off;
+  long long src_off[2];
+  int dst_ld;
+  int src_ld[2];
+  int src_buf[2];
+  int nsrc;
+  int rows, cols;
+};
+
+// error reporting (implemented in api.cpp)
+void set_error(const std::string& msg);
+
+}  // namespace hps
+
+#define HPS_HIP_TRY(expr)                                                          \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::hps::set_error(std::string(#expr " failed: ") + hipGetErrorString(_e));    \
+      return HPS_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)

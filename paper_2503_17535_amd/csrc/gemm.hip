@@ -1,0 +1,223 @@
+// Grouped, strided-batched GEMM on CDNA4 matrix cores.
+//
+// fp64: v_mfma_f64_16x16x4f64 (one 16x16x4 product per wavefront).
+// fp32: v_mfma_f32_16x16x4f32.
+// Workgroup tile 64 x 64 (4 wavefronts, each 32 x 32 = 2 x 2 MFMA blocks),
+// k-step 16 staged through LDS.  The MFMA is fed with (B-fragment, A-fragment)
+// so that its accumulator layout puts consecutive lanes on consecutive rows
+// of the column-major C: the epilogue stores 128-byte runs.  Accumulator
+// layout (measured on gfx950): lane l, element v holds D(l/16 + 4v, l%16).
+//
+// One launch covers a list of groups (GemmGroup); every (group, batch item,
+// tile) triple is one workgroup.  Block indices are remapped so that the
+// blocks the hardware dispatches to one XCD (block id mod 8) are consecutive
+// tiles of one product, which keeps their shared A/B panels in that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "../../include/hps.h"
+
+namespace hps {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, GEMM_THREADS = 256, NXCD = 8;
+
+template <typename G>
+__device__ __forceinline__ const G* find_group(const G* groups, int ngroups, long long lb) {
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {  // last group with first_block <= lb
+    int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].first_block <= lb) lo = mid; else hi = mid - 1;
+  }
+  return groups + lo;
+}
+
+__device__ __forceinline__ long long xcd_remap(long long b, long long nblocks) {
+  // hardware dispatch: block b -> XCD b % NXCD.  Give each XCD a contiguous
+  // range of logical blocks.
+  const long long q = nblocks / NXCD, r = nblocks % NXCD;
+  const long long x = b % NXCD, local = b / NXCD;
+  const long long start = x * q + (x < r ? x : r);
+  return start + local;
+}
+
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MfmaOp<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T, typename G, bool TA, bool TB>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __restrict__ groups,
+                                                                    int ngroups, long long nblocks, int n_override) {
+  typedef typename MfmaOp<T>::acc_t acc_t;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+
+  const long long lb = xcd_remap(blockIdx.x, nblocks);
+  const G* g = find_group(groups, ngroups, lb);
+  const long long rel = lb - g->first_block;
+  const int tiles = g->tiles_m * g->tiles_n;
+  const long long bat = rel / tiles;
+  const int tile = (int)(rel - bat * tiles);
+  const int tm = tile % g->tiles_m, tn = tile / g->tiles_m;
+  const int M = g->M, K = g->K;
+  const int N = (n_override > 0 && n_override < g->N) ? n_override : g->N;
+  const int i0 = tm * BM, j0 = tn * BN;
+  const int lda = g->lda, ldb = g->ldb;
+  const T* Abase = g->A + bat * g->sA;
+  const T* Bbase = g->B + bat * g->sB;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  for (int s = 0; s < g->nseg; ++s) {
+    const T* A = Abase + g->aseg[s];
+    const T* B = Bbase + g->bseg[s];
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      // ---- stage op(A) tile (BM x BK) as As[k][i]
+      if (!TA) {
+        const int i = tid & 63, kk = tid >> 6;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kk + 4 * r;
+          const int gi = i0 + i, gk = k0 + k;
+          As[k][i] = (gi < M && gk < K) ? A[gi + (long long)gk * lda] : T(0);
+        }
+      } else {
+        const int k = tid & 15, ii = tid >> 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = ii + 16 * r;
+          const int gi = i0 + i, gk = k0 + k;
+          As[k][i] = (gi < M && gk < K) ? A[gk + (long long)gi * lda] : T(0);
+        }
+      }
+      // ---- stage op(B) tile (BK x BN) as Bs[k][j]
+      if (!TB) {
+        const int k = tid & 15, jj = tid >> 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = jj + 16 * r;
+          const int gj = j0 + j, gk = k0 + k;
+          Bs[k][j] = (gj < N && gk < K) ? B[gk + (long long)gj * ldb] : T(0);
+        }
+      } else {
+        const int j = tid & 63, kk = tid >> 6;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = kk + 4 * r;
+          const int gj = j0 + j, gk = k0 + k;
+          Bs[k][j] = (gj < N && gk < K) ? B[gj + (long long)gk * ldb] : T(0);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        T af[2], bf[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[a] = As[k][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[b] = Bs[k][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = MfmaOp<T>::run(bf[b], af[a], acc[a][b]);
+      }
+      __syncthreads();
+    }
+  }
+  // ---- epilogue: acc[a][b][v] = C(row = .. + lane%16, col = .. + lane/16 + 4*v)
+  T* C = g->C + bat * g->sC;
+  const T* C0 = g->C0 ? g->C0 + bat * g->sC0 : nullptr;
+  const T alpha = g->alpha, beta = g->beta;
+  const int ldc = g->ldc, ldc0 = g->ldc0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+    if (row >= M) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + wc * 32 + b * 16 + (lane >> 4) + 4 * v;
+        if (col >= N) continue;
+        T val = alpha * acc[a][b][v];
+        if (beta != T(0)) val += beta * C0[row + (long long)col * ldc0];
+        C[row + (long long)col * ldc] = val;
+      }
+    }
+  }
+}
+
+template <typename G>
+static long long prepare_groups(std::vector<G>& groups) {
+  long long total = 0;
+  for (auto& g : groups) {
+    g.tiles_m = (g.M + BM - 1) / BM;
+    g.tiles_n = (g.N + BN - 1) / BN;
+    g.first_block = total;
+    if (g.M > 0 && g.N > 0) total += (long long)g.tiles_m * g.tiles_n * g.batch;
+  }
+  return total;
+}
+
+// Launch a grouped GEMM whose descriptors already live in device memory
+// (dev_groups) and whose host copy (with first_block filled by
+// gemm_prepare) is `groups`.
+long long gemm_prepare(std::vector<GemmGroup>& groups) { return prepare_groups(groups); }
+long long gemm_prepare_f32(std::vector<GemmGroupF32>& groups) { return prepare_groups(groups); }
+
+int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb,
+                hipStream_t st, int n_override) {
+  if (nblocks <= 0) return HPS_OK;
+  dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, false, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, true, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, false, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else
+    hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, true, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, bool ta, bool tb,
+                    hipStream_t st, int n_override) {
+  if (nblocks <= 0) return HPS_OK;
+  dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, false, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, true, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, false, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else
+    hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, true, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+}  // namespace hps

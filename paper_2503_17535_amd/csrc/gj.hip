@@ -1,0 +1,377 @@
+// Inversion of the merge matrices D (Algorithm "Merge stage": "Invert D").
+//
+// Gauss-Jordan elimination with implicit partial pivoting: rows never move;
+// at step k the pivot of column k is the unused row p_k of largest |D(r, k)|
+// (ties: lowest row), and the in-place update replaces column k by the k-th
+// column of the accumulated elimination operator.  With R the in-place result
+// and pos = p^{-1}, the inverse is  D^{-1}(a, b) = R(p_a, pos_b).
+//
+// Two forms:
+//  * gj_small: one workgroup per matrix, the whole matrix in registers
+//    (cyclic TR x TC thread grid, the pivot column rotated into slot 0), for
+//    m <= 224 (the many small merges near the leaves);
+//  * blocked: per panel of NB columns one workgroup per matrix factors the
+//    panel with the panel's rows in registers (gj_panel), then a grouped
+//    MFMA GEMM applies the panel's rank-NB update to all other columns; a
+//    final gather unscrambles rows and columns.  Used for the few large
+//    merges near the root.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+#include "../../include/hps.h"
+
+namespace hps {
+
+// ---------------------------------------------------------------------------
+// gj_small
+// ---------------------------------------------------------------------------
+template <int TR, int TC, int RI, int RJ>
+__global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restrict__ Din, double* __restrict__ Zout,
+                                                           int m, int* __restrict__ flag) {
+  constexpr int NT = TR * TC;
+  __shared__ double s_lcol[2][RI * TR];
+  __shared__ double s_urow[2][RJ * TC];
+  __shared__ int s_perm[RJ * TC], s_pos[RI * TR];
+  __shared__ int s_piv[2];
+  __shared__ double s_pv[2];
+
+  const long long b = blockIdx.x;
+  const double* D = Din + b * (long long)m * m;
+  double* Z = Zout + b * (long long)m * m;
+  const int tid = threadIdx.x;
+  const int tr = tid % TR, tc = tid / TR;
+  const int lane = tid & 63;
+  const int gbase = lane - tr;
+
+  for (int i = tid; i < RI * TR; i += NT) s_pos[i] = -1;
+  double a[RI][RJ];
+#pragma unroll
+  for (int ri = 0; ri < RI; ++ri)
+#pragma unroll
+    for (int s = 0; s < RJ; ++s) {
+      const int row = tr + TR * ri, col = tc + TC * s;
+      a[ri][s] = (row < m && col < m) ? D[row + (long long)col * m] : 0.0;
+    }
+  unsigned used = 0;
+#pragma unroll
+  for (int ri = 0; ri < RI; ++ri)
+    if (tr + TR * ri >= m) used |= 1u << ri;
+  __syncthreads();
+
+  // slot s holds column block (kb + s) mod RJ during block kb
+  for (int kb = 0; kb < RJ; ++kb) {
+    for (int t = 0; t < TC; ++t) {
+      const int k = kb * TC + t;
+      if (k >= m) break;
+      const int buf = k & 1;
+      if (tc == t) {
+        double best = -1.0;
+        int brow = 0x7fffffff;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+          double v = fabs(a[ri][0]);
+          if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();  // NaN/inf rows still pivot
+          const int row = tr + TR * ri;
+          if (!((used >> ri) & 1u) && (v > best || (v == best && row < brow))) { best = v; brow = row; }
+        }
+#pragma unroll
+        for (int off = TR / 2; off >= 1; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int orow = __shfl_xor(brow, off);
+          if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+          const int row = tr + TR * ri;
+          if (row == brow) mine = a[ri][0];
+          s_lcol[buf][row] = (row == brow) ? 0.0 : a[ri][0];
+        }
+        const double pv = __shfl(mine, gbase + brow % TR);
+        if (tr == 0) {
+          s_piv[buf] = brow;
+          s_pv[buf] = pv;
+          s_perm[k] = brow;
+          s_pos[brow] = k;
+          if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
+        }
+      }
+      __syncthreads();
+      const int pr = s_piv[buf];
+      if (tr == pr % TR) {
+        const int rip = pr / TR;
+        used |= 1u << rip;
+        const double pinv = 1.0 / s_pv[buf];
+#pragma unroll
+        for (int s = 0; s < RJ; ++s) {
+          double v = 0.0;
+#pragma unroll
+          for (int ri = 0; ri < RI; ++ri)
+            if (ri == rip) v = a[ri][s];
+          if (s == 0 && tc == t) v = 1.0;
+          v *= pinv;
+#pragma unroll
+          for (int ri = 0; ri < RI; ++ri)
+            if (ri == rip) a[ri][s] = v;
+          s_urow[buf][tc + TC * s] = v;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RJ; ++s) {
+        const double u = s_urow[buf][tc + TC * s];
+        const bool colk = (s == 0 && tc == t);
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+          const int row = tr + TR * ri;
+          if (row == pr) continue;
+          const double base = colk ? 0.0 : a[ri][s];
+          a[ri][s] = base - s_lcol[buf][row] * u;
+        }
+      }
+    }
+    // rotate slots left cyclically
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+      const double first = a[ri][0];
+#pragma unroll
+      for (int s = 0; s + 1 < RJ; ++s) a[ri][s] = a[ri][s + 1];
+      a[ri][RJ - 1] = first;
+    }
+  }
+  __syncthreads();
+  // Z(pos[row], perm[col]) = R(row, col)
+#pragma unroll
+  for (int ri = 0; ri < RI; ++ri) {
+    const int row = tr + TR * ri;
+    if (row >= m) continue;
+    const int zr = s_pos[row];
+#pragma unroll
+    for (int s = 0; s < RJ; ++s) {
+      const int col = tc + TC * s;
+      if (col < m) Z[zr + (long long)s_perm[col] * m] = a[ri][s];
+    }
+  }
+}
+
+template <int RI>
+static void launch_gj_small_ri(const double* D, double* Z, int m, int* flag, long long batch, hipStream_t st) {
+  constexpr int RJ = (RI + 1) / 2;
+  hipLaunchKernelGGL((gj_small_kernel<16, 32, RI, RJ>), dim3((unsigned)batch), dim3(512), 0, st, D, Z, m, flag);
+}
+
+int gj_small_max() { return 224; }
+
+int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batch, hipStream_t st) {
+  const int ri = (m + 15) / 16;
+  switch (ri) {
+    case 1: launch_gj_small_ri<1>(D, Z, m, flag, batch, st); break;
+    case 2: launch_gj_small_ri<2>(D, Z, m, flag, batch, st); break;
+    case 3: launch_gj_small_ri<3>(D, Z, m, flag, batch, st); break;
+    case 4: launch_gj_small_ri<4>(D, Z, m, flag, batch, st); break;
+    case 5: launch_gj_small_ri<5>(D, Z, m, flag, batch, st); break;
+    case 6: launch_gj_small_ri<6>(D, Z, m, flag, batch, st); break;
+    case 7: launch_gj_small_ri<7>(D, Z, m, flag, batch, st); break;
+    case 8: launch_gj_small_ri<8>(D, Z, m, flag, batch, st); break;
+    case 9: launch_gj_small_ri<9>(D, Z, m, flag, batch, st); break;
+    case 10: launch_gj_small_ri<10>(D, Z, m, flag, batch, st); break;
+    case 11: launch_gj_small_ri<11>(D, Z, m, flag, batch, st); break;
+    case 12: launch_gj_small_ri<12>(D, Z, m, flag, batch, st); break;
+    case 13: launch_gj_small_ri<13>(D, Z, m, flag, batch, st); break;
+    case 14: launch_gj_small_ri<14>(D, Z, m, flag, batch, st); break;
+    default:
+      set_error("gj_small: m too large");
+      return HPS_EUNSUPPORTED;
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// blocked form
+// ---------------------------------------------------------------------------
+constexpr int PANEL_THREADS = 1024;
+
+// Initialize the pivot bookkeeping of a batch (pos = -1).
+__global__ void gj_init_kernel(int* pos, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) pos[i] = -1;
+}
+
+template <int RPT, int NB>
+__global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
+                                                                  int* __restrict__ posall, int* __restrict__ pivall,
+                                                                  double* __restrict__ Wall, double* __restrict__ snapall,
+                                                                  int* __restrict__ flag) {
+  constexpr int NW = PANEL_THREADS / 64;
+  __shared__ double s_cv[2][NW];
+  __shared__ int s_cr[2][NW];
+  __shared__ double s_prow[2][NB];
+  __shared__ double s_pv[2];
+  __shared__ int s_piv[NB];
+
+  const long long b = blockIdx.x;
+  double* A = Aall + b * (long long)m * m;
+  int* pos = posall + b * (long long)m;
+  int* piv = pivall + b * (long long)m;
+  double* W = Wall + b * (long long)m * NB;
+  double* snap = snapall + b * (long long)m * NB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  double a[RPT][NB];
+  unsigned used = 0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + PANEL_THREADS * i;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      a[i][c] = (row < m && c < nbw) ? A[row + (long long)(j0 + c) * m] : 0.0;
+    if (row >= m || pos[row] >= 0) used |= 1u << i;
+  }
+
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c >= nbw) break;
+    const int k = j0 + c;
+    const int buf = c & 1;
+    double best = -1.0;
+    int brow = 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      double v = fabs(a[i][c]);
+      if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();  // NaN/inf rows still pivot
+      const int row = tid + PANEL_THREADS * i;
+      if (!((used >> i) & 1u) && (v > best || (v == best && row < brow))) { best = v; brow = row; }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int orow = __shfl_xor(brow, off);
+      if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+    }
+    if (lane == 0) { s_cv[buf][wave] = best; s_cr[buf][wave] = brow; }
+    __syncthreads();
+    best = s_cv[buf][0];
+    brow = s_cr[buf][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double ob = s_cv[buf][w];
+      const int orow = s_cr[buf][w];
+      if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+    }
+    const int pr = brow;
+    if (tid == pr % PANEL_THREADS) {
+      const int ip = pr / PANEL_THREADS;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == ip) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) s_prow[buf][cc] = a[i][cc];
+          s_pv[buf] = a[i][c];
+          used |= 1u << i;
+        }
+      pos[pr] = k;
+      piv[k] = pr;
+      s_piv[c] = pr;
+    }
+    __syncthreads();
+    const double pv = s_pv[buf];
+    if (tid == 0 && (!(pv != 0.0) || !isfinite(pv))) atomicOr(flag, 2);
+    const double pinv = 1.0 / pv;
+    double u[NB];
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) u[cc] = (cc == c ? 1.0 : s_prow[buf][cc]) * pinv;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + PANEL_THREADS * i;
+      if (row == pr) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) a[i][cc] = u[cc];
+      } else {
+        const double l = a[i][c];
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) a[i][cc] = (cc == c ? 0.0 : a[i][cc]) - l * u[cc];
+      }
+    }
+  }
+  __syncthreads();
+  // write the panel back (its columns are final for this panel) and W = panel - E_P
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + PANEL_THREADS * i;
+    if (row >= m) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c < nbw) {
+        A[row + (long long)(j0 + c) * m] = a[i][c];
+        W[row + (long long)c * m] = a[i][c] - (row == s_piv[c] ? 1.0 : 0.0);
+      } else {
+        W[row + (long long)c * m] = 0.0;
+      }
+    }
+  }
+  // snapshot of the pivot rows outside the panel (before the GEMM updates them)
+  for (long long e = tid; e < (long long)NB * m; e += PANEL_THREADS) {
+    const int c = (int)(e % NB);
+    const int col = (int)(e / NB);
+    double v = 0.0;
+    if (c < nbw && (col < j0 || col >= j0 + nbw)) v = A[s_piv[c] + (long long)col * m];
+    snap[e] = v;
+  }
+}
+
+int gj_panel_width(int m) {
+  if (m <= 2048) return 16;
+  if (m <= 4096) return 8;
+  if (m <= 8192) return 4;
+  return 0;
+}
+
+int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
+                    long long batch, hipStream_t st) {
+  dim3 grid((unsigned)batch), block(PANEL_THREADS);
+  if (m <= 1024)
+    hipLaunchKernelGGL((gj_panel_kernel<1, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  else if (m <= 2048)
+    hipLaunchKernelGGL((gj_panel_kernel<2, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  else if (m <= 4096)
+    hipLaunchKernelGGL((gj_panel_kernel<4, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  else if (m <= 8192)
+    hipLaunchKernelGGL((gj_panel_kernel<8, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  else {
+    set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
+    return HPS_EUNSUPPORTED;
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int gj_init_launch(int* pos, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(gj_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// Z(a, b) = R(piv[a], pos[b])
+__global__ void gj_unscramble_kernel(const double* __restrict__ Rall, double* __restrict__ Zall, int m,
+                                     const int* __restrict__ posall, const int* __restrict__ pivall) {
+  const long long b = blockIdx.y;
+  const int col = blockIdx.x;
+  const double* R = Rall + b * (long long)m * m;
+  double* Z = Zall + b * (long long)m * m;
+  const int* pos = posall + b * (long long)m;
+  const int* piv = pivall + b * (long long)m;
+  const long long src_col = (long long)pos[col] * m;
+  for (int a = threadIdx.x; a < m; a += blockDim.x) Z[a + (long long)col * m] = R[piv[a] + src_col];
+}
+
+int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(gj_unscramble_kernel, dim3((unsigned)m, (unsigned)batch), dim3(256), 0, st, R, Z, m, pos, piv);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+}  // namespace hps

@@ -1,0 +1,91 @@
+"""GPU parity: the HIP build + solve against the CPU oracle on the same
+seeded inputs (rel. l_inf <= 1e-10 per right-hand side, the solver's stated
+fp64 bar).  Sizes span several tiles, ragged tails, both Gauss-Jordan forms
+(register-resident for D <= 224, blocked above) and the 16-rhs chunking."""
+import numpy as np
+import pytest
+
+from gpu_util import oracle_solve, rel_inf, rhs, say, var_coeffs
+from oracle import hps as ohps
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-10
+
+
+def _run(d, p, L, nrhs, seed=0, k=0.0, with_src=True, mixed=True, flags=0):
+    import paper_2503_17535_amd as hp
+    say(f"[case] d={d} p={p} L={L} nrhs={nrhs} k={k} src={with_src}")
+    tree = ohps.Tree(d, L)
+    disc = ohps.LeafDisc(d, p)
+    pts = tree.leaf_points(disc)
+    bpts = tree.root_boundary_points(disc)
+    c = var_coeffs(pts, seed, k, mixed)
+    bd, src = rhs(pts, bpts, nrhs, seed)
+    if not with_src:
+        src = None
+    ref = oracle_solve(d, p, L, c, bd, src)
+    dev = torch.device("cuda:0")
+    t = hp.tree(d, L)
+    op = hp.build(t, p, torch.tensor(c, device=dev), flags=flags)
+    u = op.solve(torch.tensor(bd, device=dev), None if src is None else torch.tensor(src, device=dev))
+    torch.cuda.synchronize()
+    err = rel_inf(u.cpu().numpy(), ref)
+    say(f"[case] rel err {err:.3e}")
+    op.free()
+    return err
+
+
+@pytest.mark.parametrize("p,L,nrhs", [(8, 2, 1), (6, 3, 3), (10, 3, 2), (12, 2, 5), (16, 2, 2)])
+def test_parity_small_2d(p, L, nrhs):
+    assert _run(2, p, L, nrhs) < TOL
+
+
+def test_parity_no_source():
+    assert _run(2, 8, 3, 2, with_src=False) < TOL
+
+
+def test_parity_helmholtz_like_p16():
+    assert _run(2, 16, 3, 4, k=10.0, mixed=False) < TOL
+
+
+@pytest.mark.parametrize("p,L", [(16, 4), (7, 5)])
+def test_parity_blocked_gauss_jordan(p, L):
+    # root D = 448 (p=16, L=4) and 320 (p=7, L=5): blocked Gauss-Jordan path
+    assert _run(2, p, L, 2) < TOL
+
+
+def test_parity_many_rhs_chunks():
+    # 20 right-hand sides: two passes of the 16-column solve
+    assert _run(2, 8, 2, 20) < TOL
+
+
+def test_singular_coefficients_raise():
+    import paper_2503_17535_amd as hp
+    say("[case] singular")
+    t = hp.tree(2, 2)
+    s = hp.sizes(t, 8)
+    c = torch.zeros((s.n_leaves, s.n_terms, s.pts_per_leaf), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(hp.HPSError) as e:
+        hp.build(t, 8, c)
+    assert e.value.code == hp.HPS_ESINGULAR
+
+
+def test_determinism_bitwise():
+    import paper_2503_17535_amd as hp
+    say("[case] determinism")
+    d, p, L = 2, 12, 3
+    tree = ohps.Tree(d, L)
+    disc = ohps.LeafDisc(d, p)
+    pts = tree.leaf_points(disc)
+    c = torch.tensor(var_coeffs(pts, 3), device="cuda:0")
+    bd, src = rhs(pts, tree.root_boundary_points(disc), 3, 3)
+    bd, src = torch.tensor(bd, device="cuda:0"), torch.tensor(src, device="cuda:0")
+    t = hp.tree(d, L)
+    us = []
+    for _ in range(2):
+        op = hp.build(t, p, c)
+        us.append(op.solve(bd, src).cpu())
+        op.free()
+    assert torch.equal(us[0], us[1])

@@ -1,0 +1,95 @@
+"""Host-side checks of the C library (no GPU): it loads, exports every
+symbol include/hps.h declares, its host precompute and point layouts agree
+with the oracle, and invalid arguments are rejected."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2503_17535_amd as hp
+from oracle import hps as ohps
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hps.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hps_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hp.lib()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hp.EXPORTS)
+
+
+@pytest.mark.parametrize("d,p", [(2, 4), (2, 8), (2, 12), (2, 16), (3, 5), (3, 8)])
+def test_precompute_matches_oracle(d, p):
+    disc = ohps.LeafDisc(d, p)
+    np.testing.assert_allclose(hp.precompute_matrix(d, p, 0)[0], disc.x, atol=1e-15)
+    np.testing.assert_allclose(hp.precompute_matrix(d, p, 1)[0], disc.gl, atol=1e-14)
+    np.testing.assert_allclose(hp.precompute_matrix(d, p, 2)[0], disc.glw, atol=1e-14)
+    D = hp.precompute_matrix(d, p, 3)
+    np.testing.assert_allclose(D, disc.D, atol=1e-11 * p * p)
+    np.testing.assert_array_equal(hp.precompute_matrix(d, p, 6)[0].astype(int), disc.Ii)
+    np.testing.assert_array_equal(hp.precompute_matrix(d, p, 7)[0].astype(int), disc.Ie)
+    np.testing.assert_allclose(hp.precompute_matrix(d, p, 4), disc.P, atol=1e-13)
+    Q = hp.precompute_matrix(d, p, 5)
+    np.testing.assert_allclose(Q, disc.Q, atol=1e-11 * np.abs(disc.Q).max())
+
+
+@pytest.mark.parametrize("d,p,L", [(2, 8, 2), (2, 16, 3), (3, 6, 2)])
+def test_point_layouts_match_oracle(d, p, L):
+    t = hp.tree(d, L)
+    tr = ohps.Tree(d, L)
+    disc = ohps.LeafDisc(d, p)
+    np.testing.assert_allclose(hp.leaf_points(t, p), tr.leaf_points(disc), atol=1e-15)
+    np.testing.assert_allclose(hp.boundary_points(t, p), tr.root_boundary_points(disc), atol=1e-15)
+
+
+def test_sizes_and_paper_D_sizes():
+    for p, L, want in [(8, 3, 6912), (12, 3, 19200), (16, 2, 9408)]:
+        assert hp.sizes(hp.tree(3, L), p).root_D == want
+    s = hp.sizes(hp.tree(2, 6), 16)
+    assert (s.n_leaves, s.pts_per_leaf, s.n_root_bdry, s.root_D) == (4096, 256, 3584, 1792)
+    for d, p, L in [(2, 8, 2), (2, 16, 6), (3, 12, 3)]:
+        assert hp.sizes(hp.tree(d, L), p).root_D == ohps.merge_sizes(d, p, L)[-1][1]
+
+
+def test_footprint_counts_resident_operators():
+    t = hp.tree(2, 6)
+    fp = hp.footprint(t, 16)
+    # leaf LU + Y (+pivots) and per merge Z, S, B blocks
+    leaf = 4096 * (196 * 196 + 196 * 56) * 8
+    assert leaf < fp < leaf + 6 * 110e6
+    assert hp.footprint(t, 16, hp.FLAG_ROOT_T) > fp
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(depth=0), dict(lo=1.0, hi=-1.0)])
+def test_invalid_tree_rejected(bad):
+    args = dict(dim=2, depth=2, lo=-1.0, hi=1.0)
+    args.update(bad)
+    t = hp.Tree(args["dim"], args["depth"], args["lo"], args["hi"])
+    with pytest.raises(hp.HPSError) as e:
+        hp.sizes(t, 8)
+    assert e.value.code == hp.HPS_EINVAL
+
+
+def test_invalid_p_and_null_pointers_rejected():
+    L = hp.lib()
+    t = hp.tree(2, 2)
+    with pytest.raises(hp.HPSError):
+        hp.sizes(t, 3)
+    with pytest.raises(hp.HPSError):
+        hp.sizes(t, 17)
+    # build with NULL coefficients fails in argument checking, before any device work
+    h = ctypes.c_void_p()
+    rc = L.hps_build(ctypes.byref(t), 8, None, 0, None, ctypes.byref(h))
+    assert rc == hp.HPS_EINVAL and not h.value
+    assert b"NULL" in L.hps_last_error()
+    assert L.hps_solve(None, None, None, None, 1, 0, None) == hp.HPS_EINVAL

@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the HPS hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2D
+variable-coefficient Helmholtz  -Lap u - k^2 (1 + q(x)) u = f  on [-1, 1]^2,
+k = 40, q = 8 seeded Gaussian bumps (amplitude U(0, 0.5), width 0.1), uniform
+quadtree of depth 6 (4096 leaves), p = 16, fp64, 16 right-hand sides (Fourier
+boundary data + one Gaussian source bump each).  Inputs are synthetic, seeded
+(``workloads``), and resident in HBM before timing starts.
+
+One step = build (leaf stage + all merge levels) + one 16-rhs solve (upward
+source pass + downward pass) + release of the operator.  ``value`` is leaves
+per second of whole steps; build-only leaves/s and solves/s are reported
+beside it from HIP events on the stream the library runs on.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HPS build leaves/s + solves/s at rel.err<=1e-10; serving p99 latency"
+K_WAVE, DEPTH, P, NRHS = 40.0, 6, 16, 16
+
+# MI355X published peaks used for roofline fractions
+PEAK_FP64_TFLOPS = 78.6      # fp64 vector and fp64 matrix (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+
+def leaf_flops(p: int) -> float:
+    """Algorithmic flops of one 2D leaf in the fused leaf kernel: LU of
+    L_ii (n_i = (p-2)^2) with partial pivoting, (2/3) n_i^3, plus the forward
+    and back substitution of the n_b = 4(p-2) columns of L_ie P, 2 n_i^2 n_b."""
+    ni, nb = (p - 2) ** 2, 4 * (p - 2)
+    return (2.0 / 3.0) * ni ** 3 + 2.0 * ni * ni * nb
+
+
+def cpu_baseline(seconds_budget: float = 30.0):
+    """The oracle (plain NumPy/SciPy) on a bounded sample of the workload:
+    one quadrant subtree of depth 5 (1024 leaves, same p, k and inputs), build
+    + 16 solves, scaled to leaves/s."""
+    import numpy as np
+    import workloads as W
+    from oracle import hps as ohps
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    depth = DEPTH - 1
+    tree = ohps.Tree(2, depth, -1.0, 0.0)          # the SW quadrant of [-1,1]^2
+    disc = ohps.LeafDisc(2, P)
+    pts = tree.leaf_points(disc)
+    bpts = tree.root_boundary_points(disc)
+    c, bd, src = W.helmholtz_inputs(pts, bpts, K_WAVE, NRHS)
+    t0 = time.perf_counter()
+    op = ohps.build(tree, P, c)
+    t1 = time.perf_counter()
+    for r in range(NRHS):
+        ohps.solve(op, bd[r], src[r])
+    t2 = time.perf_counter()
+    nl = tree.n_leaves
+    return {"value": nl / (t2 - t0), "unit": "leaves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle build + {NRHS} solves of one depth-{depth} quadrant subtree "
+                      f"({nl} leaves, p={P}, k={K_WAVE:g}); build {t1 - t0:.2f}s, solves {t2 - t1:.2f}s",
+            "build_leaves_per_s": nl / (t1 - t0), "solves_per_s": NRHS / (t2 - t1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2503_17535_amd as hp
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    t = hp.tree(2, DEPTH)
+    sz = hp.sizes(t, P)
+    pts = hp.leaf_points(t, P)
+    bpts = hp.boundary_points(t, P)
+    coeffs, bdry, src = W.helmholtz_inputs(pts, bpts, K_WAVE, NRHS)
+    c_d = torch.tensor(coeffs, device=dev)
+    b_d = torch.tensor(bdry, device=dev)
+    s_d = torch.tensor(src, device=dev)
+    u_d = torch.empty((NRHS, sz.n_leaves, sz.pts_per_leaf), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    flags = hp.FLAG_TIMING
+
+    def step(record=None):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        op = hp.build(t, P, c_d, flags=flags)
+        build_stages = op.stage_times()
+        e1.record()
+        op.solve(b_d, s_d, out=u_d)
+        e2.record()
+        solve_stages = op.stage_times()
+        op.free()
+        if record is not None:
+            record.append((e0, e1, e2, build_stages + solve_stages))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ms_step = wall * 1e3 / args.steps
+    build_ms = float(np.mean([a.elapsed_time(b) for a, b, c, s in recs]))
+    solve_ms = float(np.mean([b.elapsed_time(c) for a, b, c, s in recs]))
+    stages = {}
+    for *_, st in recs:
+        for name, ms in st:
+            stages.setdefault(name, []).append(ms)
+    stages = {k: float(np.mean(v)) for k, v in stages.items()}
+
+    # dominant kernel: the fused leaf factorization (one launch per build)
+    leaf_ms = stages.get("leaf_factor", float("nan"))
+    flops = leaf_flops(P) * sz.n_leaves
+    achieved = flops / (leaf_ms * 1e-3) / 1e12
+    roofline = {"kernel": "leaf2d_factor_kernel<16>", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "algorithmic_flops_per_launch": flops, "avg_launch_ms": leaf_ms}
+
+    out = {
+        "metric": METRIC,
+        "value": sz.n_leaves * 1e3 / ms_step,
+        "unit": "leaves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2D Helmholtz k=40, q = 8 Gaussian bumps, depth-6 quadtree (4096 leaves), "
+                               "p=16, build + 16-rhs solve", "n_leaves": sz.n_leaves, "p": P,
+                   "depth": DEPTH, "nrhs": NRHS, "k": K_WAVE},
+        "build_ms": build_ms, "solve_ms": solve_ms,
+        "build_leaves_per_s": sz.n_leaves * 1e3 / build_ms,
+        "solves_per_s": NRHS * 1e3 / solve_ms,
+        "stages_ms": stages,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,3 +89,25 @@ def test_determinism_bitwise():
         us.append(op.solve(bd, src).cpu())
         op.free()
     assert torch.equal(us[0], us[1])
+
+
+def test_parity_helmholtz_full_size():
+    """The benchmark workload at full size (k = 40, depth 6, p = 16, 4096
+    leaves, 16 right-hand sides), every output point against the oracle."""
+    import paper_2503_17535_amd as hp
+    import workloads as W
+    say("[case] full-size Helmholtz k=40 L=6 p=16 nrhs=16")
+    tree = ohps.Tree(2, 6)
+    disc = ohps.LeafDisc(2, 16)
+    pts = tree.leaf_points(disc)
+    bpts = tree.root_boundary_points(disc)
+    c, bd, src = W.helmholtz_inputs(pts, bpts, 40.0, 16)
+    dev = torch.device("cuda:0")
+    op = hp.build(hp.tree(2, 6), 16, torch.tensor(c, device=dev))
+    u = op.solve(torch.tensor(bd, device=dev), torch.tensor(src, device=dev)).cpu().numpy()
+    op.free()
+    op_o = ohps.build(tree, 16, c)
+    ref = np.stack([ohps.solve(op_o, bd[r], src[r]) for r in range(16)])
+    err = rel_inf(u, ref)
+    say(f"[case] rel err {err:.3e}")
+    assert err < TOL

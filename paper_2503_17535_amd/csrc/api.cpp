@@ -37,14 +37,15 @@ int leaf2d_launch(int p, const double* coeffs, const double* D1, const double* D
 int gj_small_max();
 int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batch, hipStream_t st);
 int gj_panel_width(int m);
+int gj_panel_max_nb();
 int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
                     long long batch, hipStream_t st);
 int gj_init_launch(int* pos, long long n, hipStream_t st);
 int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
                          hipStream_t st);
-int block_copy_launch(const BlockOp* dev_ops, int nops, int max_cols, int ncols_rt, double* dst, long long dst_stride,
-                      const double* src0, long long s0_stride, const double* src1, long long s1_stride,
-                      long long batch, int max_rows, hipStream_t st);
+int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
+                      int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
+                      const double* src1, long long s1_stride, long long batch, hipStream_t st);
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
                     int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st);
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
@@ -180,8 +181,7 @@ struct GemmCall {
   bool ta = false, tb = false;
 };
 struct CopyCall {
-  int first = 0, count = 0;
-  int max_rows = 0, max_cols = 0;  // max_cols 0 = runtime column count
+  int first_task = 0, ntasks = 0;
 };
 
 struct LevelPlan {
@@ -234,6 +234,10 @@ struct hps_op {
   hps::GemmGroup* dgroups = nullptr;
   std::vector<hps::BlockOp> hops;
   hps::BlockOp* dops = nullptr;
+  std::vector<hps::CopyItem> hitems;
+  hps::CopyItem* ditems = nullptr;
+  std::vector<hps::CopyTask> htasks;
+  hps::CopyTask* dtasks = nullptr;
   hps::GemmCall gemmTleaf, gemmHleaf;
   hps::CopyCall copyRoot;
   std::vector<hps::Alloc> allocs;
@@ -263,19 +267,42 @@ int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta 
   return HPS_OK;
 }
 
+// Split a table of block ops into workgroup tasks of about kTaskElems elements
+// (runtime-column ops count as 16 columns).
 void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
-  call->first = (int)op->hops.size();
-  call->count = (int)ops.size();
-  call->max_rows = 0;
-  call->max_cols = 0;
-  bool runtime_cols = false;
-  for (auto& o : ops) {
-    call->max_rows = std::max(call->max_rows, o.rows);
-    if (o.cols <= 0) runtime_cols = true;
-    call->max_cols = std::max(call->max_cols, o.cols);
-  }
-  if (runtime_cols) call->max_cols = 0;
+  constexpr long long kTaskElems = 16384;
+  const int op0 = (int)op->hops.size();
   op->hops.insert(op->hops.end(), ops.begin(), ops.end());
+  call->first_task = (int)op->htasks.size();
+  CopyTask cur{(int)op->hitems.size(), (int)op->hitems.size()};
+  long long load = 0;
+  auto flush = [&]() {
+    if (cur.end > cur.begin) op->htasks.push_back(cur);
+    cur.begin = cur.end = (int)op->hitems.size();
+    load = 0;
+  };
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const BlockOp& o = ops[i];
+    if (o.cols <= 0) {
+      const long long e = (long long)o.rows * 16;
+      if (load + e > kTaskElems) flush();
+      op->hitems.push_back({op0 + (int)i, 0, -1});
+      cur.end = (int)op->hitems.size();
+      load += e;
+      continue;
+    }
+    const int chunk = (int)std::max<long long>(1, kTaskElems / std::max(1, o.rows));
+    for (int c0 = 0; c0 < o.cols; c0 += chunk) {
+      const int c1 = std::min(o.cols, c0 + chunk);
+      const long long e = (long long)o.rows * (c1 - c0);
+      if (load + e > kTaskElems) flush();
+      op->hitems.push_back({op0 + (int)i, c0, c1});
+      cur.end = (int)op->hitems.size();
+      load += e;
+    }
+  }
+  flush();
+  call->ntasks = (int)op->htasks.size() - call->first_task;
 }
 
 GemmGroup make_group(const double* A, long long sA, int lda, const double* B, long long sB, int ldb, double* C,
@@ -315,8 +342,8 @@ int run_gemm(hps_op* op, const GemmCall& c, hipStream_t st, int n_override = 0) 
 
 int run_copy(hps_op* op, const CopyCall& c, int ncols_rt, double* dst, long long dst_stride, const double* s0,
              long long s0_stride, const double* s1, long long s1_stride, long long batch, hipStream_t st) {
-  return block_copy_launch(op->dops + c.first, c.count, c.max_cols, ncols_rt, dst, dst_stride, s0, s0_stride, s1,
-                           s1_stride, batch, c.max_rows, st);
+  return block_copy_launch(op->dops, op->ditems, op->dtasks + c.first_task, c.ntasks, ncols_rt, dst, dst_stride, s0,
+                           s0_stride, s1, s1_stride, batch, st);
 }
 
 void stage_begin(hps_op* op, const char* name, hipStream_t st) {
@@ -425,8 +452,9 @@ int plan_op(hps_op* op) {
       }
       P.gj_pos = (int*)op_alloc(op, sizeof(int) * nm * m, false);
       P.gj_piv = (int*)op_alloc(op, sizeof(int) * nm * m, false);
-      P.gj_W = (double*)op_alloc(op, sizeof(double) * nm * m * P.gj_nb, false);
-      P.gj_snap = (double*)op_alloc(op, sizeof(double) * nm * m * P.gj_nb, false);
+      const int mnb = gj_panel_max_nb();
+      P.gj_W = (double*)op_alloc(op, sizeof(double) * nm * m * mnb, false);
+      P.gj_snap = (double*)op_alloc(op, sizeof(double) * nm * m * mnb, false);
       if (!P.gj_pos || !P.gj_piv || !P.gj_W || !P.gj_snap) {
         set_error("device allocation failed (Gauss-Jordan workspace)");
         return HPS_ENOMEM;
@@ -434,14 +462,14 @@ int plan_op(hps_op* op) {
       for (int j0 = 0; j0 < m; j0 += P.gj_nb) {
         const int w = std::min(P.gj_nb, m - j0);
         std::vector<GemmGroup> gs;
+        const long long sw = (long long)m * mnb;  // W: m x mnb (ld m); snapshot: mnb x m (ld mnb)
         if (j0 > 0)
-          gs.push_back(make_group(P.gj_W, (long long)m * P.gj_nb, m, P.gj_snap, (long long)m * P.gj_nb, P.gj_nb, P.Dbuf,
-                                  (long long)m * m, m, m, j0, w, 1.0, 1.0, nm, P.Dbuf, (long long)m * m, m));
+          gs.push_back(make_group(P.gj_W, sw, m, P.gj_snap, sw, mnb, P.Dbuf, (long long)m * m, m, m, j0, w, 1.0, 1.0,
+                                  nm, P.Dbuf, (long long)m * m, m));
         if (j0 + w < m)
-          gs.push_back(make_group(P.gj_W, (long long)m * P.gj_nb, m, P.gj_snap + (long long)(j0 + w) * P.gj_nb,
-                                  (long long)m * P.gj_nb, P.gj_nb, P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m,
-                                  m, m - j0 - w, w, 1.0, 1.0, nm, P.Dbuf + (long long)(j0 + w) * m, (long long)m * m,
-                                  m));
+          gs.push_back(make_group(P.gj_W, sw, m, P.gj_snap + (long long)(j0 + w) * mnb, sw, mnb,
+                                  P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m, m, m - j0 - w, w, 1.0, 1.0, nm,
+                                  P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m));
         GemmCall c;
         add_gemm(op, gs, &c);
         P.gj_upd.push_back(c);
@@ -584,7 +612,14 @@ int plan_op(hps_op* op) {
   // upload descriptor tables
   op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
   op->dops = (BlockOp*)op_alloc(op, sizeof(BlockOp) * std::max<size_t>(1, op->hops.size()), false);
-  if (!op->dgroups || !op->dops) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
+  op->ditems = (CopyItem*)op_alloc(op, sizeof(CopyItem) * std::max<size_t>(1, op->hitems.size()), false);
+  op->dtasks = (CopyTask*)op_alloc(op, sizeof(CopyTask) * std::max<size_t>(1, op->htasks.size()), false);
+  if (!op->dgroups || !op->dops || !op->ditems || !op->dtasks) {
+    set_error("device allocation failed (descriptors)");
+    return HPS_ENOMEM;
+  }
+  HPS_HIP_TRY(hipMemcpy(op->ditems, op->hitems.data(), sizeof(CopyItem) * op->hitems.size(), hipMemcpyHostToDevice));
+  HPS_HIP_TRY(hipMemcpy(op->dtasks, op->htasks.data(), sizeof(CopyTask) * op->htasks.size(), hipMemcpyHostToDevice));
   HPS_HIP_TRY(hipMemcpy(op->dgroups, op->hgroups.data(), sizeof(GemmGroup) * op->hgroups.size(), hipMemcpyHostToDevice));
   HPS_HIP_TRY(hipMemcpy(op->dops, op->hops.data(), sizeof(BlockOp) * op->hops.size(), hipMemcpyHostToDevice));
   return HPS_OK;

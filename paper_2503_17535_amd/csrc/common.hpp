@@ -63,6 +63,17 @@ struct BlockOp {
   int rows, cols;
 };
 
+// Work decomposition of a table of BlockOps: an item is a column range of one
+// op (c1 < 0: all runtime columns); a task (one workgroup per batch item) is a
+// run of consecutive items, sized so that every workgroup moves a similar
+// number of elements.
+struct CopyItem {
+  int op, c0, c1;
+};
+struct CopyTask {
+  int begin, end;
+};
+
 // error reporting (implemented in api.cpp)
 void set_error(const std::string& msg);
 

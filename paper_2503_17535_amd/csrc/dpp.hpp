@@ -1,0 +1,81 @@
+// Cross-lane argmax helpers on DPP (data-parallel primitives): VALU lane
+// exchanges within a 16-lane row, no LDS round trip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hps {
+
+// DPP controls (GFX9 encoding)
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_ROR4 = 0x124;  // rotate right by 4 within a 16-lane row
+constexpr int DPP_ROW_ROR8 = 0x128;  // rotate right by 8 within a 16-lane row
+constexpr int DPP_HALF_MIRROR = 0x141;  // reverse within each 8-lane half row
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// (key, row, val): keep the larger key; ties go to the lower row.
+__device__ __forceinline__ void amax_merge(double& key, int& row, double& val, double ok, int orow, double oval) {
+  if (ok > key || (ok == key && orow < row)) {
+    key = ok;
+    row = orow;
+    val = oval;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void amax_step(double& key, int& row, double& val) {
+  const double ok = dpp_d<CTRL>(key);
+  const int orow = dpp_i<CTRL>(row);
+  const double oval = dpp_d<CTRL>(val);
+  amax_merge(key, row, val, ok, orow, oval);
+}
+
+// Argmax over groups of G consecutive lanes (G = 8 or 16, aligned); every lane
+// of the group ends with the group's result.
+template <int G>
+__device__ __forceinline__ void group_argmax(double& key, int& row, double& val) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  if (G == 16) {
+    amax_step<DPP_ROW_ROR8>(key, row, val);
+    amax_step<DPP_ROW_ROR4>(key, row, val);
+  } else {
+    amax_step<DPP_HALF_MIRROR>(key, row, val);
+  }
+  amax_step<DPP_QUAD_XOR2>(key, row, val);
+  amax_step<DPP_QUAD_XOR1>(key, row, val);
+}
+
+// Argmax over the whole 64-lane wavefront; every lane ends with the result.
+__device__ __forceinline__ void wave_argmax(double& key, int& row, double& val) {
+  group_argmax<16>(key, row, val);
+  double k = key, v = val;
+  int r = row;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const double ok = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(k), 16 * g),
+                                       __builtin_amdgcn_readlane(__double2loint(k), 16 * g));
+    const int orow = __builtin_amdgcn_readlane(r, 16 * g);
+    const double oval = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * g),
+                                         __builtin_amdgcn_readlane(__double2loint(v), 16 * g));
+    amax_merge(key, row, val, ok, orow, oval);
+  }
+}
+
+// |x| as a pivot key: NaN and inf map to +inf so that some unused row is
+// always chosen.
+__device__ __forceinline__ double pivot_key(double x) {
+  double v = fabs(x);
+  return (v <= 1.7976931348623157e308) ? v : __builtin_inf();
+}
+
+}  // namespace hps

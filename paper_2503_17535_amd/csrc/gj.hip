@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "dpp.hpp"
 #include "../../include/hps.h"
 
 namespace hps {
@@ -67,29 +68,17 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
       if (k >= m) break;
       const int buf = k & 1;
       if (tc == t) {
-        double best = -1.0;
+        double key = -1.0, pv = 0.0;
         int brow = 0x7fffffff;
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri) {
-          double v = fabs(a[ri][0]);
-          if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();  // NaN/inf rows still pivot
-          const int row = tr + TR * ri;
-          if (!((used >> ri) & 1u) && (v > best || (v == best && row < brow))) { best = v; brow = row; }
-        }
-#pragma unroll
-        for (int off = TR / 2; off >= 1; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int orow = __shfl_xor(brow, off);
-          if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-        }
-        double mine = 0.0;
+        for (int ri = 0; ri < RI; ++ri)
+          if (!((used >> ri) & 1u)) amax_merge(key, brow, pv, pivot_key(a[ri][0]), tr + TR * ri, a[ri][0]);
+        group_argmax<TR>(key, brow, pv);
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
           const int row = tr + TR * ri;
-          if (row == brow) mine = a[ri][0];
           s_lcol[buf][row] = (row == brow) ? 0.0 : a[ri][0];
         }
-        const double pv = __shfl(mine, gbase + brow % TR);
         if (tr == 0) {
           s_piv[buf] = brow;
           s_pv[buf] = pv;
@@ -99,24 +88,21 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
         }
       }
       __syncthreads();
-      const int pr = s_piv[buf];
+      const int pr = __builtin_amdgcn_readfirstlane(s_piv[buf]);  // uniform: scalar branches below
       if (tr == pr % TR) {
-        const int rip = pr / TR;
+        const int rip = pr / TR;  // uniform: one scalar branch is taken
         used |= 1u << rip;
         const double pinv = 1.0 / s_pv[buf];
 #pragma unroll
-        for (int s = 0; s < RJ; ++s) {
-          double v = 0.0;
+        for (int ri = 0; ri < RI; ++ri)
+          if (ri == rip) {
 #pragma unroll
-          for (int ri = 0; ri < RI; ++ri)
-            if (ri == rip) v = a[ri][s];
-          if (s == 0 && tc == t) v = 1.0;
-          v *= pinv;
-#pragma unroll
-          for (int ri = 0; ri < RI; ++ri)
-            if (ri == rip) a[ri][s] = v;
-          s_urow[buf][tc + TC * s] = v;
-        }
+            for (int s = 0; s < RJ; ++s) {
+              const double v = ((s == 0 && tc == t) ? 1.0 : a[ri][s]) * pinv;
+              a[ri][s] = v;
+              s_urow[buf][tc + TC * s] = v;
+            }
+          }
       }
       __syncthreads();
 #pragma unroll
@@ -192,7 +178,8 @@ int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batc
 // ---------------------------------------------------------------------------
 // blocked form
 // ---------------------------------------------------------------------------
-constexpr int PANEL_THREADS = 1024;
+constexpr int PANEL_THREADS = 512;
+constexpr int PANEL_MAX_NB = 32;
 
 // Initialize the pivot bookkeeping of a batch (pos = -1).
 __global__ void gj_init_kernel(int* pos, long long n) {
@@ -200,24 +187,25 @@ __global__ void gj_init_kernel(int* pos, long long n) {
   if (i < n) pos[i] = -1;
 }
 
+// One Gauss-Jordan panel: columns [j0, j0+nbw) of every row, rows
+// distributed cyclically over the workgroup (row = tid + 512 i), in registers.
 template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                   int* __restrict__ posall, int* __restrict__ pivall,
                                                                   double* __restrict__ Wall, double* __restrict__ snapall,
                                                                   int* __restrict__ flag) {
   constexpr int NW = PANEL_THREADS / 64;
-  __shared__ double s_cv[2][NW];
+  __shared__ double s_ck[2][NW], s_cv[2][NW];
   __shared__ int s_cr[2][NW];
   __shared__ double s_prow[2][NB];
-  __shared__ double s_pv[2];
   __shared__ int s_piv[NB];
 
   const long long b = blockIdx.x;
   double* A = Aall + b * (long long)m * m;
   int* pos = posall + b * (long long)m;
   int* piv = pivall + b * (long long)m;
-  double* W = Wall + b * (long long)m * NB;
-  double* snap = snapall + b * (long long)m * NB;
+  double* W = Wall + b * (long long)m * PANEL_MAX_NB;
+  double* snap = snapall + b * (long long)m * PANEL_MAX_NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   double a[RPT][NB];
@@ -231,69 +219,59 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
     if (row >= m || pos[row] >= 0) used |= 1u << i;
   }
 
-#pragma unroll
+  // column c of the panel sits in register slot 0 while it is the pivot
+  // column: the slots rotate left once per column (a full cycle per panel)
   for (int c = 0; c < NB; ++c) {
-    if (c >= nbw) break;
-    const int k = j0 + c;
-    const int buf = c & 1;
-    double best = -1.0;
-    int brow = 0x7fffffff;
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      double v = fabs(a[i][c]);
-      if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();  // NaN/inf rows still pivot
-      const int row = tid + PANEL_THREADS * i;
-      if (!((used >> i) & 1u) && (v > best || (v == best && row < brow))) { best = v; brow = row; }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int orow = __shfl_xor(brow, off);
-      if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-    }
-    if (lane == 0) { s_cv[buf][wave] = best; s_cr[buf][wave] = brow; }
-    __syncthreads();
-    best = s_cv[buf][0];
-    brow = s_cr[buf][0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const double ob = s_cv[buf][w];
-      const int orow = s_cr[buf][w];
-      if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-    }
-    const int pr = brow;
-    if (tid == pr % PANEL_THREADS) {
-      const int ip = pr / PANEL_THREADS;
+    if (c < nbw) {
+      const int k = j0 + c;
+      const int buf = c & 1;
+      double key = -1.0, val = 0.0;
+      int brow = 0x7fffffff;
 #pragma unroll
       for (int i = 0; i < RPT; ++i)
-        if (i == ip) {
+        if (!((used >> i) & 1u)) amax_merge(key, brow, val, pivot_key(a[i][0]), tid + PANEL_THREADS * i, a[i][0]);
+      wave_argmax(key, brow, val);
+      if (lane == 0) { s_ck[buf][wave] = key; s_cr[buf][wave] = brow; s_cv[buf][wave] = val; }
+      __syncthreads();
+      key = s_ck[buf][0]; brow = s_cr[buf][0]; val = s_cv[buf][0];
 #pragma unroll
-          for (int cc = 0; cc < NB; ++cc) s_prow[buf][cc] = a[i][cc];
-          s_pv[buf] = a[i][c];
-          used |= 1u << i;
+      for (int w = 1; w < NW; ++w) amax_merge(key, brow, val, s_ck[buf][w], s_cr[buf][w], s_cv[buf][w]);
+      const int pr = __builtin_amdgcn_readfirstlane(brow);  // uniform: scalar branches below
+      const double pv = val;
+      if (tid == pr % PANEL_THREADS) {
+        const int ip = pr / PANEL_THREADS;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == ip) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) s_prow[buf][cc] = a[i][cc];
+            used |= 1u << i;
+          }
+        pos[pr] = k;
+        piv[k] = pr;
+        s_piv[c] = pr;
+        if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
+      }
+      __syncthreads();
+      const double pinv = 1.0 / pv;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = tid + PANEL_THREADS * i;
+        const double l = a[i][0];
+        const bool isp = row == pr;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+          const double u = (cc == 0 ? 1.0 : s_prow[buf][cc]) * pinv;
+          a[i][cc] = isp ? u : ((cc == 0 ? 0.0 : a[i][cc]) - l * u);
         }
-      pos[pr] = k;
-      piv[k] = pr;
-      s_piv[c] = pr;
+      }
     }
-    __syncthreads();
-    const double pv = s_pv[buf];
-    if (tid == 0 && (!(pv != 0.0) || !isfinite(pv))) atomicOr(flag, 2);
-    const double pinv = 1.0 / pv;
-    double u[NB];
-#pragma unroll
-    for (int cc = 0; cc < NB; ++cc) u[cc] = (cc == c ? 1.0 : s_prow[buf][cc]) * pinv;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + PANEL_THREADS * i;
-      if (row == pr) {
+      const double first = a[i][0];
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc) a[i][cc] = u[cc];
-      } else {
-        const double l = a[i][c];
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) a[i][cc] = (cc == c ? 0.0 : a[i][cc]) - l * u[cc];
-      }
+      for (int cc = 0; cc + 1 < NB; ++cc) a[i][cc] = a[i][cc + 1];
+      a[i][NB - 1] = first;
     }
   }
   __syncthreads();
@@ -318,28 +296,32 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
     const int col = (int)(e / NB);
     double v = 0.0;
     if (c < nbw && (col < j0 || col >= j0 + nbw)) v = A[s_piv[c] + (long long)col * m];
-    snap[e] = v;
+    snap[c + (long long)col * PANEL_MAX_NB] = v;
   }
 }
 
 int gj_panel_width(int m) {
+  if (m <= 1024) return 32;
   if (m <= 2048) return 16;
   if (m <= 4096) return 8;
   if (m <= 8192) return 4;
   return 0;
 }
+int gj_panel_max_nb() { return PANEL_MAX_NB; }
 
 int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
                     long long batch, hipStream_t st) {
   dim3 grid((unsigned)batch), block(PANEL_THREADS);
-  if (m <= 1024)
-    hipLaunchKernelGGL((gj_panel_kernel<1, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  if (m <= 512)
+    hipLaunchKernelGGL((gj_panel_kernel<1, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+  else if (m <= 1024)
+    hipLaunchKernelGGL((gj_panel_kernel<2, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
   else if (m <= 2048)
-    hipLaunchKernelGGL((gj_panel_kernel<2, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
   else if (m <= 4096)
-    hipLaunchKernelGGL((gj_panel_kernel<4, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
   else if (m <= 8192)
-    hipLaunchKernelGGL((gj_panel_kernel<8, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
   else {
     set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
     return HPS_EUNSUPPORTED;

@@ -18,12 +18,13 @@
 // pivot is marked used, the pivot order is recorded (perm[k] = row of step k,
 // pos[row] = k), and the factors are stored with rows in their original
 // positions.  The pivot search of column k runs inside the TR lanes that own
-// the column (one wavefront, cross-lane shuffles); ties go to the lowest row.
+// the column (one wavefront, DPP lane exchanges); ties go to the lowest row.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "common.hpp"
+#include "dpp.hpp"
 #include "../../include/hps.h"
 
 namespace hps {
@@ -122,6 +123,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   const int tr = tid % TR, tc = tid / TR;
   const int lane = tid & 63;
   const int gbase = lane - tr;  // first lane of this thread's column group
+  (void)gbase;
 
   // ---- stage coefficients and 1D operators
   const double* cf = coeffs + leaf * 6 * C::NPTS;
@@ -166,26 +168,12 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       if (k >= NI) break;
       const int buf = k & 1;
       if (tc == t) {
-        double best = -1.0;
+        double key = -1.0, pv = 0.0;
         int brow = 0x7fffffff;
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri) {
-          double v = fabs(a[ri][0]);
-          if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();  // NaN/inf rows still pivot
-          const int row = tr + TR * ri;
-          if (!((used >> ri) & 1u) && (v > best || (v == best && row < brow))) { best = v; brow = row; }
-        }
-#pragma unroll
-        for (int off = TR / 2; off >= 1; off >>= 1) {
-          const double ob = __shfl_xor(best, off);
-          const int orow = __shfl_xor(brow, off);
-          if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
-        }
-        double mine = 0.0;
-#pragma unroll
         for (int ri = 0; ri < RI; ++ri)
-          if (tr + TR * ri == brow) mine = a[ri][0];
-        const double pv = __shfl(mine, gbase + brow % TR);
+          if (!((used >> ri) & 1u)) amax_merge(key, brow, pv, pivot_key(a[ri][0]), tr + TR * ri, a[ri][0]);
+        group_argmax<TR>(key, brow, pv);
         const double pinv = 1.0 / pv;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
@@ -206,19 +194,17 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         }
       }
       __syncthreads();
-      const int pr = s_piv[buf];
+      const int pr = __builtin_amdgcn_readfirstlane(s_piv[buf]);  // uniform: scalar branches below
       if (tr == pr % TR) {
-        const int rip = pr / TR;
+        const int rip = pr / TR;  // uniform: one scalar branch is taken
         used |= 1u << rip;
 #pragma unroll
-        for (int s = 0; s < RJ; ++s) {
-          if (r + s >= NBLK) break;
-          double v = 0.0;
+        for (int ri = 0; ri < RI; ++ri)
+          if (ri == rip) {
 #pragma unroll
-          for (int ri = 0; ri < RI; ++ri)
-            if (ri == rip) v = a[ri][s];
-          s_urow[buf][tc + TC * s] = v;
-        }
+            for (int s = 0; s < RJ; ++s)
+              if (r + s < NBLK) s_urow[buf][tc + TC * s] = a[ri][s];
+          }
       }
       __syncthreads();
 #pragma unroll
@@ -260,7 +246,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         a[ri][RJ - 1] = (row < NI && tc < C::AUG_LATE) ? s_aug[row + tc * NI] : 0.0;
       }
       for (int j = 0; j < TC; ++j) {
-        const int pj = s_perm[j];
+        const int pj = __builtin_amdgcn_readfirstlane(s_perm[j]);  // uniform: scalar branches below
         double mine = 0.0;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri)
@@ -297,7 +283,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       const int k = kb * TC + t;
       if (k >= NI) continue;
       const int buf = k & 1;
-      const int pr = s_perm[k];
+      const int pr = __builtin_amdgcn_readfirstlane(s_perm[k]);  // uniform: scalar branches below
       if (tc == t) {
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
@@ -307,18 +293,20 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         }
       }
       if (tr == pr % TR) {
-        const int rip = pr / TR;
+        const int rip = pr / TR;  // uniform: one scalar branch is taken
         const double dinv = 1.0 / s_diag[k];
 #pragma unroll
-        for (int s = 0; s < NLB; ++s) {
-          const int col = (RF + s) * TC + tc;
-          if (col < NI || col >= NC) continue;
-          double x = 0.0;
+        for (int ri = 0; ri < RI; ++ri)
+          if (ri == rip) {
 #pragma unroll
-          for (int ri = 0; ri < RI; ++ri)
-            if (ri == rip) { x = a[ri][s] * dinv; a[ri][s] = x; }
-          s_xrow[buf][col - NI] = x;
-        }
+            for (int s = 0; s < NLB; ++s) {
+              const int col = (RF + s) * TC + tc;
+              if (col < NI || col >= NC) continue;
+              const double x = a[ri][s] * dinv;
+              a[ri][s] = x;
+              s_xrow[buf][col - NI] = x;
+            }
+          }
       }
       __syncthreads();
 #pragma unroll

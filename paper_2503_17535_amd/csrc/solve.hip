@@ -19,46 +19,44 @@
 
 namespace hps {
 
-constexpr int BC_COLS = 8;  // columns per workgroup of block_copy
+constexpr int BC_THREADS = 256;
 
-__global__ void block_copy_kernel(const BlockOp* __restrict__ ops, int nops, int ncols_rt, double* __restrict__ dst,
-                                  long long dst_stride, const double* __restrict__ src0, long long s0_stride,
-                                  const double* __restrict__ src1, long long s1_stride) {
-  const int opi = blockIdx.x % nops;
-  const int chunk = blockIdx.x / nops;
+__global__ __launch_bounds__(BC_THREADS) void block_copy_kernel(const BlockOp* __restrict__ ops,
+                                                                const CopyItem* __restrict__ items,
+                                                                const CopyTask* __restrict__ tasks, int ncols_rt,
+                                                                double* __restrict__ dst, long long dst_stride,
+                                                                const double* __restrict__ src0, long long s0_stride,
+                                                                const double* __restrict__ src1, long long s1_stride) {
+  const CopyTask task = tasks[blockIdx.x];
   const long long b = blockIdx.y;
-  const BlockOp op = ops[opi];
-  const int cols = op.cols > 0 ? op.cols : ncols_rt;
-  const int c0 = chunk * BC_COLS;
-  if (c0 >= cols) return;
-  const int c1 = min(cols, c0 + BC_COLS);
-  double* D = dst + b * dst_stride + op.dst_off;
-  const double* S[2] = {nullptr, nullptr};
-  for (int s = 0; s < op.nsrc; ++s) {
-    const double* base = op.src_buf[s] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride;
-    S[s] = base + op.src_off[s];
-  }
-  const int rows = op.rows;
-  for (int c = c0; c < c1; ++c) {
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+  for (int it = task.begin; it < task.end; ++it) {
+    const CopyItem item = items[it];
+    const BlockOp op = ops[item.op];
+    const int c0 = item.c0, c1 = item.c1 < 0 ? ncols_rt : item.c1;
+    double* D = dst + b * dst_stride + op.dst_off;
+    const double* S0 = nullptr;
+    const double* S1 = nullptr;
+    if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
+    if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
+    const int rows = op.rows;
+    const int n = rows * (c1 - c0);
+    for (int e = threadIdx.x; e < n; e += BC_THREADS) {
+      const int r = e % rows, c = c0 + e / rows;
       double v = 0.0;
-      if (op.nsrc > 0) v = S[0][r + (long long)c * op.src_ld[0]];
-      if (op.nsrc > 1) v += S[1][r + (long long)c * op.src_ld[1]];
+      if (S0) v = S0[r + (long long)c * op.src_ld[0]];
+      if (S1) v += S1[r + (long long)c * op.src_ld[1]];
       D[r + (long long)c * op.dst_ld] = v;
     }
   }
 }
 
-int block_copy_launch(const BlockOp* dev_ops, int nops, int max_cols, int ncols_rt, double* dst, long long dst_stride,
-                      const double* src0, long long s0_stride, const double* src1, long long s1_stride,
-                      long long batch, int max_rows, hipStream_t st) {
-  if (nops <= 0 || batch <= 0) return HPS_OK;
-  const int cols = max_cols > 0 ? max_cols : ncols_rt;
-  const int nch = (cols + BC_COLS - 1) / BC_COLS;
-  const int threads = max_rows >= 256 ? 256 : (max_rows >= 128 ? 128 : 64);
-  dim3 grid((unsigned)(nops * nch), (unsigned)batch);
-  hipLaunchKernelGGL(block_copy_kernel, grid, dim3(threads), 0, st, dev_ops, nops, ncols_rt, dst, dst_stride, src0,
-                     s0_stride, src1, s1_stride);
+int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
+                      int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
+                      const double* src1, long long s1_stride, long long batch, hipStream_t st) {
+  if (ntasks <= 0 || batch <= 0) return HPS_OK;
+  dim3 grid((unsigned)ntasks, (unsigned)batch);
+  hipLaunchKernelGGL(block_copy_kernel, grid, dim3(BC_THREADS), 0, st, dev_ops, dev_items, dev_tasks, ncols_rt, dst,
+                     dst_stride, src0, s0_stride, src1, s1_stride);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
@@ -108,7 +106,7 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
   // forward: y_s = b[perm[s]];  b[r] -= L(r, s) y_s for pos[r] > s
   for (int s = 0; s < NI; ++s) {
     const int buf = s & 1;
-    const int pr = s_perm[s];
+    const int pr = __builtin_amdgcn_readfirstlane(s_perm[s]);  // uniform: scalar branches below
     if (tid == pr % SRC_THREADS) {
       const int ip = pr / SRC_THREADS;
 #pragma unroll
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
   // backward: x_s = b[perm[s]] / U(s, s);  b[r] -= U(pos[r], s) x_s for pos[r] < s
   for (int s = NI - 1; s >= 0; --s) {
     const int buf = s & 1;
-    const int pr = s_perm[s];
+    const int pr = __builtin_amdgcn_readfirstlane(s_perm[s]);  // uniform: scalar branches below
     if (tid == pr % SRC_THREADS) {
       const int ip = pr / SRC_THREADS;
       const double dinv = 1.0 / LU[pr + (long long)s * NI];

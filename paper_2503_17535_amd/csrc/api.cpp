@@ -43,6 +43,10 @@ int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, doubl
 int gj_init_launch(int* pos, long long n, hipStream_t st);
 int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
                          hipStream_t st);
+int leaf3d_assemble_launch(const double* coeffs, const double* D1, const double* D2, const double* Mt, int p,
+                           double* Lii, double* R, long long nl, hipStream_t st);
+int leaf_gather_int_launch(const double* src, const int* Ii, int ni, int npts, long long nl, int nrhs, int NRcap,
+                           double* fint, hipStream_t st);
 int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
                       int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
                       const double* src1, long long s1_stride, long long batch, hipStream_t st);
@@ -144,22 +148,22 @@ int get_consts(int d, int p, double r, DevConsts** out) {
   std::vector<double> QeP((size_t)n_b * n_b, 0.0), Pc((size_t)n_e * n_b);
   for (int e = 0; e < n_e; ++e)
     for (int b = 0; b < n_b; ++b) Pc[e + (size_t)b * n_e] = o.P[(size_t)e * n_b + b];
-  for (int a = 0; a < n_b; ++a)
-    for (int b = 0; b < n_b; ++b) {
-      double s = 0.0;
-      for (int e = 0; e < n_e; ++e) s += Qe[a + (size_t)e * n_b] * Pc[e + (size_t)b * n_e];
-      QeP[a + (size_t)b * n_b] = s;
+  for (int e = 0; e < n_e; ++e)
+    for (int a = 0; a < n_b; ++a) {
+      const double qa = Qe[a + (size_t)e * n_b];
+      if (qa == 0.0) continue;
+      for (int b = 0; b < n_b; ++b) QeP[a + (size_t)b * n_b] += qa * Pc[e + (size_t)b * n_e];
     }
   // M_t = D_t(I_i, I_e) P for every term, column-major n_i x n_b
   const int nt = n_terms(d);
   std::vector<double> Mt((size_t)nt * n_i * n_b, 0.0), blk;
   for (int t = 0; t < nt; ++t) {
-    term_block(o, t, r, o.Ii, o.Ie, blk);  // n_i x n_e row-major
+    term_block(o, t, r, o.Ii, o.Ie, blk);  // n_i x n_e row-major, mostly zero (stencil)
     for (int i = 0; i < n_i; ++i)
-      for (int b = 0; b < n_b; ++b) {
-        double s = 0.0;
-        for (int e = 0; e < n_e; ++e) s += blk[(size_t)i * n_e + e] * Pc[e + (size_t)b * n_e];
-        Mt[(size_t)t * n_i * n_b + i + (size_t)b * n_i] = s;
+      for (int e = 0; e < n_e; ++e) {
+        const double l = blk[(size_t)i * n_e + e];
+        if (l == 0.0) continue;
+        for (int b = 0; b < n_b; ++b) Mt[(size_t)t * n_i * n_b + i + (size_t)b * n_i] += l * Pc[e + (size_t)b * n_e];
       }
   }
   HPS_TRY(upload(&c.D1, D1));
@@ -184,17 +188,25 @@ struct CopyCall {
   int first_task = 0, ntasks = 0;
 };
 
+// Batched inversion of m x m matrices held in `A` (overwritten) into `Z`.
+struct GJPlan {
+  int m = 0;
+  long long batch = 0;
+  double *A = nullptr, *Z = nullptr;
+  bool small = true;
+  int nb = 0;
+  int *pos = nullptr, *piv = nullptr;
+  double *W = nullptr, *snap = nullptr;
+  std::vector<GemmCall> upd;
+};
+
 struct LevelPlan {
   int lev = 0;
   long long nm = 0;
   int n = 0, m = 0, nbc = 0, nbp = 0, dn = 0;
   double *Z = nullptr, *S = nullptr, *Bnz = nullptr, *Tp = nullptr, *Dbuf = nullptr;
-  int *gj_pos = nullptr, *gj_piv = nullptr;
-  double *gj_W = nullptr, *gj_snap = nullptr;
-  int gj_nb = 0;
-  bool small = true;
+  GJPlan gj;
   CopyCall copyD, fillT, copyB;
-  std::vector<GemmCall> gj_upd;
   GemmCall gemmS, gemmT;
   // solve
   double *hint = nullptr, *gt = nullptr, *gint = nullptr;
@@ -224,6 +236,11 @@ struct hps_op {
   hps::DevConsts* cst = nullptr;
   hipStream_t stream = nullptr;
   double *LU = nullptr, *Y = nullptr, *Tleaf = nullptr;
+  // 3D leaves: LU holds L_ii^{-1}; Lbuf / Rbuf are build workspace, fint the
+  // gathered interior sources
+  double *Lbuf = nullptr, *Rbuf = nullptr, *fint = nullptr;
+  hps::GJPlan leaf_gj;
+  hps::GemmCall gemmYleaf, gemmVleaf;
   int *perm = nullptr, *pos = nullptr, *flag = nullptr;
   std::vector<hps::LevelPlan> levels;  // index = tree level of the parents
   std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
@@ -368,6 +385,58 @@ void clear_stages(hps_op* op) {
 }
 
 // ---------------------------------------------------------------------------
+// batched Gauss-Jordan inversion: register form for m <= 224, blocked above
+// ---------------------------------------------------------------------------
+int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch) {
+  g->m = m;
+  g->batch = batch;
+  g->A = A;
+  g->Z = Z;
+  g->small = m <= gj_small_max();
+  if (g->small) return HPS_OK;
+  g->nb = gj_panel_width(m);
+  if (g->nb == 0) {
+    set_error("matrix of size " + std::to_string(m) + " exceeds the blocked Gauss-Jordan limit (8192)");
+    return HPS_EUNSUPPORTED;
+  }
+  const int mnb = gj_panel_max_nb();
+  g->pos = (int*)op_alloc(op, sizeof(int) * batch * m, false);
+  g->piv = (int*)op_alloc(op, sizeof(int) * batch * m, false);
+  g->W = (double*)op_alloc(op, sizeof(double) * batch * m * mnb, false);
+  g->snap = (double*)op_alloc(op, sizeof(double) * batch * m * mnb, false);
+  if (!g->pos || !g->piv || !g->W || !g->snap) {
+    set_error("device allocation failed (Gauss-Jordan workspace)");
+    return HPS_ENOMEM;
+  }
+  const long long sw = (long long)m * mnb;  // W: m x mnb (ld m); snapshot: mnb x m (ld mnb)
+  const long long sm = (long long)m * m;
+  for (int j0 = 0; j0 < m; j0 += g->nb) {
+    const int w = std::min(g->nb, m - j0);
+    std::vector<GemmGroup> gs;
+    if (j0 > 0) gs.push_back(make_group(g->W, sw, m, g->snap, sw, mnb, A, sm, m, m, j0, w, 1.0, 1.0, batch, A, sm, m));
+    if (j0 + w < m)
+      gs.push_back(make_group(g->W, sw, m, g->snap + (long long)(j0 + w) * mnb, sw, mnb, A + (long long)(j0 + w) * m,
+                              sm, m, m, m - j0 - w, w, 1.0, 1.0, batch, A + (long long)(j0 + w) * m, sm, m));
+    GemmCall c;
+    add_gemm(op, gs, &c);
+    g->upd.push_back(c);
+  }
+  return HPS_OK;
+}
+
+int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
+  if (g.small) return gj_small_launch(g.A, g.Z, g.m, op->flag, g.batch, st);
+  HPS_TRY(gj_init_launch(g.pos, g.batch * g.m, st));
+  int step = 0;
+  for (int j0 = 0; j0 < g.m; j0 += g.nb, ++step) {
+    const int w = std::min(g.nb, g.m - j0);
+    HPS_TRY(gj_panel_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W, g.snap, op->flag, g.batch, st));
+    HPS_TRY(run_gemm(op, g.upd[step], st));
+  }
+  return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
+}
+
+// ---------------------------------------------------------------------------
 // plan: allocations + every descriptor table
 // ---------------------------------------------------------------------------
 int plan_op(hps_op* op) {
@@ -380,6 +449,17 @@ int plan_op(hps_op* op) {
   op->Y = (double*)op_alloc(op, sizeof(double) * nl * ni * nb);
   op->perm = (int*)op_alloc(op, sizeof(int) * nl * ni);
   op->pos = (int*)op_alloc(op, sizeof(int) * nl * ni);
+  if (d == 3) {
+    op->Lbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * ni, false);
+    op->Rbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * nb, false);
+    op->fint = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
+    if (!op->Lbuf || !op->Rbuf || !op->fint) { set_error("device allocation failed (3D leaf workspace)"); return HPS_ENOMEM; }
+    HPS_TRY(plan_gj(op, &op->leaf_gj, op->Lbuf, op->LU, ni, nl));
+    // Y_int = -L_ii^{-1} (L_ie P);  v = L_ii^{-1} f_int
+    add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->Rbuf, (long long)ni * nb, ni, op->Y,
+                             (long long)ni * nb, ni, ni, nb, ni, -1.0, 0.0, nl)},
+             &op->gemmYleaf);
+  }
   op->Tleaf = (double*)op_alloc(op, sizeof(double) * nl * nb * nb, false);
   op->flag = (int*)op_alloc(op, sizeof(int) * 4, false);
   if (!op->LU || !op->Y || !op->perm || !op->pos || !op->Tleaf || !op->flag) {
@@ -400,6 +480,10 @@ int plan_op(hps_op* op) {
   }
   op->v = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
   if (!op->v) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+  if (d == 3)
+    add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->fint, (long long)NR * ni, ni, op->v, (long long)NR * ni,
+                             ni, ni, NR, ni, 1.0, 0.0, nl)},
+             &op->gemmVleaf);
 
   // leaf T = Q_e P + Q_i Y_int
   add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->Y, (long long)ni * nb, ni, op->Tleaf, (long long)nb * nb, nb, nb,
@@ -443,38 +527,7 @@ int plan_op(hps_op* op) {
       set_error("device allocation failed (merge level)");
       return HPS_ENOMEM;
     }
-    P.small = m <= gj_small_max();
-    if (!P.small) {
-      P.gj_nb = gj_panel_width(m);
-      if (P.gj_nb == 0) {
-        set_error("merge matrix D of size " + std::to_string(m) + " exceeds the blocked Gauss-Jordan limit");
-        return HPS_EUNSUPPORTED;
-      }
-      P.gj_pos = (int*)op_alloc(op, sizeof(int) * nm * m, false);
-      P.gj_piv = (int*)op_alloc(op, sizeof(int) * nm * m, false);
-      const int mnb = gj_panel_max_nb();
-      P.gj_W = (double*)op_alloc(op, sizeof(double) * nm * m * mnb, false);
-      P.gj_snap = (double*)op_alloc(op, sizeof(double) * nm * m * mnb, false);
-      if (!P.gj_pos || !P.gj_piv || !P.gj_W || !P.gj_snap) {
-        set_error("device allocation failed (Gauss-Jordan workspace)");
-        return HPS_ENOMEM;
-      }
-      for (int j0 = 0; j0 < m; j0 += P.gj_nb) {
-        const int w = std::min(P.gj_nb, m - j0);
-        std::vector<GemmGroup> gs;
-        const long long sw = (long long)m * mnb;  // W: m x mnb (ld m); snapshot: mnb x m (ld mnb)
-        if (j0 > 0)
-          gs.push_back(make_group(P.gj_W, sw, m, P.gj_snap, sw, mnb, P.Dbuf, (long long)m * m, m, m, j0, w, 1.0, 1.0,
-                                  nm, P.Dbuf, (long long)m * m, m));
-        if (j0 + w < m)
-          gs.push_back(make_group(P.gj_W, sw, m, P.gj_snap + (long long)(j0 + w) * mnb, sw, mnb,
-                                  P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m, m, m - j0 - w, w, 1.0, 1.0, nm,
-                                  P.Dbuf + (long long)(j0 + w) * m, (long long)m * m, m));
-        GemmCall c;
-        add_gemm(op, gs, &c);
-        P.gj_upd.push_back(c);
-      }
-    }
+    HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));
     // --- D = sum over children touching interfaces i and j of T_c(face_i, face_j)
     {
       std::vector<BlockOp> ops;
@@ -633,8 +686,10 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
     HPS_TRY(leaf2d_launch(op->p, coeffs, op->cst->D1, op->cst->D2, op->cst->Mt, op->LU, op->perm, op->pos, op->Y,
                           op->flag, op->nl, st));
   } else {
-    set_error("3D leaf stage not available in this build");
-    return HPS_EUNSUPPORTED;
+    HPS_TRY(leaf3d_assemble_launch(coeffs, op->cst->D1, op->cst->D2, op->cst->Mt, op->p, op->Lbuf, op->Rbuf, op->nl,
+                                   st));
+    HPS_TRY(run_gj(op, op->leaf_gj, st));
+    HPS_TRY(run_gemm(op, op->gemmYleaf, st));
   }
   stage_end(op, st);
   stage_begin(op, "leaf_T", st);
@@ -648,18 +703,7 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
     const long long childstride = (long long)nd * P.nbc * P.nbc;
     stage_begin(op, names[lev < 12 ? lev : 11], st);
     HPS_TRY(run_copy(op, P.copyD, 0, P.Dbuf, (long long)P.m * P.m, Tchild, childstride, nullptr, 0, P.nm, st));
-    if (P.small) {
-      HPS_TRY(gj_small_launch(P.Dbuf, P.Z, P.m, op->flag, P.nm, st));
-    } else {
-      HPS_TRY(gj_init_launch(P.gj_pos, P.nm * P.m, st));
-      int step = 0;
-      for (int j0 = 0; j0 < P.m; j0 += P.gj_nb, ++step) {
-        const int w = std::min(P.gj_nb, P.m - j0);
-        HPS_TRY(gj_panel_launch(P.Dbuf, P.m, j0, w, P.gj_pos, P.gj_piv, P.gj_W, P.gj_snap, op->flag, P.nm, st));
-        HPS_TRY(run_gemm(op, P.gj_upd[step], st));
-      }
-      HPS_TRY(gj_unscramble_launch(P.Dbuf, P.Z, P.m, P.gj_pos, P.gj_piv, P.nm, st));
-    }
+    HPS_TRY(run_gj(op, P.gj, st));
     HPS_TRY(run_gemm(op, P.gemmS, st));
     HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)nd * P.dn * P.dn, Tchild, childstride, nullptr, 0, P.nm, st));
     if (P.Tp) {
@@ -677,7 +721,13 @@ int run_solve_chunk(hps_op* op, const double* bdry, const double* src, double* u
   // root data
   HPS_TRY(run_copy(op, op->copyRoot, nrhs, op->g[0], 0, bdry, 0, nullptr, 0, 1, st));
   if (src) {
-    HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, op->v, NR, st));
+    if (op->d == 2) {
+      HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, op->v, NR,
+                              st));
+    } else {
+      HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, op->fint, st));
+      HPS_TRY(run_gemm(op, op->gemmVleaf, st, nrhs));
+    }
     HPS_TRY(run_gemm(op, op->gemmHleaf, st, nrhs));
     for (int lev = L - 1; lev >= 0; --lev) {
       LevelPlan& P = op->levels[lev];

@@ -247,6 +247,13 @@ int leaf_out_launch(const double* Y, const double* P, const double* g, const dou
     return HPS_EINVAL;
   }
   const size_t shm = (size_t)NB * OUT_MAXR * sizeof(double);
+  if (shm > 65536) {
+    if (shm > 160 * 1024) {
+      set_error("leaf_out: boundary too large for LDS staging");
+      return HPS_EUNSUPPORTED;
+    }
+    HPS_HIP_TRY(hipFuncSetAttribute((const void*)leaf_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  }
   hipLaunchKernelGGL(leaf_out_kernel, dim3((unsigned)nl), dim3(OUT_THREADS), shm, st, Y, P, g, v, Ii, Ie, NI, NE, NB,
                      npts, nl, nrhs, NRcap, u);
   HPS_HIP_TRY(hipGetLastError());

@@ -20,6 +20,7 @@ boundary values) on every distinct leaf face ("panel").  Equations:
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sps
 
 from .hps import FACES, LeafDisc, Tree, leaf_operator
 
@@ -30,8 +31,9 @@ def _panel_key(tree: Tree, i: int, f: int):
     return (axis, int(cell[axis] + side)) + tuple(int(cell[t]) for t in tang)
 
 
-def assemble(tree: Tree, p: int, coeffs: np.ndarray):
-    """Returns (K, layout) with K the square system matrix."""
+def assemble(tree: Tree, p: int, coeffs: np.ndarray, sparse: bool = False):
+    """Returns (K, layout) with K the square system matrix (a dense array, or
+    a scipy CSC matrix when ``sparse``; the entries are the same)."""
     d = tree.d
     disc = LeafDisc(d, p)
     ops = disc.term_ops(tree.leaf_r)
@@ -49,34 +51,49 @@ def assemble(tree: Tree, p: int, coeffs: np.ndarray):
             owners[key].append((i, f))
     n_u = tree.n_leaves * npts
     n_unk = n_u + len(panels) * nf
-    K = np.zeros((n_unk, n_unk))
+    # every entry of K is written by exactly one of the blocks below
+    blocks = []          # (row indices, column indices, dense block)
+
+    def put(r0, nr, cols, blk):
+        blocks.append((np.arange(r0, r0 + nr), np.asarray(cols), np.asarray(blk, dtype=float)))
+
     row = 0
     for i in range(tree.n_leaves):
         L = leaf_operator(disc, ops, coeffs[i])
-        cu = slice(i * npts, (i + 1) * npts)
+        cu = np.arange(i * npts, (i + 1) * npts)
         # E1
-        K[row:row + disc.n_i, cu] = L[disc.Ii]
+        put(row, disc.n_i, cu, L[disc.Ii])
         row += disc.n_i
         # E2
-        for k, e in enumerate(disc.Ie):
-            K[row + k, i * npts + e] = 1.0
+        put(row, disc.n_e, i * npts + np.asarray(disc.Ie), np.eye(disc.n_e))
         for f in range(2 * d):
             pc = n_u + panels[_panel_key(tree, i, f)] * nf
-            K[row:row + disc.n_e, pc:pc + nf] -= disc.P[:, f * nf:(f + 1) * nf]
+            put(row, disc.n_e, np.arange(pc, pc + nf), -disc.P[:, f * nf:(f + 1) * nf])
         row += disc.n_e
     bnd_rows = {}
     for key, own in owners.items():
         pc = n_u + panels[key] * nf
         if len(own) == 2:              # E3
             for (i, f) in own:
-                K[row:row + nf, i * npts:(i + 1) * npts] += Qr[f * nf:(f + 1) * nf]
+                put(row, nf, np.arange(i * npts, (i + 1) * npts), Qr[f * nf:(f + 1) * nf])
         else:                          # gamma = g
-            K[row:row + nf, pc:pc + nf] = np.eye(nf)
+            put(row, nf, np.arange(pc, pc + nf), np.eye(nf))
             bnd_rows[key] = row
         row += nf
     assert row == n_unk
-    return K, dict(panels=panels, owners=owners, bnd_rows=bnd_rows, disc=disc,
-                   n_u=n_u, nf=nf, npts=npts)
+    layout = dict(panels=panels, owners=owners, bnd_rows=bnd_rows, disc=disc,
+                  n_u=n_u, nf=nf, npts=npts)
+    if sparse:
+        rr = np.concatenate([np.repeat(r, len(c)) for r, c, _ in blocks])
+        cc = np.concatenate([np.tile(c, len(r)) for r, c, _ in blocks])
+        vv = np.concatenate([b.ravel() for _, _, b in blocks])
+        keep = vv != 0.0
+        K = sps.csc_matrix((vv[keep], (rr[keep], cc[keep])), shape=(n_unk, n_unk))
+        return K, layout
+    K = np.zeros((n_unk, n_unk))
+    for r, c, b in blocks:
+        K[np.ix_(r, c)] = b
+    return K, layout
 
 
 def _panel_points(tree: Tree, disc: LeafDisc, i: int, f: int):

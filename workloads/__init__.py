@@ -263,3 +263,26 @@ def helmholtz_inputs(leaf_pts: np.ndarray, bdry_pts: np.ndarray, k: float,
         bdry[r] = eval_fourier(draw_fourier(gr), bdry_pts)
         src[r] = eval_bumps(draw_source_bump(gr), leaf_pts, width=0.1)
     return coeffs, bdry, src
+
+
+def differentiation_inputs(leaf_pts: np.ndarray, bdry_pts: np.ndarray, k: float = 20.0,
+                           nfields: int = 32, nobs: int = 256, config: int = 5):
+    """Misfit-gradient workload: ``nfields`` seeded scattering potentials q
+    (8 bumps each, as the Helmholtz workload), a separately seeded q* whose
+    solution supplies the observations, ``nobs`` observation points
+    ~ U([-0.9, 0.9]^2), and one right-hand side (Fourier boundary data + one
+    source bump).
+
+    Returns dict(q [nfields, nl, np], q_star [nl, np], x_obs [nobs, 2],
+    bdry [1, nb], src [1, nl, np], k)."""
+    q = np.empty((nfields,) + leaf_pts.shape[:-1])
+    for f in range(nfields):
+        qp = draw_bumps(rng(config, 200 + f), nbumps=8, amp=(0.0, 0.5), box=0.75, dim=2)
+        q[f] = eval_bumps(qp, leaf_pts, width=0.1)
+    qs = draw_bumps(rng(config, 199), nbumps=8, amp=(0.0, 0.5), box=0.75, dim=2)
+    x_obs = rng(config, 198).uniform(-0.9, 0.9, size=(nobs, 2))
+    gr = rng(config, 1000)
+    bdry = eval_fourier(draw_fourier(gr), bdry_pts)[None]
+    src = eval_bumps(draw_source_bump(gr), leaf_pts, width=0.1)[None]
+    return dict(q=q, q_star=eval_bumps(qs, leaf_pts, width=0.1), x_obs=x_obs,
+                bdry=bdry, src=src, k=float(k))

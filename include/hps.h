@@ -118,13 +118,86 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
 int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u,
               int nrhs, int precision, void* stream);
 
-/* Adjoint (transposed) solve: for w dev [nrhs][n_leaves][p^dim] returns the
- * source-space adjoint lam_src dev [nrhs][n_leaves][p^dim] (zero at leaf
- * boundary points) and the boundary-space adjoint lam_bdry dev
- * [nrhs][n_root_bdry] (may be NULL), i.e. G^T w for the linear map
- * G: (f, g) -> u of hps_solve.  Asynchronous like hps_solve. */
+/* Mixed-precision solve (precision HPS_FP32_REFINED; operator built with
+ * HPS_FLAG_FP32_COPY, 2D).  The stored operators are copied to fp32 at build
+ * time (leaf LU and Y, merge D^{-1}, S and B's nonzero blocks); the solution
+ * is refined in fp64 on the composite collocation system that HPS eliminates
+ * (collocation rows at interior leaf points, boundary bordering, flux balance
+ * on shared panels; Section 3): each sweep computes the fp64 residual from
+ * the coefficients and applies an fp32 HPS solve to it.  The factorizations
+ * themselves are never redone in fp32.  Sets the number of correction sweeps
+ * used by later refined solves of `op` (sweeps == 0 only queries); returns
+ * the previous value, or a negative error code. */
+int hps_refine_sweeps(hps_op_t* op, int sweeps);
+
+/* Adjoint (transposed) solve.  The solve is linear in its data,
+ * u = G_f f + G_g g; this returns lam_src = G_f^T w and lam_bdry = G_g^T w by
+ * running the stored leaf and merge operators of the build transposed, in
+ * reverse order (the transposes of the downward pass and of the upward source
+ * pass of Section 3; derivative rules for the solver are the future work of
+ * Section 6).  No factorization is redone.
+ *   w         dev [nrhs][n_leaves][p^dim]   weight, laid out like u
+ *   lam_src   dev [nrhs][n_leaves][p^dim]   output; zero at leaf boundary points
+ *                                           (the source is not read there)
+ *   lam_bdry  dev [nrhs][n_root_bdry]       output, or NULL if not wanted
+ * Asynchronous on `stream`, like hps_solve. */
 int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src,
                       double* lam_bdry, int nrhs, void* stream);
+
+/* Gradient with respect to the coefficient fields.  Only the collocation rows
+ * at interior leaf points contain the coefficients (boundary bordering
+ * replaces the others, Section 2), so for a scalar J(u) with lam = adjoint of
+ * grad_u J:
+ *   grad[leaf][t][pt] = - sum_r lam[r][leaf][pt] * (d_t u_r)(pt)   at interior pts,
+ *                       0                                           at boundary pts,
+ * with d_t the leaf's spectral derivative of term t.
+ *   u     dev [nrhs][n_leaves][p^dim]   the solution (from hps_solve)
+ *   lam   dev [nrhs][n_leaves][p^dim]   lam_src of hps_solve_adjoint
+ *   grad  dev [n_leaves][n_terms][p^dim] output (overwritten)
+ * Asynchronous on `stream`. */
+int hps_coeff_grad(hps_op_t* op, const double* u, const double* lam, int nrhs,
+                   double* grad, void* stream);
+
+/* Interpolation of a leaf-point field at scattered points (host only): the
+ * solution on a leaf is its tensor Chebyshev interpolant (Section 2).  For
+ * each point x[m] (host [m][dim]) returns the containing leaf leaf[m] (on a
+ * shared edge or face, the lowest leaf index) and the barycentric weights
+ * w[m][p^dim] with u(x[m]) = sum_k w[m][k] u[leaf[m]][k].  Points outside the
+ * domain give HPS_EINVAL. */
+int hps_interp_weights(const hps_tree_t* tree, int p, const double* x, long long m,
+                       long long* leaf, double* w);
+
+/* Batched solve over several resident operators (continuous-batching
+ * serving).  The solves of all items run as one sequence of launches in
+ * which every launch covers the same pass stage of every item (the source
+ * up-pass of Section 3 aligned at the leaves, the downward pass aligned at
+ * the root), so a batch costs a fixed number of launches (5 L_max + 4)
+ * whatever the number of operators and right-hand sides.  Each item is one
+ * operator with 1..16 right-hand sides given as separate device vectors:
+ *   bdry[j]  dev [n_root_bdry]            Dirichlet data of rhs j
+ *   src[j]   dev [n_leaves][p^2]           source of rhs j, or NULL for f = 0
+ *   u[j]     dev [n_leaves][p^2]           output of rhs j
+ * Results equal those of hps_solve on the same data (the arithmetic of every
+ * output entry is the same).  2D operators only; an operator may appear at
+ * most once per batch, and must not be used by another solve on another
+ * stream until this batch has completed (the batch uses the operator's solve
+ * workspace).  The batcher owns two pinned host / device descriptor blocks
+ * and alternates them: the host packs batch n+1 while the device runs batch
+ * n, and waits only when it comes back to a block still in use.  Asynchronous
+ * on `stream`. */
+typedef struct hps_batcher hps_batcher_t;
+
+typedef struct {
+  hps_op_t* op;
+  int nrhs;
+  const double* bdry[16];
+  const double* src[16];
+  double* u[16];
+} hps_batch_item_t;
+
+int hps_batcher_create(hps_batcher_t** out);
+int hps_solve_batch(hps_batcher_t* batcher, const hps_batch_item_t* items, int nitems, void* stream);
+void hps_batcher_free(hps_batcher_t* batcher);
 
 /* Per-stage device times (ms) of the last build/solve queued with
  * HPS_FLAG_TIMING: names[i] (static strings) and ms[i], up to cap entries.
@@ -158,6 +231,12 @@ long long hps_debug_download(const hps_op_t* op, int which, int level, double* o
 int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, int trans_a,
                    const double* b, int ldb, int trans_b, double beta, double* c, int ldc,
                    void* stream);
+
+/* The same GEMM kernel with fp32 operands and fp32 accumulation (the
+ * mixed-precision solve's products), for tests. */
+int hps_debug_gemm_f32(int m, int n, int k, float alpha, const float* a, int lda, int trans_a,
+                       const float* b, int ldb, int trans_b, float beta, float* c, int ldc,
+                       void* stream);
 
 /* Host precompute inspection, for tests (no device work).  which:
  *   0 Chebyshev nodes (p), 1 Gauss nodes (q), 2 Gauss weights (q),

@@ -24,7 +24,9 @@ FP64, FP32_REFINED = 0, 1
 EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footprint",
            "hps_build", "hps_solve", "hps_solve_adjoint", "hps_stage_times",
            "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
-           "hps_debug_download", "hps_debug_gemm")
+           "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
+           "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
+           "hps_debug_gemm_f32")
 
 
 class HPSError(RuntimeError):
@@ -43,6 +45,12 @@ class Sizes(ctypes.Structure):
                 ("n_terms", ctypes.c_int), ("n_root_bdry", ctypes.c_longlong),
                 ("n_interior", ctypes.c_int), ("n_leaf_bdry", ctypes.c_int),
                 ("n_levels", ctypes.c_int), ("root_D", ctypes.c_longlong)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("nrhs", ctypes.c_int),
+                ("bdry", ctypes.c_void_p * 16), ("src", ctypes.c_void_p * 16),
+                ("u", ctypes.c_void_p * 16)]
 
 
 _lib = None
@@ -75,10 +83,21 @@ def lib():
         L.hps_debug_download.argtypes = [P, I, I, P, LL]
         L.hps_debug_download.restype = LL
         L.hps_debug_gemm.argtypes = [I, I, I, D, P, I, I, P, I, I, D, P, I, P]
+        L.hps_coeff_grad.argtypes = [P, P, P, I, P, P]
+        L.hps_interp_weights.argtypes = [TP, I, P, LL, P, P]
+        L.hps_refine_sweeps.argtypes = [P, I]
+        F = ctypes.c_float
+        L.hps_debug_gemm_f32.argtypes = [I, I, I, F, P, I, I, P, I, I, F, P, I, P]
+        L.hps_batcher_create.argtypes = [ctypes.POINTER(P)]
+        L.hps_solve_batch.argtypes = [P, ctypes.POINTER(BatchItem), I, P]
+        L.hps_batcher_free.argtypes = [P]
+        L.hps_batcher_free.restype = None
         L.hps_precompute_matrix.argtypes = [I, I, I, P, LL, ctypes.POINTER(I), ctypes.POINTER(I)]
         for name in EXPORTS:
-            if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error",
-                            "hps_debug_download", "hps_debug_gemm"):
+            if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error", "hps_batcher_free",
+                            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
+           "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
+           "hps_debug_gemm_f32"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -123,6 +142,18 @@ def precompute_matrix(dim: int, p: int, which: int) -> np.ndarray:
     r, c = ctypes.c_int(), ctypes.c_int()
     _check(lib().hps_precompute_matrix(dim, p, which, buf.ctypes.data, cap, ctypes.byref(r), ctypes.byref(c)))
     return buf[: r.value * c.value].reshape(r.value, c.value).copy()
+
+
+def interp_weights(t: Tree, p: int, x) -> tuple[np.ndarray, np.ndarray]:
+    """Containing leaf [m] and barycentric weights [m, p^dim] of the points
+    x [m, dim] (see hps_interp_weights)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    m = x.shape[0]
+    s = sizes(t, p)
+    leaf = np.empty(m, dtype=np.int64)
+    w = np.empty((m, s.pts_per_leaf))
+    _check(lib().hps_interp_weights(ctypes.byref(t), p, x.ctypes.data, m, leaf.ctypes.data, w.ctypes.data))
+    return leaf, w
 
 
 def _stream_ptr(stream):
@@ -179,6 +210,28 @@ class Operator:
         _check(lib().hps_solve_adjoint(self._h, wptr, lptr, bptr, nrhs, _stream_ptr(stream)))
         return lam_src, lam_bdry
 
+    def refine_sweeps(self, sweeps: int = 0) -> int:
+        """Set the number of fp64 refinement sweeps of FP32_REFINED solves
+        (0 only queries); returns the previous value."""
+        rc = lib().hps_refine_sweeps(self._h, sweeps)
+        if rc < 0:
+            _check(-rc)
+        return rc
+
+    def coeff_grad(self, u, lam, out=None, stream=None):
+        """dJ/dc [n_leaves, n_terms, p^dim] from u and lam_src (both
+        [nrhs, n_leaves, p^dim]), summed over the right-hand sides."""
+        import torch
+        s = self.sizes
+        nrhs = u.shape[0]
+        uptr = _dev_ptr(u, "u", (nrhs, s.n_leaves, s.pts_per_leaf))
+        lptr = _dev_ptr(lam, "lam", (nrhs, s.n_leaves, s.pts_per_leaf))
+        if out is None:
+            out = torch.empty((s.n_leaves, s.n_terms, s.pts_per_leaf), dtype=torch.float64, device=u.device)
+        gptr = _dev_ptr(out, "grad", (s.n_leaves, s.n_terms, s.pts_per_leaf))
+        _check(lib().hps_coeff_grad(self._h, uptr, lptr, nrhs, gptr, _stream_ptr(stream)))
+        return out
+
     def stage_times(self):
         names = (ctypes.c_char_p * 64)()
         ms = (ctypes.c_double * 64)()
@@ -211,16 +264,59 @@ class Operator:
             pass
 
 
+class Batcher:
+    """Batched solve over several resident operators (see hps_solve_batch)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().hps_batcher_create(ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, items, stream=None):
+        """items: sequence of (Operator, [bdry_j], [src_j or None], [u_j]) with
+        per-rhs CUDA float64 vectors (bdry_j [n_root_bdry], src_j and u_j
+        [n_leaves, p^2]).  The tensors must stay alive until the work queued
+        on `stream` has completed."""
+        arr = (BatchItem * len(items))()
+        for k, (op, bd, sr, uu) in enumerate(items):
+            s = op.sizes
+            n = len(bd)
+            if not (1 <= n <= 16) or len(uu) != n or (sr is not None and len(sr) != n):
+                raise ValueError("each item needs 1..16 right-hand sides and matching lists")
+            it = arr[k]
+            it.op = op._h.value
+            it.nrhs = n
+            for j in range(n):
+                it.bdry[j] = _dev_ptr(bd[j], "bdry", (s.n_root_bdry,)).value
+                it.u[j] = _dev_ptr(uu[j], "u", (s.n_leaves, s.pts_per_leaf)).value
+                if sr is not None and sr[j] is not None:
+                    it.src[j] = _dev_ptr(sr[j], "src", (s.n_leaves, s.pts_per_leaf)).value
+        _check(lib().hps_solve_batch(self._h, arr, len(items), _stream_ptr(stream)))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hps_batcher_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def debug_gemm(A, B, C, alpha=1.0, beta=0.0, trans_a=False, trans_b=False, stream=None):
     """C = alpha op(A) op(B) + beta C with the library's MFMA GEMM (test hook).
-    Tensors are CUDA float64, column-major views (pass X.T.contiguous().T or
+    Tensors are CUDA float64 (or all float32), column-major views (pass X.T.contiguous().T or
     Fortran-ordered data via .t())."""
+    import torch
     m, n = C.shape
     k = A.shape[0] if trans_a else A.shape[1]
     for X, nm in ((A, "A"), (B, "B"), (C, "C")):
         if X.stride(0) != 1:
             raise ValueError(f"{nm} must be column-major (stride(0) == 1)")
-    _check(lib().hps_debug_gemm(m, n, k, alpha, ctypes.c_void_p(A.data_ptr()), A.stride(1), int(trans_a),
+    fn = lib().hps_debug_gemm_f32 if C.dtype == torch.float32 else lib().hps_debug_gemm
+    _check(fn(m, n, k, alpha, ctypes.c_void_p(A.data_ptr()), A.stride(1), int(trans_a),
                                 ctypes.c_void_p(B.data_ptr()), B.stride(1), int(trans_b), beta,
                                 ctypes.c_void_p(C.data_ptr()), C.stride(1), _stream_ptr(stream)))
     return C

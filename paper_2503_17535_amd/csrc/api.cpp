@@ -24,6 +24,7 @@
 
 #include "../../include/hps.h"
 #include "common.hpp"
+#include "op.hpp"
 #include "precompute.hpp"
 
 namespace hps {
@@ -47,6 +48,29 @@ int leaf3d_assemble_launch(const double* coeffs, const double* D1, const double*
                            double* Lii, double* R, long long nl, hipStream_t st);
 int leaf_gather_int_launch(const double* src, const int* Ii, int ni, int npts, long long nl, int nrhs, int NRcap,
                            double* fint, hipStream_t st);
+int leaf_gather_pts_launch(const double* w, const int* idx, int n, int npts, long long nl, int nrhs, int NRcap,
+                           double* out, hipStream_t st);
+int leaf_scatter_int_launch(const double* fint, const int* pos_i, int ni, int npts, long long nl, int nrhs, int NRcap,
+                            double* lam, hipStream_t st);
+int leaf_src_t_launch(const double* LU, const int* perm, const double* b, int NI, long long nl, int nrhs, int NRcap,
+                      double* x, hipStream_t st);
+int block_copy_launch_f32(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
+                          int ncols_rt, float* dst, long long dst_stride, const float* src0, long long s0_stride,
+                          const float* src1, long long s1_stride, long long batch, hipStream_t st);
+int leaf_src_f32_launch(const float* LU, const int* perm, const int* pos, const double* r, int NI, long long nl,
+                        int nrhs, int NRcap, float* v, hipStream_t st);
+int to_f32_launch(const double* src, float* dst, long long n, hipStream_t st);
+int refine_init_launch(const double* bdry, const long long* bidx, int q, int nb0, long long nl, int nrhs, int NRcap,
+                       double* gam, hipStream_t st);
+int refine_residual_launch(const double* coef, const double* src, const double* gam, const double* D1,
+                           const double* D2, const double* P, const double* C2G, const int* Ii, const int* Ie, int p,
+                           long long nl, int nrhs, int NRcap, double* u, double* r1, double* Qu, hipStream_t st);
+int refine_flux_launch(const double* Qu, const int* nbr, int q, long long nl, int nrhs, int NRcap, float* hx,
+                       hipStream_t st);
+int refine_update_launch(const float* dg, const float* Y32, const float* v32, const int* Ii, int ni, int nb, int npts,
+                         long long nl, int nrhs, int NRcap, double* gam, double* u, hipStream_t st);
+int coeff_grad_launch(int d, int p, const double* u, const double* lam, const double* D1, const double* D2,
+                      long long nl, int nrhs, double* grad, hipStream_t st);
 int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
                       int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
                       const double* src1, long long s1_stride, long long batch, hipStream_t st);
@@ -58,11 +82,6 @@ int leaf_out_launch(const double* Y, const double* P, const double* g, const dou
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
-#define HPS_TRY(expr)            \
-  do {                           \
-    int _rc = (expr);            \
-    if (_rc != HPS_OK) return _rc; \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // device memory: a size-keyed cache of freed blocks, so repeated builds of the
@@ -107,10 +126,6 @@ void dfree(void* p, size_t bytes) {
 }
 
 // device copies of the precomputed leaf operators, per (d, p, leaf half-width)
-struct DevConsts {
-  double *D1 = nullptr, *D2 = nullptr, *Mt = nullptr, *QeP = nullptr, *Qi = nullptr, *P = nullptr;
-  int *Ii = nullptr, *Ie = nullptr;
-};
 std::mutex g_cst_mu;
 std::map<std::tuple<int, int, double>, DevConsts> g_cst;
 
@@ -174,93 +189,15 @@ int get_consts(int d, int p, double r, DevConsts** out) {
   HPS_TRY(upload(&c.P, Pc));
   HPS_TRY(upload(&c.Ii, o.Ii));
   HPS_TRY(upload(&c.Ie, o.Ie));
+  HPS_TRY(upload(&c.PosI, o.pos_i));
   auto res = g_cst.emplace(key, c);
   *out = &res.first->second;
   return HPS_OK;
 }
 
-struct GemmCall {
-  int first = 0, count = 0;
-  long long nblocks = 0;
-  bool ta = false, tb = false;
-};
-struct CopyCall {
-  int first_task = 0, ntasks = 0;
-};
-
-// Batched inversion of m x m matrices held in `A` (overwritten) into `Z`.
-struct GJPlan {
-  int m = 0;
-  long long batch = 0;
-  double *A = nullptr, *Z = nullptr;
-  bool small = true;
-  int nb = 0;
-  int *pos = nullptr, *piv = nullptr;
-  double *W = nullptr, *snap = nullptr;
-  std::vector<GemmCall> upd;
-};
-
-struct LevelPlan {
-  int lev = 0;
-  long long nm = 0;
-  int n = 0, m = 0, nbc = 0, nbp = 0, dn = 0;
-  double *Z = nullptr, *S = nullptr, *Bnz = nullptr, *Tp = nullptr, *Dbuf = nullptr;
-  GJPlan gj;
-  CopyCall copyD, fillT, copyB;
-  GemmCall gemmS, gemmT;
-  // solve
-  double *hint = nullptr, *gt = nullptr, *gint = nullptr;
-  CopyCall copyHint, copyGchild;
-  GemmCall gemmGt, gemmHp, gemmDown;
-};
-
-struct Alloc {
-  void* p;
-  size_t bytes;
-};
-
-struct TimedStage {
-  const char* name;
-  hipEvent_t a, b;
-};
-
 }  // namespace
 }  // namespace hps
 
-struct hps_op {
-  hps_tree_t tree{};
-  int p = 0, d = 0, flags = 0, nd = 0;
-  long long nl = 0;
-  int npts = 0, ni = 0, ne = 0, nb = 0;
-  double r = 0.0;
-  hps::DevConsts* cst = nullptr;
-  hipStream_t stream = nullptr;
-  double *LU = nullptr, *Y = nullptr, *Tleaf = nullptr;
-  // 3D leaves: LU holds L_ii^{-1}; Lbuf / Rbuf are build workspace, fint the
-  // gathered interior sources
-  double *Lbuf = nullptr, *Rbuf = nullptr, *fint = nullptr;
-  hps::GJPlan leaf_gj;
-  hps::GemmCall gemmYleaf, gemmVleaf;
-  int *perm = nullptr, *pos = nullptr, *flag = nullptr;
-  std::vector<hps::LevelPlan> levels;  // index = tree level of the parents
-  std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
-  std::vector<int> nbl;                // boundary size per tree level
-  double* v = nullptr;                 // [nl][NR][ni]
-  int NR = 16;
-  std::vector<hps::GemmGroup> hgroups;
-  hps::GemmGroup* dgroups = nullptr;
-  std::vector<hps::BlockOp> hops;
-  hps::BlockOp* dops = nullptr;
-  std::vector<hps::CopyItem> hitems;
-  hps::CopyItem* ditems = nullptr;
-  std::vector<hps::CopyTask> htasks;
-  hps::CopyTask* dtasks = nullptr;
-  hps::GemmCall gemmTleaf, gemmHleaf;
-  hps::CopyCall copyRoot;
-  std::vector<hps::Alloc> allocs;
-  size_t resident = 0;
-  std::vector<hps::TimedStage> stages;
-};
 
 namespace hps {
 namespace {
@@ -484,6 +421,31 @@ int plan_op(hps_op* op) {
     add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->fint, (long long)NR * ni, ni, op->v, (long long)NR * ni,
                              ni, ni, NR, ni, 1.0, 0.0, nl)},
              &op->gemmVleaf);
+  // adjoint leaf products
+  {
+    const int ne = op->ne;
+    if (d == 2) {
+      op->fint = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
+      if (!op->fint) { set_error("device allocation failed (adjoint workspace)"); return HPS_ENOMEM; }
+    }
+    op->wext = (double*)op_alloc(op, sizeof(double) * nl * NR * ne, false);
+    if (!op->wext) { set_error("device allocation failed (adjoint workspace)"); return HPS_ENOMEM; }
+    // g_leaf = Y^T w_int,  += P^T w_ext
+    add_gemm(op, {make_group(op->Y, (long long)ni * nb, ni, op->v, (long long)NR * ni, ni, op->g[L], (long long)NR * nb,
+                             nb, nb, NR, ni, 1.0, 0.0, nl)},
+             &op->adjYt, true, false);
+    add_gemm(op, {make_group(op->cst->P, 0, ne, op->wext, (long long)NR * ne, ne, op->g[L], (long long)NR * nb, nb, nb,
+                             NR, ne, 1.0, 1.0, nl, op->g[L], (long long)NR * nb, nb)},
+             &op->adjPt, true, false);
+    // v += Q_i^T h_leaf
+    add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->h[L], (long long)NR * nb, nb, op->v, (long long)NR * ni, ni, ni, NR,
+                             nb, 1.0, 1.0, nl, op->v, (long long)NR * ni, ni)},
+             &op->adjQt, true, false);
+    if (d == 3)  // f = L_ii^{-T} v
+      add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->v, (long long)NR * ni, ni, op->fint,
+                               (long long)NR * ni, ni, ni, NR, ni, 1.0, 0.0, nl)},
+               &op->adjLinvT, true, false);
+  }
 
   // leaf T = Q_e P + Q_i Y_int
   add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->Y, (long long)ni * nb, ni, op->Tleaf, (long long)nb * nb, nb, nb,
@@ -661,6 +623,47 @@ int plan_op(hps_op* op) {
         }
       add_copy(op, ops, &P.copyGchild);
     }
+    // --- adjoint: parent groups <- children's exterior faces
+    {
+      std::vector<BlockOp> ops;
+      const int ngrp = 2 * d * G.sub_per_face;
+      for (int gi = 0; gi < ngrp; ++gi) {
+        BlockOp o = make_op((long long)gi * n, nbp, n, 0);
+        op_src(o, 0, G.group_child[gi] * hstride_c + (long long)G.group_face[gi] * n, nbc);
+        ops.push_back(o);
+      }
+      add_copy(op, ops, &P.copyPext);
+    }
+    // g_parent += S^T g_int
+    add_gemm(op, {make_group(P.S, (long long)m * nbp, m, P.gint, (long long)NR * m, m, op->g[lev], (long long)NR * nbp,
+                             nbp, nbp, NR, m, 1.0, 1.0, nm, op->g[lev], (long long)NR * nbp, nbp)},
+             &P.gemmSt, true, false);
+    // gt_total(i) = g_int(i) + sum over both children of Bnz_c(., i)^T h_parent(c, .)
+    if (lev > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<GemmGroup> gs;
+        for (int c = 0; c < nd; ++c)
+          for (int k = 0; k < d; ++k) {
+            const int i = G.int_list[c][k];
+            if ((G.iface[i][pass == 0 ? 0 : 2]) != c) continue;
+            const double* C0 = pass == 0 ? P.gint + (long long)i * n : P.gt + (long long)i * n;
+            GemmGroup g = make_group(P.Bnz, (long long)nd * dn * dn, dn, op->h[lev], (long long)NR * nbp, nbp,
+                                     P.gt + (long long)i * n, (long long)NR * m, m, n, NR, n, 1.0, 1.0, nm, C0,
+                                     (long long)NR * m, m);
+            g.nseg = d;
+            for (int e = 0; e < d; ++e) {
+              g.aseg[e] = (long long)c * dn * dn + (long long)e * n + (long long)k * n * dn;
+              g.bseg[e] = (long long)G.group_of[c][G.ext_face[c][e]] * n;
+            }
+            gs.push_back(g);
+          }
+        add_gemm(op, gs, pass == 0 ? &P.gemmBt1 : &P.gemmBt2, true, false);
+      }
+    }
+    // h_int = -Z^T gt_total
+    add_gemm(op, {make_group(P.Z, (long long)m * m, m, lev > 0 ? P.gt : P.gint, (long long)NR * m, m, P.hint,
+                             (long long)NR * m, m, m, NR, m, -1.0, 0.0, nm)},
+             &P.gemmZt, true, false);
   }
   // upload descriptor tables
   op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
@@ -750,6 +753,245 @@ int run_solve_chunk(hps_op* op, const double* bdry, const double* src, double* u
   }
   HPS_TRY(leaf_out_launch(op->Y, op->cst->P, op->g[L], src ? op->v : nullptr, op->cst->Ii, op->cst->Ie, op->ni,
                           op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st));
+  stage_end(op, st);
+  return HPS_OK;
+}
+
+int run_adjoint_chunk(hps_op* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd, NR = op->NR;
+  stage_begin(op, "adjoint", st);
+  // leaves: g_leaf = Y^T w_int + P^T w_ext; v = w_int
+  HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, op->v, st));
+  HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ie, op->ne, op->npts, op->nl, nrhs, NR, op->wext, st));
+  HPS_TRY(run_gemm(op, op->adjYt, st, nrhs));
+  HPS_TRY(run_gemm(op, op->adjPt, st, nrhs));
+  // transposed downward pass, leaves to root
+  for (int lev = L - 1; lev >= 0; --lev) {
+    LevelPlan& P = op->levels[lev];
+    const long long cstride = (long long)nd * NR * P.nbc;
+    HPS_TRY(run_copy(op, P.copyHint, nrhs, P.gint, (long long)NR * P.m, op->g[lev + 1], cstride, nullptr, 0, P.nm, st));
+    HPS_TRY(run_copy(op, P.copyPext, nrhs, op->g[lev], (long long)NR * P.nbp, op->g[lev + 1], cstride, nullptr, 0, P.nm,
+                     st));
+    HPS_TRY(run_gemm(op, P.gemmSt, st, nrhs));
+  }
+  if (lam_bdry) HPS_TRY(run_copy(op, op->copyRoot, nrhs, lam_bdry, 0, op->g[0], 0, nullptr, 0, 1, st));
+  // transposed upward pass, root to leaves
+  HPS_HIP_TRY(hipMemsetAsync(op->h[0], 0, sizeof(double) * NR * op->nbl[0], st));
+  for (int lev = 0; lev < L; ++lev) {
+    LevelPlan& P = op->levels[lev];
+    if (lev > 0) {
+      HPS_TRY(run_gemm(op, P.gemmBt1, st, nrhs));
+      HPS_TRY(run_gemm(op, P.gemmBt2, st, nrhs));
+    }
+    HPS_TRY(run_gemm(op, P.gemmZt, st, nrhs));
+    HPS_TRY(run_copy(op, P.copyGchild, nrhs, op->h[lev + 1], (long long)nd * NR * P.nbc, op->h[lev],
+                     (long long)NR * P.nbp, P.hint, (long long)NR * P.m, P.nm, st));
+  }
+  // leaves: v += Q_i^T h_leaf;  f_int = L_ii^{-T} v
+  HPS_TRY(run_gemm(op, op->adjQt, st, nrhs));
+  if (op->d == 2) {
+    HPS_TRY(leaf_src_t_launch(op->LU, op->perm, op->v, op->ni, op->nl, nrhs, NR, op->fint, st));
+  } else {
+    HPS_TRY(run_gemm(op, op->adjLinvT, st, nrhs));
+  }
+  HPS_TRY(leaf_scatter_int_launch(op->fint, op->cst->PosI, op->ni, op->npts, op->nl, nrhs, NR, lam_src, st));
+  stage_end(op, st);
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mixed-precision solve: fp32 operator copies + fp64 residual refinement
+// ---------------------------------------------------------------------------
+struct Map32 {
+  struct E {
+    const double* base;
+    long long n;
+    float* f;
+  };
+  std::vector<E> e;
+  void add(const double* base, long long n, float* f) { e.push_back({base, n, f}); }
+  const float* operator()(const double* p) const {
+    if (!p) return nullptr;
+    for (const E& x : e)
+      if (p >= x.base && p < x.base + x.n) return x.f + (p - x.base);
+    return nullptr;
+  }
+};
+
+int to_group32(const GemmGroup& g, const Map32& m, GemmGroupF32* out) {
+  GemmGroupF32 f;
+  std::memset(&f, 0, sizeof(f));
+  f.A = m(g.A);
+  f.B = m(g.B);
+  f.C = const_cast<float*>(m(g.C));
+  f.C0 = g.C0 ? m(g.C0) : nullptr;
+  if (!f.A || !f.B || !f.C || (g.C0 && !f.C0)) {
+    set_error("internal: operand without an fp32 copy");
+    return HPS_EINVAL;
+  }
+  f.sA = g.sA; f.sB = g.sB; f.sC = g.sC; f.sC0 = g.sC0;
+  for (int k = 0; k < kMaxSeg; ++k) { f.aseg[k] = g.aseg[k]; f.bseg[k] = g.bseg[k]; }
+  f.lda = g.lda; f.ldb = g.ldb; f.ldc = g.ldc; f.ldc0 = g.ldc0;
+  f.M = g.M; f.N = g.N; f.K = g.K; f.nseg = g.nseg;
+  f.alpha = (float)g.alpha; f.beta = (float)g.beta;
+  f.batch = g.batch;
+  *out = f;
+  return HPS_OK;
+}
+
+int add_gemm32(hps_op* op, const GemmCall& c, const Map32& m, GemmCall* out) {
+  std::vector<GemmGroupF32> gs(c.count);
+  for (int i = 0; i < c.count; ++i) HPS_TRY(to_group32(op->hgroups[c.first + i], m, &gs[i]));
+  out->first = (int)op->hgroups32.size();
+  out->count = c.count;
+  out->nblocks = gemm_prepare_f32(gs);
+  out->ta = c.ta;
+  out->tb = c.tb;
+  op->hgroups32.insert(op->hgroups32.end(), gs.begin(), gs.end());
+  return HPS_OK;
+}
+
+float* alloc32(hps_op* op, long long n) { return (float*)op_alloc(op, sizeof(float) * std::max(1LL, n)); }
+
+// fp32 copies of the solve operators, fp32 / fp64 workspaces of the refined
+// solve, the coefficient copy for the fp64 residual, leaf adjacency tables.
+int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
+  if (op->d != 2) { set_error("the mixed-precision solve supports 2D operators"); return HPS_EUNSUPPORTED; }
+  const long long nl = op->nl;
+  const int ni = op->ni, nb = op->nb, NR = op->NR, L = op->tree.depth, p = op->p, q = p - 2;
+  const int nt = n_terms(op->d);
+  op->coef = (double*)op_alloc(op, sizeof(double) * nl * nt * op->npts);
+  op->LU32 = alloc32(op, nl * ni * ni);
+  op->Y32 = alloc32(op, nl * ni * nb);
+  op->Qi32 = alloc32(op, (long long)nb * ni);
+  op->v32 = alloc32(op, nl * NR * ni);
+  op->hx32 = alloc32(op, nl * NR * nb);
+  op->gam = (double*)op_alloc(op, sizeof(double) * nl * NR * nb);
+  op->r1 = (double*)op_alloc(op, sizeof(double) * nl * NR * ni);
+  op->Qu = (double*)op_alloc(op, sizeof(double) * nl * NR * nb);
+  op->C2G = (double*)op_alloc(op, sizeof(double) * q * p);
+  op->nbr = (int*)op_alloc(op, sizeof(int) * nl * 4);
+  op->bidx = (long long*)op_alloc(op, sizeof(long long) * nl * 4);
+  if (!op->coef || !op->LU32 || !op->Y32 || !op->Qi32 || !op->v32 || !op->hx32 || !op->gam || !op->r1 || !op->Qu ||
+      !op->C2G || !op->nbr || !op->bidx) {
+    set_error("device allocation failed (mixed-precision copies)");
+    return HPS_ENOMEM;
+  }
+  HPS_HIP_TRY(hipMemcpyAsync(op->coef, coeffs, sizeof(double) * nl * nt * op->npts, hipMemcpyDeviceToDevice, st));
+  HPS_TRY(to_f32_launch(op->LU, op->LU32, nl * ni * ni, st));
+  HPS_TRY(to_f32_launch(op->Y, op->Y32, nl * ni * nb, st));
+  HPS_TRY(to_f32_launch(op->cst->Qi, op->Qi32, (long long)nb * ni, st));
+  Map32 m;
+  m.add(op->cst->Qi, (long long)nb * ni, op->Qi32);
+  m.add(op->v, nl * NR * ni, op->v32);
+  op->g32.assign(L + 1, nullptr);
+  op->h32.assign(L + 1, nullptr);
+  for (int l = 0; l <= L; ++l) {
+    const long long n = (1LL << (2 * l)) * NR * op->nbl[l];
+    op->g32[l] = alloc32(op, n);
+    op->h32[l] = alloc32(op, n);
+    if (!op->g32[l] || !op->h32[l]) { set_error("device allocation failed (fp32 workspace)"); return HPS_ENOMEM; }
+    m.add(op->g[l], n, op->g32[l]);
+    m.add(op->h[l], n, op->h32[l]);
+  }
+  for (auto& P : op->levels) {
+    const long long nZ = P.nm * P.m * P.m, nS = P.nm * P.m * P.nbp, nB = P.nm * op->nd * P.dn * P.dn;
+    const long long nw = P.nm * NR * P.m;
+    P.Z32 = alloc32(op, nZ);
+    P.S32 = alloc32(op, nS);
+    P.Bnz32 = alloc32(op, nB);
+    P.hint32 = alloc32(op, nw);
+    P.gt32 = alloc32(op, nw);
+    P.gint32 = alloc32(op, nw);
+    if (!P.Z32 || !P.S32 || !P.Bnz32 || !P.hint32 || !P.gt32 || !P.gint32) {
+      set_error("device allocation failed (fp32 merge copies)");
+      return HPS_ENOMEM;
+    }
+    HPS_TRY(to_f32_launch(P.Z, P.Z32, nZ, st));
+    HPS_TRY(to_f32_launch(P.S, P.S32, nS, st));
+    HPS_TRY(to_f32_launch(P.Bnz, P.Bnz32, nB, st));
+    m.add(P.Z, nZ, P.Z32);
+    m.add(P.S, nS, P.S32);
+    m.add(P.Bnz, nB, P.Bnz32);
+    m.add(P.hint, nw, P.hint32);
+    m.add(P.gt, nw, P.gt32);
+    m.add(P.gint, nw, P.gint32);
+  }
+  // fp32 descriptor tables: the fp64 solve's groups with every operand mapped
+  HPS_TRY(add_gemm32(op, op->gemmHleaf, m, &op->gemmHleaf32));
+  {  // h = Q_i v + (flux imbalance handed to this leaf)
+    GemmGroupF32& g = op->hgroups32[op->gemmHleaf32.first];
+    g.beta = 1.0f;
+    g.C0 = op->hx32;
+    g.sC0 = (long long)NR * nb;
+    g.ldc0 = nb;
+  }
+  for (auto& P : op->levels) {
+    HPS_TRY(add_gemm32(op, P.gemmGt, m, &P.gemmGt32));
+    if (P.lev > 0) HPS_TRY(add_gemm32(op, P.gemmHp, m, &P.gemmHp32));
+    HPS_TRY(add_gemm32(op, P.gemmDown, m, &P.gemmDown32));
+  }
+  op->dgroups32 = (GemmGroupF32*)op_alloc(op, sizeof(GemmGroupF32) * std::max<size_t>(1, op->hgroups32.size()), false);
+  if (!op->dgroups32) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
+  HPS_HIP_TRY(hipMemcpy(op->dgroups32, op->hgroups32.data(), sizeof(GemmGroupF32) * op->hgroups32.size(),
+                        hipMemcpyHostToDevice));
+  // host constants: Chebyshev -> Gauss interpolation, leaf adjacency
+  const LeafOps& o = leaf_ops(op->d, p);
+  HPS_HIP_TRY(hipMemcpy(op->C2G, o.C2G.data(), sizeof(double) * q * p, hipMemcpyHostToDevice));
+  std::vector<int> nbr;
+  std::vector<long long> bidx;
+  leaf_face_tables(L, p, nbr, bidx);
+  HPS_HIP_TRY(hipMemcpy(op->nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
+  HPS_HIP_TRY(hipMemcpy(op->bidx, bidx.data(), sizeof(long long) * bidx.size(), hipMemcpyHostToDevice));
+  op->fp32 = true;
+  return HPS_OK;
+}
+
+int run_gemm32(hps_op* op, const GemmCall& c, hipStream_t st, int n_override) {
+  return gemm_launch_f32(op->dgroups32 + c.first, c.count, c.nblocks, c.ta, c.tb, st, n_override);
+}
+
+int run_copy32(hps_op* op, const CopyCall& c, int ncols_rt, float* dst, long long dst_stride, const float* s0,
+               long long s0_stride, const float* s1, long long s1_stride, long long batch, hipStream_t st) {
+  return block_copy_launch_f32(op->dops, op->ditems, op->dtasks + c.first_task, c.ntasks, ncols_rt, dst, dst_stride,
+                               s0, s0_stride, s1, s1_stride, batch, st);
+}
+
+// Iterative refinement on the composite collocation system: the iterate
+// (gamma, u_int) is fp64, each correction is an fp32 HPS solve of the fp64
+// residual (collocation rows as a source, flux-balance rows as an extra
+// outgoing flux of the panel's lower-index leaf).
+int run_solve_refined_chunk(hps_op* op, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd, NR = op->NR, p = op->p, q = p - 2;
+  const long long nl = op->nl;
+  stage_begin(op, "solve_refined", st);
+  HPS_HIP_TRY(hipMemsetAsync(u, 0, sizeof(double) * nrhs * nl * op->npts, st));
+  HPS_TRY(refine_init_launch(bdry, op->bidx, q, op->nbl[0], nl, nrhs, NR, op->gam, st));
+  for (int sweep = 0; sweep <= op->refine_sweeps; ++sweep) {
+    HPS_TRY(refine_residual_launch(op->coef, src, op->gam, op->cst->D1, op->cst->D2, op->cst->P, op->C2G, op->cst->Ii,
+                                   op->cst->Ie, p, nl, nrhs, NR, u, op->r1, op->Qu, st));
+    if (sweep == op->refine_sweeps) break;  // the last pass only completes u(I_e) = P gamma
+    HPS_TRY(refine_flux_launch(op->Qu, op->nbr, q, nl, nrhs, NR, op->hx32, st));
+    // fp32 correction solve with zero Dirichlet data
+    HPS_TRY(leaf_src_f32_launch(op->LU32, op->perm, op->pos, op->r1, op->ni, nl, nrhs, NR, op->v32, st));
+    HPS_TRY(run_gemm32(op, op->gemmHleaf32, st, nrhs));
+    for (int lev = L - 1; lev >= 0; --lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_TRY(run_copy32(op, P.copyHint, nrhs, P.hint32, (long long)NR * P.m, op->h32[lev + 1],
+                         (long long)nd * NR * P.nbc, nullptr, 0, P.nm, st));
+      HPS_TRY(run_gemm32(op, P.gemmGt32, st, nrhs));
+      if (lev > 0) HPS_TRY(run_gemm32(op, P.gemmHp32, st, nrhs));
+    }
+    HPS_HIP_TRY(hipMemsetAsync(op->g32[0], 0, sizeof(float) * NR * op->nbl[0], st));
+    for (int lev = 0; lev < L; ++lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_TRY(run_gemm32(op, P.gemmDown32, st, nrhs));
+      HPS_TRY(run_copy32(op, P.copyGchild, nrhs, op->g32[lev + 1], (long long)nd * NR * P.nbc, op->g32[lev],
+                         (long long)NR * P.nbp, P.gint32, (long long)NR * P.m, P.nm, st));
+    }
+    HPS_TRY(refine_update_launch(op->g32[L], op->Y32, op->v32, op->cst->Ii, op->ni, op->nb, op->npts, nl, nrhs, NR,
+                                 op->gam, u, st));
+  }
   stage_end(op, st);
   return HPS_OK;
 }
@@ -861,6 +1103,7 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
       rc = HPS_ESINGULAR;
     }
   }
+  if (rc == HPS_OK && (flags & HPS_FLAG_FP32_COPY)) rc = setup_fp32(op, coeffs, op->stream);
   if (rc != HPS_OK) {
     if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(op->stream);
     hps_free(op);
@@ -872,7 +1115,11 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
 
 int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, int precision, void* stream) {
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
-  if (precision != HPS_FP64) { set_error("only HPS_FP64 solves are available in this build"); return HPS_EUNSUPPORTED; }
+  if (precision != HPS_FP64 && precision != HPS_FP32_REFINED) { set_error("unknown precision"); return HPS_EINVAL; }
+  if (precision == HPS_FP32_REFINED && !op->fp32) {
+    set_error("HPS_FP32_REFINED needs an operator built with HPS_FLAG_FP32_COPY");
+    return HPS_EINVAL;
+  }
   hipError_t pending = hipGetLastError();
   if (pending != hipSuccess) {
     set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
@@ -883,15 +1130,54 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
   const long long nbr = op->nbl[0], field = op->nl * op->npts;
   for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
     const int k = std::min(op->NR, nrhs - r0);
-    HPS_TRY(run_solve_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+    if (precision == HPS_FP32_REFINED)
+      HPS_TRY(run_solve_refined_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+    else
+      HPS_TRY(run_solve_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
   }
   return HPS_OK;
 }
 
+int hps_refine_sweeps(hps_op_t* op, int sweeps) {
+  if (!op || sweeps < 0 || sweeps > 64) { set_error("op must be non-NULL and 0 <= sweeps <= 64"); return -HPS_EINVAL; }
+  const int old = op->refine_sweeps;
+  if (sweeps > 0) op->refine_sweeps = sweeps;
+  return old;
+}
+
 int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, void* stream) {
-  (void)op; (void)w; (void)lam_src; (void)lam_bdry; (void)nrhs; (void)stream;
-  set_error("adjoint solve not available in this build");
-  return HPS_EUNSUPPORTED;
+  if (!op || !w || !lam_src || nrhs < 1) { set_error("op, w, lam_src must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
+  hipError_t pending = hipGetLastError();
+  if (pending != hipSuccess) {
+    set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
+    return HPS_EDEVICE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  clear_stages(op);
+  const long long nbr = op->nbl[0], field = op->nl * op->npts;
+  for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
+    const int k = std::min(op->NR, nrhs - r0);
+    HPS_TRY(run_adjoint_chunk(op, w + r0 * field, lam_src + r0 * field, lam_bdry ? lam_bdry + r0 * nbr : nullptr, k, st));
+  }
+  return HPS_OK;
+}
+
+int hps_coeff_grad(hps_op_t* op, const double* u, const double* lam, int nrhs, double* grad, void* stream) {
+  if (!op || !u || !lam || !grad || nrhs < 1) {
+    set_error("op, u, lam, grad must be non-NULL and nrhs >= 1");
+    return HPS_EINVAL;
+  }
+  return coeff_grad_launch(op->d, op->p, u, lam, op->cst->D1, op->cst->D2, op->nl, nrhs, grad, (hipStream_t)stream);
+}
+
+int hps_interp_weights(const hps_tree_t* tree, int p, const double* x, long long m, long long* leaf, double* w) {
+  HPS_TRY(check_tree(tree, p));
+  if (m < 0 || (m > 0 && (!x || !leaf || !w))) { set_error("x, leaf, w must be non-NULL and m >= 0"); return HPS_EINVAL; }
+  if (interp_weights(tree->dim, tree->depth, tree->lo, tree->hi, p, x, m, leaf, w) != 0) {
+    set_error("a point lies outside the domain");
+    return HPS_EINVAL;
+  }
+  return HPS_OK;
 }
 
 int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap) {
@@ -915,6 +1201,28 @@ void hps_free(hps_op_t* op) {
   clear_stages(op);
   for (auto& a : op->allocs) dfree(a.p, a.bytes);
   delete op;
+}
+
+int hps_debug_gemm_f32(int m, int n, int k, float alpha, const float* a, int lda, int trans_a, const float* b,
+                       int ldb, int trans_b, float beta, float* c, int ldc, void* stream) {
+  if (m < 0 || n < 0 || k < 0 || !a || !b || !c) { set_error("bad GEMM arguments"); return HPS_EINVAL; }
+  GemmGroupF32 g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = a; g.B = b; g.C = c; g.C0 = c;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc; g.ldc0 = ldc;
+  g.M = m; g.N = n; g.K = k; g.nseg = 1;
+  g.alpha = alpha; g.beta = beta; g.batch = 1;
+  std::vector<GemmGroupF32> gs = {g};
+  const long long nblocks = gemm_prepare_f32(gs);
+  GemmGroupF32* dg = nullptr;
+  HPS_HIP_TRY(hipMalloc(&dg, sizeof(GemmGroupF32)));
+  hipStream_t st = (hipStream_t)stream;
+  int rc = HPS_OK;
+  if (hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroupF32), hipMemcpyHostToDevice, st) != hipSuccess) rc = HPS_EDEVICE;
+  if (rc == HPS_OK) rc = gemm_launch_f32(dg, 1, nblocks, trans_a != 0, trans_b != 0, st, 0);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dg);
+  return rc;
 }
 
 int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, int trans_a, const double* b, int ldb,

@@ -74,6 +74,38 @@ struct CopyTask {
   int begin, end;
 };
 
+// ---------------------------------------------------------------------------
+// Batched solve over several operators: one launch per pass stage covers the
+// work of every operator in the batch.  A job is one operator's share of a
+// launch; `first_block` is the prefix sum of the blocks of earlier jobs.
+// ---------------------------------------------------------------------------
+constexpr int kBatchMaxRhs = 16;
+
+struct LeafJob {
+  const double *LU, *Y, *P, *g;
+  const int *perm, *pos, *Ii, *Ie;
+  double *v, *g0;
+  int NI, NE, NB, npts, nrhs, NRcap, nb0;
+  long long nl, first_block;
+  const double* bdry[kBatchMaxRhs];
+  const double* src[kBatchMaxRhs];  // NULL entries mean f = 0
+  double* u[kBatchMaxRhs];
+};
+
+struct CopyJob {
+  const BlockOp* ops;
+  const CopyItem* items;
+  const CopyTask* tasks;  // the call's first task
+  int ntasks, ncols_rt;
+  long long batch, first_block;
+  double* dst;
+  long long dst_stride;
+  const double* src0;
+  long long s0_stride;
+  const double* src1;
+  long long s1_stride;
+};
+
 // error reporting (implemented in api.cpp)
 void set_error(const std::string& msg);
 

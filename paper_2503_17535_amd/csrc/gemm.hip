@@ -6,7 +6,8 @@
 // k-step 16 staged through LDS.  The MFMA is fed with (B-fragment, A-fragment)
 // so that its accumulator layout puts consecutive lanes on consecutive rows
 // of the column-major C: the epilogue stores 128-byte runs.  Accumulator
-// layout (measured on gfx950): lane l, element v holds D(l/16 + 4v, l%16).
+// layout (measured on gfx950): fp64 lane l, element v holds D(l/16 + 4v, l%16);
+// fp32 lane l, element v holds D(4 (l/16) + v, l%16).
 //
 // One launch covers a list of groups (GemmGroup); every (group, batch item,
 // tile) triple is one workgroup.  Block indices are remapped so that the
@@ -46,17 +47,23 @@ __device__ __forceinline__ long long xcd_remap(long long b, long long nblocks) {
 }
 
 template <typename T> struct MfmaOp;
+// col(lane, v): column of C (within the 16 x 16 block) that accumulator
+// element v of `lane` holds; its row is lane % 16 (see the feeding order).
 template <> struct MfmaOp<double> {
   typedef v4d acc_t;
   static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // fp64 accumulator: lane l, element v holds D(l/16 + 4v, l%16)
+  static __device__ __forceinline__ int col(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 template <> struct MfmaOp<float> {
   typedef v4f acc_t;
   static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // fp32 accumulator: lane l, element v holds D(4 (l/16) + v, l%16)
+  static __device__ __forceinline__ int col(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 template <typename T, typename G, bool TA, bool TB>
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
       __syncthreads();
     }
   }
-  // ---- epilogue: acc[a][b][v] = C(row = .. + lane%16, col = .. + lane/16 + 4*v)
+  // ---- epilogue: acc[a][b][v] = C(row = .. + lane%16, col = .. + MfmaOp<T>::col(lane, v))
   T* C = g->C + bat * g->sC;
   const T* C0 = g->C0 ? g->C0 + bat * g->sC0 : nullptr;
   const T alpha = g->alpha, beta = g->beta;
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
     for (int b = 0; b < 2; ++b) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = j0 + wc * 32 + b * 16 + (lane >> 4) + 4 * v;
+        const int col = j0 + wc * 32 + b * 16 + MfmaOp<T>::col(lane, v);
         if (col >= N) continue;
         T val = alpha * acc[a][b][v];
         if (beta != T(0)) val += beta * C0[row + (long long)col * ldc0];

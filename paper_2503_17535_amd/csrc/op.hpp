@@ -1,0 +1,138 @@
+// Internal definitions shared by the host sources of the library: the
+// operator record and the launch plans its build and solve replay.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/hps.h"
+#include "common.hpp"
+
+#define HPS_TRY(expr)              \
+  do {                             \
+    int _rc = (expr);              \
+    if (_rc != HPS_OK) return _rc; \
+  } while (0)
+
+namespace hps {
+
+// Per-(dim, p, leaf size) constants resident on the device.
+struct DevConsts {
+  double *D1 = nullptr, *D2 = nullptr, *Mt = nullptr, *QeP = nullptr, *Qi = nullptr, *P = nullptr;
+  int *Ii = nullptr, *Ie = nullptr, *PosI = nullptr;
+};
+
+struct GemmCall {
+  int first = 0, count = 0;
+  long long nblocks = 0;
+  bool ta = false, tb = false;
+};
+struct CopyCall {
+  int first_task = 0, ntasks = 0;
+};
+
+// Batched inversion of m x m matrices held in `A` (overwritten) into `Z`.
+struct GJPlan {
+  int m = 0;
+  long long batch = 0;
+  double *A = nullptr, *Z = nullptr;
+  bool small = true;
+  int nb = 0;
+  int *pos = nullptr, *piv = nullptr;
+  double *W = nullptr, *snap = nullptr;
+  std::vector<GemmCall> upd;
+};
+
+struct LevelPlan {
+  int lev = 0;
+  long long nm = 0;
+  int n = 0, m = 0, nbc = 0, nbp = 0, dn = 0;
+  double *Z = nullptr, *S = nullptr, *Bnz = nullptr, *Tp = nullptr, *Dbuf = nullptr;
+  GJPlan gj;
+  CopyCall copyD, fillT, copyB;
+  GemmCall gemmS, gemmT;
+  // solve
+  double *hint = nullptr, *gt = nullptr, *gint = nullptr;
+  CopyCall copyHint, copyGchild;
+  GemmCall gemmGt, gemmHp, gemmDown;
+  // adjoint
+  CopyCall copyPext;
+  GemmCall gemmSt, gemmBt1, gemmBt2, gemmZt;
+  // fp32 copies for the mixed-precision solve
+  float *Z32 = nullptr, *S32 = nullptr, *Bnz32 = nullptr;
+  float *hint32 = nullptr, *gt32 = nullptr, *gint32 = nullptr;
+  GemmCall gemmGt32, gemmHp32, gemmDown32;
+};
+
+struct Alloc {
+  void* p;
+  size_t bytes;
+};
+
+struct TimedStage {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace hps
+
+struct hps_op {
+  hps_tree_t tree{};
+  int p = 0, d = 0, flags = 0, nd = 0;
+  long long nl = 0;
+  int npts = 0, ni = 0, ne = 0, nb = 0;
+  double r = 0.0;
+  hps::DevConsts* cst = nullptr;
+  hipStream_t stream = nullptr;
+  double *LU = nullptr, *Y = nullptr, *Tleaf = nullptr;
+  // 3D leaves: LU holds L_ii^{-1}; Lbuf / Rbuf are build workspace, fint the
+  // gathered interior sources
+  double *Lbuf = nullptr, *Rbuf = nullptr, *fint = nullptr;
+  hps::GJPlan leaf_gj;
+  hps::GemmCall gemmYleaf, gemmVleaf;
+  int *perm = nullptr, *pos = nullptr, *flag = nullptr;
+  std::vector<hps::LevelPlan> levels;  // index = tree level of the parents
+  std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
+  std::vector<int> nbl;                // boundary size per tree level
+  double* v = nullptr;                 // [nl][NR][ni]
+  int NR = 16;
+  std::vector<hps::GemmGroup> hgroups;
+  hps::GemmGroup* dgroups = nullptr;
+  std::vector<hps::BlockOp> hops;
+  hps::BlockOp* dops = nullptr;
+  std::vector<hps::CopyItem> hitems;
+  hps::CopyItem* ditems = nullptr;
+  std::vector<hps::CopyTask> htasks;
+  hps::CopyTask* dtasks = nullptr;
+  hps::GemmCall gemmTleaf, gemmHleaf;
+  hps::GemmCall adjYt, adjPt, adjQt, adjLinvT;  // adjoint leaf products
+  double* wext = nullptr;                       // [nl][NR][ne]
+  hps::CopyCall copyRoot;
+  // mixed-precision solve (HPS_FLAG_FP32_COPY): fp32 operator copies and
+  // workspaces, fp64 iterate and residuals, leaf adjacency
+  bool fp32 = false;
+  int refine_sweeps = 6;
+  double* coef = nullptr;                      // [nl][n_terms][npts]
+  double* C2G = nullptr;                       // q x p row-major
+  float *LU32 = nullptr, *Y32 = nullptr, *Qi32 = nullptr;
+  std::vector<float*> g32, h32;
+  float *v32 = nullptr, *hx32 = nullptr;
+  double *gam = nullptr, *r1 = nullptr, *Qu = nullptr;
+  int* nbr = nullptr;                          // [nl][4]: neighbour leaf*4 + face, or -1
+  long long* bidx = nullptr;                   // [nl][4]: root-boundary offset, or -1
+  std::vector<hps::GemmGroupF32> hgroups32;
+  hps::GemmGroupF32* dgroups32 = nullptr;
+  hps::GemmCall gemmHleaf32;
+  std::vector<hps::Alloc> allocs;
+  size_t resident = 0;
+  std::vector<hps::TimedStage> stages;
+};
+
+namespace hps {
+long long gemm_prepare(std::vector<GemmGroup>& groups);
+long long gemm_prepare_f32(std::vector<GemmGroupF32>& groups);
+int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
+                    int n_override);
+int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
+                int n_override);
+}  // namespace hps

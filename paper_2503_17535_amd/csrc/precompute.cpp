@@ -412,4 +412,111 @@ void boundary_points(int d, int depth, double lo, double hi, int p, double* xyz)
   }
 }
 
+// ---------------------------------------------------------------------------
+// interpolation at scattered points: containing leaf + tensor barycentric
+// weights on its Chebyshev grid
+// ---------------------------------------------------------------------------
+static long long cell_leaf(int d, int depth, const long long* cell) {
+  const MergeGeom& g = merge_geom(d);
+  long long leaf = 0;
+  for (int l = 0; l < depth; ++l) {
+    const int sh = depth - 1 - l;
+    int digit = 0;
+    for (int c = 0; c < (1 << d); ++c) {
+      bool ok = true;
+      for (int a = 0; a < d; ++a) ok = ok && g.child_off[c][a] == (int)((cell[a] >> sh) & 1);
+      if (ok) { digit = c; break; }
+    }
+    leaf = leaf * (1 << d) + digit;
+  }
+  return leaf;
+}
+
+int interp_weights(int d, int depth, double lo, double hi, int p, const double* x, long long m, long long* leaf,
+                   double* w) {
+  const LeafOps& o = leaf_ops(d, p);
+  const long long ncell = 1LL << depth;
+  const double h = (hi - lo) / (double)ncell, r = h / 2.0, tol = 1e-14;
+  for (long long k = 0; k < m; ++k) {
+    const double* xk = x + k * d;
+    long long c0[3];
+    for (int a = 0; a < d; ++a) {
+      if (!(xk[a] >= lo - tol && xk[a] <= hi + tol)) return -1;
+      c0[a] = std::min(ncell - 1, std::max(0LL, (long long)std::floor((xk[a] - lo) / h)));
+    }
+    // lowest-index leaf among the (up to 3^d) nearby cells that contain x
+    long long best = -1, bestcell[3] = {0, 0, 0};
+    const int nn = d == 2 ? 9 : 27;
+    for (int t = 0; t < nn; ++t) {
+      long long cell[3] = {0, 0, 0};
+      bool ok = true;
+      int tt = t;
+      for (int a = 0; a < d; ++a) {
+        cell[a] = c0[a] + (tt % 3) - 1;
+        tt /= 3;
+        if (cell[a] < 0 || cell[a] >= ncell) { ok = false; break; }
+        const double clo = lo + (double)cell[a] * h;
+        if (xk[a] < clo - tol || xk[a] > clo + h + tol) { ok = false; break; }
+      }
+      if (!ok) continue;
+      const long long lf = cell_leaf(d, depth, cell);
+      if (best < 0 || lf < best) {
+        best = lf;
+        for (int a = 0; a < d; ++a) bestcell[a] = cell[a];
+      }
+    }
+    if (best < 0) return -1;
+    leaf[k] = best;
+    std::vector<double> w1[3];
+    for (int a = 0; a < d; ++a) {
+      double ref = (xk[a] - (lo + (double)bestcell[a] * h)) / r - 1.0;
+      ref = std::min(1.0, std::max(-1.0, ref));
+      w1[a] = interp(o.cheb, std::vector<double>{ref});
+    }
+    double* wk = w + k * (long long)o.npts;
+    for (int pt = 0; pt < o.npts; ++pt) {
+      const int c[3] = {pt % p, (pt / p) % p, pt / (p * p)};
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) v *= w1[a][c[a]];
+      wk[pt] = v;
+    }
+  }
+  return 0;
+}
+
+void leaf_face_tables(int depth, int p, std::vector<int>& nbr, std::vector<long long>& bidx) {
+  const MergeGeom& g = merge_geom(2);
+  const long long nl = 1LL << (2 * depth), ncell = 1LL << depth;
+  const int q = p - 2;
+  nbr.assign(nl * 4, -1);
+  bidx.assign(nl * 4, -1);
+  std::vector<long long> cx(nl), cy(nl);
+  std::vector<long long> at((size_t)ncell * ncell);
+  for (long long l = 0; l < nl; ++l) {
+    long long x = 0, y = 0, rem = l;
+    std::vector<int> digits(depth);
+    for (int k = depth - 1; k >= 0; --k) { digits[k] = (int)(rem % 4); rem /= 4; }
+    for (int k = 0; k < depth; ++k) {
+      x = 2 * x + g.child_off[digits[k]][0];
+      y = 2 * y + g.child_off[digits[k]][1];
+    }
+    cx[l] = x;
+    cy[l] = y;
+    at[(size_t)(y * ncell + x)] = l;
+  }
+  const int opposite[4] = {2, 3, 0, 1};
+  for (long long l = 0; l < nl; ++l)
+    for (int f = 0; f < 4; ++f) {
+      const FaceDesc& fd = g.faces[f];
+      long long c[2] = {cx[l], cy[l]};
+      c[fd.axis] += fd.side ? 1 : -1;
+      if (c[fd.axis] < 0 || c[fd.axis] >= ncell) {
+        const long long t = fd.axis == 0 ? cy[l] : cx[l];  // panel position along the face
+        bidx[l * 4 + f] = ((long long)f * ncell + t) * q;
+      } else {
+        nbr[l * 4 + f] = (int)(at[(size_t)(c[1] * ncell + c[0])] * 4 + opposite[f]);
+      }
+    }
+}
+
 }  // namespace hps

@@ -73,4 +73,14 @@ void leaf_points(int d, int depth, double lo, double hi, int p, double* xyz);
 void boundary_points(int d, int depth, double lo, double hi, int p, double* xyz);
 long long n_root_bdry(int d, int depth, int p);
 
+// 2D leaf adjacency: nbr[leaf*4 + f] = neighbour leaf * 4 + its face across
+// face f, or -1 on the domain boundary; bidx[leaf*4 + f] = offset of face f's
+// Gauss points in the root boundary order, or -1 for an interior face.
+void leaf_face_tables(int depth, int p, std::vector<int>& nbr, std::vector<long long>& bidx);
+
+// Containing leaf and tensor barycentric weights of m scattered points (see
+// hps_interp_weights); returns -1 if a point lies outside the domain.
+int interp_weights(int d, int depth, double lo, double hi, int p, const double* x, long long m, long long* leaf,
+                   double* w);
+
 }  // namespace hps

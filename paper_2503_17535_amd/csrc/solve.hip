@@ -14,6 +14,8 @@
 //   with Y = [I; Y_int] P written out as  u(I_e) = P g,  u(I_i) = Y_int g + v.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "../../include/hps.h"
 
@@ -21,28 +23,26 @@ namespace hps {
 
 constexpr int BC_THREADS = 256;
 
-__global__ __launch_bounds__(BC_THREADS) void block_copy_kernel(const BlockOp* __restrict__ ops,
-                                                                const CopyItem* __restrict__ items,
-                                                                const CopyTask* __restrict__ tasks, int ncols_rt,
-                                                                double* __restrict__ dst, long long dst_stride,
-                                                                const double* __restrict__ src0, long long s0_stride,
-                                                                const double* __restrict__ src1, long long s1_stride) {
-  const CopyTask task = tasks[blockIdx.x];
-  const long long b = blockIdx.y;
+template <typename T>
+__device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops, const CopyItem* __restrict__ items,
+                                                const CopyTask task, long long b, int ncols_rt, T* __restrict__ dst,
+                                                long long dst_stride, const T* __restrict__ src0,
+                                                long long s0_stride, const T* __restrict__ src1,
+                                                long long s1_stride) {
   for (int it = task.begin; it < task.end; ++it) {
     const CopyItem item = items[it];
     const BlockOp op = ops[item.op];
     const int c0 = item.c0, c1 = item.c1 < 0 ? ncols_rt : item.c1;
-    double* D = dst + b * dst_stride + op.dst_off;
-    const double* S0 = nullptr;
-    const double* S1 = nullptr;
+    T* D = dst + b * dst_stride + op.dst_off;
+    const T* S0 = nullptr;
+    const T* S1 = nullptr;
     if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
     if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
     const int rows = op.rows;
     const int n = rows * (c1 - c0);
     for (int e = threadIdx.x; e < n; e += BC_THREADS) {
       const int r = e % rows, c = c0 + e / rows;
-      double v = 0.0;
+      T v = T(0);
       if (S0) v = S0[r + (long long)c * op.src_ld[0]];
       if (S1) v += S1[r + (long long)c * op.src_ld[1]];
       D[r + (long long)c * op.dst_ld] = v;
@@ -50,13 +50,35 @@ __global__ __launch_bounds__(BC_THREADS) void block_copy_kernel(const BlockOp* _
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BC_THREADS) void block_copy_kernel(const BlockOp* __restrict__ ops,
+                                                                const CopyItem* __restrict__ items,
+                                                                const CopyTask* __restrict__ tasks, int ncols_rt,
+                                                                T* __restrict__ dst, long long dst_stride,
+                                                                const T* __restrict__ src0, long long s0_stride,
+                                                                const T* __restrict__ src1, long long s1_stride) {
+  block_copy_body(ops, items, tasks[blockIdx.x], blockIdx.y, ncols_rt, dst, dst_stride, src0, s0_stride, src1,
+                  s1_stride);
+}
+
 int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
                       int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
                       const double* src1, long long s1_stride, long long batch, hipStream_t st) {
   if (ntasks <= 0 || batch <= 0) return HPS_OK;
   dim3 grid((unsigned)ntasks, (unsigned)batch);
-  hipLaunchKernelGGL(block_copy_kernel, grid, dim3(BC_THREADS), 0, st, dev_ops, dev_items, dev_tasks, ncols_rt, dst,
-                     dst_stride, src0, s0_stride, src1, s1_stride);
+  hipLaunchKernelGGL(block_copy_kernel<double>, grid, dim3(BC_THREADS), 0, st, dev_ops, dev_items, dev_tasks, ncols_rt,
+                     dst, dst_stride, src0, s0_stride, src1, s1_stride);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int block_copy_launch_f32(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
+                          int ncols_rt, float* dst, long long dst_stride, const float* src0, long long s0_stride,
+                          const float* src1, long long s1_stride, long long batch, hipStream_t st) {
+  if (ntasks <= 0 || batch <= 0) return HPS_OK;
+  dim3 grid((unsigned)ntasks, (unsigned)batch);
+  hipLaunchKernelGGL(block_copy_kernel<float>, grid, dim3(BC_THREADS), 0, st, dev_ops, dev_items, dev_tasks, ncols_rt,
+                     dst, dst_stride, src0, s0_stride, src1, s1_stride);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
@@ -70,31 +92,25 @@ int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const C
 constexpr int SRC_THREADS = 256;
 constexpr int SRC_MAXR = 16;
 
-template <int RPT>
-__global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __restrict__ LUall,
-                                                               const int* __restrict__ permall,
-                                                               const int* __restrict__ posall,
-                                                               const double* __restrict__ src, const int* __restrict__ Ii,
-                                                               int NI, int npts, long long nl, int nrhs,
-                                                               double* __restrict__ vout, int NRcap) {
-  __shared__ double s_y[2][SRC_MAXR];
-  extern __shared__ int s_int[];  // perm[NI], pos[NI]
-  int* s_perm = s_int;
-  int* s_pos = s_int + NI;
-  const long long leaf = blockIdx.x;
-  const double* LU = LUall + leaf * (long long)NI * NI;
+// Body shared by the single-operator, the batched (cross-operator) and the
+// fp32 launches: one workgroup solves one leaf in precision T.  src(j, k) is
+// the source of rhs j at interior point k (as double); the result for rhs j
+// goes to v[j * NI + k].
+template <int RPT, typename T, class Src>
+__device__ __forceinline__ void leaf_src_body(const T* __restrict__ LU, const int* __restrict__ perm_g,
+                                              const int* __restrict__ pos_g, Src src, int NI, int nrhs,
+                                              T* __restrict__ v, int* s_perm, int* s_pos, T (*s_y)[SRC_MAXR]) {
   const int tid = threadIdx.x;
   for (int i = tid; i < NI; i += SRC_THREADS) {
-    s_perm[i] = permall[leaf * NI + i];
-    s_pos[i] = posall[leaf * NI + i];
+    s_perm[i] = perm_g[i];
+    s_pos[i] = pos_g[i];
   }
-  double b[RPT][SRC_MAXR];
+  T b[RPT][SRC_MAXR];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + SRC_THREADS * i;
 #pragma unroll
-    for (int j = 0; j < SRC_MAXR; ++j)
-      b[i][j] = (row < NI && j < nrhs) ? src[(long long)j * nl * npts + leaf * npts + Ii[row]] : 0.0;
+    for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? (T)src(j, row) : T(0);
   }
   __syncthreads();
   int mypos[RPT];
@@ -120,7 +136,7 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
     for (int i = 0; i < RPT; ++i) {
       const int row = tid + SRC_THREADS * i;
       if (row < NI && mypos[i] > s) {
-        const double l = LU[row + (long long)s * NI];
+        const T l = LU[row + (long long)s * NI];
 #pragma unroll
         for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= l * s_y[buf][j];
       }
@@ -132,7 +148,7 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
     const int pr = __builtin_amdgcn_readfirstlane(s_perm[s]);  // uniform: scalar branches below
     if (tid == pr % SRC_THREADS) {
       const int ip = pr / SRC_THREADS;
-      const double dinv = 1.0 / LU[pr + (long long)s * NI];
+      const T dinv = T(1) / LU[pr + (long long)s * NI];
 #pragma unroll
       for (int i = 0; i < RPT; ++i)
         if (i == ip)
@@ -147,14 +163,13 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
     for (int i = 0; i < RPT; ++i) {
       const int row = tid + SRC_THREADS * i;
       if (row < NI && mypos[i] < s) {
-        const double u = LU[row + (long long)s * NI];
+        const T u = LU[row + (long long)s * NI];
 #pragma unroll
         for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= u * s_y[buf][j];
       }
     }
   }
   // unknown pos[r] sits in row r
-  double* v = vout + leaf * (long long)NRcap * NI;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + SRC_THREADS * i;
@@ -163,6 +178,23 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __r
     for (int j = 0; j < SRC_MAXR; ++j)
       if (j < nrhs) v[(long long)j * NI + mypos[i]] = b[i][j];
   }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __restrict__ LUall,
+                                                               const int* __restrict__ permall,
+                                                               const int* __restrict__ posall,
+                                                               const double* __restrict__ src, const int* __restrict__ Ii,
+                                                               int NI, int npts, long long nl, int nrhs,
+                                                               double* __restrict__ vout, int NRcap) {
+  __shared__ double s_y[2][SRC_MAXR];
+  extern __shared__ int s_int[];  // perm[NI], pos[NI]
+  const long long leaf = blockIdx.x;
+  const double* f = src + leaf * npts;
+  const long long rstride = nl * npts;
+  auto at = [=](int j, int k) { return f[(long long)j * rstride + Ii[k]]; };
+  leaf_src_body<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI,
+                             nrhs, vout + leaf * (long long)NRcap * NI, s_int, s_int + NI, s_y);
 }
 
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
@@ -193,22 +225,20 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
 constexpr int OUT_THREADS = 256;
 constexpr int OUT_MAXR = 16;
 
-__global__ __launch_bounds__(OUT_THREADS) void leaf_out_kernel(const double* __restrict__ Yall, const double* __restrict__ P,
-                                                               const double* __restrict__ gall, const double* __restrict__ vall,
-                                                               const int* __restrict__ Ii, const int* __restrict__ Ie,
-                                                               int NI, int NE, int NB, int npts, long long nl, int nrhs,
-                                                               int NRcap, double* __restrict__ u) {
-  extern __shared__ double s_g[];  // [NB][OUT_MAXR]
-  const long long leaf = blockIdx.x;
+// Body shared by the single-operator and the batched launches: one
+// workgroup per leaf; g holds the leaf's boundary data [rhs][NB] (NRcap
+// stride), out(j, pt, value) stores u of rhs j at leaf point pt.
+template <class Out>
+__device__ __forceinline__ void leaf_out_body(const double* __restrict__ Y, const double* __restrict__ P,
+                                              const double* __restrict__ g, const double* __restrict__ v,
+                                              const int* __restrict__ Ii, const int* __restrict__ Ie, int NI, int NE,
+                                              int NB, int npts, int nrhs, Out out, double* s_g) {
   const int tid = threadIdx.x;
-  const double* g = gall + leaf * (long long)NRcap * NB;
   for (int e = tid; e < NB * OUT_MAXR; e += OUT_THREADS) {
     const int c = e / OUT_MAXR, j = e % OUT_MAXR;
     s_g[e] = j < nrhs ? g[(long long)j * NB + c] : 0.0;
   }
   __syncthreads();
-  const double* Y = Yall + leaf * (long long)NI * NB;
-  const double* v = vall ? vall + leaf * (long long)NRcap * NI : nullptr;
   for (int k = tid; k < npts; k += OUT_THREADS) {
     double acc[OUT_MAXR];
 #pragma unroll
@@ -236,8 +266,22 @@ __global__ __launch_bounds__(OUT_THREADS) void leaf_out_kernel(const double* __r
     }
 #pragma unroll
     for (int j = 0; j < OUT_MAXR; ++j)
-      if (j < nrhs) u[(long long)j * nl * npts + leaf * npts + pt] = acc[j];
+      if (j < nrhs) out(j, pt, acc[j]);
   }
+}
+
+__global__ __launch_bounds__(OUT_THREADS) void leaf_out_kernel(const double* __restrict__ Yall, const double* __restrict__ P,
+                                                               const double* __restrict__ gall, const double* __restrict__ vall,
+                                                               const int* __restrict__ Ii, const int* __restrict__ Ie,
+                                                               int NI, int NE, int NB, int npts, long long nl, int nrhs,
+                                                               int NRcap, double* __restrict__ u) {
+  extern __shared__ double s_g[];  // [NB][OUT_MAXR]
+  const long long leaf = blockIdx.x;
+  double* ul = u + leaf * npts;
+  const long long rstride = nl * npts;
+  auto out = [=](int j, int pt, double val) { ul[(long long)j * rstride + pt] = val; };
+  leaf_out_body(Yall + leaf * (long long)NI * NB, P, gall + leaf * (long long)NRcap * NB,
+                vall ? vall + leaf * (long long)NRcap * NI : nullptr, Ii, Ie, NI, NE, NB, npts, nrhs, out, s_g);
 }
 
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
@@ -256,6 +300,285 @@ int leaf_out_launch(const double* Y, const double* P, const double* g, const dou
   }
   hipLaunchKernelGGL(leaf_out_kernel, dim3((unsigned)nl), dim3(OUT_THREADS), shm, st, Y, P, g, v, Ii, Ie, NI, NE, NB,
                      npts, nl, nrhs, NRcap, u);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Adjoint (transposed) solve pieces.
+// ---------------------------------------------------------------------------
+// out[leaf][r][k] = w[r][leaf][idx[k]]  (k < n)
+__global__ void leaf_gather_pts_kernel(const double* __restrict__ w, const int* __restrict__ idx, int n, int npts,
+                                       long long nl, int nrhs, int NRcap, double* __restrict__ out) {
+  const long long leaf = blockIdx.y;
+  const int r = blockIdx.z;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    out[(leaf * NRcap + r) * n + k] = w[((long long)r * nl + leaf) * npts + idx[k]];
+}
+
+int leaf_gather_pts_launch(const double* w, const int* idx, int n, int npts, long long nl, int nrhs, int NRcap,
+                           double* out, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nl, (unsigned)nrhs);
+  hipLaunchKernelGGL(leaf_gather_pts_kernel, grid, dim3(256), 0, st, w, idx, n, npts, nl, nrhs, NRcap, out);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// lam[r][leaf][pt] = interior value fint[leaf][r][k] at pt = Ii[k], 0 at exterior points
+__global__ void leaf_scatter_int_kernel(const double* __restrict__ fint, const int* __restrict__ pos_i, int ni,
+                                        int npts, long long nl, int nrhs, int NRcap, double* __restrict__ lam) {
+  const long long leaf = blockIdx.y;
+  const int r = blockIdx.z;
+  for (int pt = blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += gridDim.x * blockDim.x) {
+    const int k = pos_i[pt];
+    lam[((long long)r * nl + leaf) * npts + pt] = k >= 0 ? fint[(leaf * NRcap + r) * ni + k] : 0.0;
+  }
+}
+
+int leaf_scatter_int_launch(const double* fint, const int* pos_i, int ni, int npts, long long nl, int nrhs, int NRcap,
+                            double* lam, hipStream_t st) {
+  dim3 grid((unsigned)((npts + 255) / 256), (unsigned)nl, (unsigned)nrhs);
+  hipLaunchKernelGGL(leaf_scatter_int_kernel, grid, dim3(256), 0, st, fint, pos_i, ni, npts, nl, nrhs, NRcap, lam);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// Transposed leaf solve  x = L_ii^{-T} b  with the stored factors
+// (A = P^T L U,  A^T = U^T L^T P):  U^T y = b (forward), L^T z = y (backward),
+// x[perm[k]] = z_k.  b: [leaf][NRcap][NI] in natural interior order (read
+// from `bin`); x written to `xout` in the same layout.
+template <int RPT>
+__global__ __launch_bounds__(SRC_THREADS) void leaf_src_t_kernel(const double* __restrict__ LUall,
+                                                                 const int* __restrict__ permall,
+                                                                 const double* __restrict__ bin, int NI, int nrhs,
+                                                                 int NRcap, double* __restrict__ xout) {
+  __shared__ double s_y[2][SRC_MAXR];
+  extern __shared__ int s_perm[];
+  const long long leaf = blockIdx.x;
+  const double* LU = LUall + leaf * (long long)NI * NI;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NI; i += SRC_THREADS) s_perm[i] = permall[leaf * NI + i];
+  const double* b = bin + leaf * (long long)NRcap * NI;
+  double y[RPT][SRC_MAXR];  // thread owns natural indices m = tid + 256 i
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int mm = tid + SRC_THREADS * i;
+#pragma unroll
+    for (int j = 0; j < SRC_MAXR; ++j) y[i][j] = (mm < NI && j < nrhs) ? b[(long long)j * NI + mm] : 0.0;
+  }
+  __syncthreads();
+  // U^T y = b:  y_k = b_k / U(k,k);  b_m -= U(k, m) y_k  for m > k,  U(k, m) = LU[perm[k], m]
+  for (int k = 0; k < NI; ++k) {
+    const int buf = k & 1;
+    const int pk = __builtin_amdgcn_readfirstlane(s_perm[k]);
+    if (tid == k % SRC_THREADS) {
+      const double dinv = 1.0 / LU[pk + (long long)k * NI];
+      const int ik = k / SRC_THREADS;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == ik)
+#pragma unroll
+          for (int j = 0; j < SRC_MAXR; ++j) {
+            y[i][j] *= dinv;
+            s_y[buf][j] = y[i][j];
+          }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int mm = tid + SRC_THREADS * i;
+      if (mm > k && mm < NI) {
+        const double u = LU[pk + (long long)mm * NI];
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) y[i][j] -= u * s_y[buf][j];
+      }
+    }
+  }
+  // L^T z = y:  z_k = y_k;  y_m -= L(k, m) z_k  for m < k,  L(k, m) = LU[perm[k], m]
+  for (int k = NI - 1; k >= 0; --k) {
+    const int buf = k & 1;
+    const int pk = __builtin_amdgcn_readfirstlane(s_perm[k]);
+    if (tid == k % SRC_THREADS) {
+      const int ik = k / SRC_THREADS;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == ik)
+#pragma unroll
+          for (int j = 0; j < SRC_MAXR; ++j) s_y[buf][j] = y[i][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int mm = tid + SRC_THREADS * i;
+      if (mm < k) {
+        const double l = LU[pk + (long long)mm * NI];
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) y[i][j] -= l * s_y[buf][j];
+      }
+    }
+  }
+  // x[perm[k]] = z_k (thread of index k holds z_k)
+  double* x = xout + leaf * (long long)NRcap * NI;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int k = tid + SRC_THREADS * i;
+    if (k >= NI) continue;
+    const int pk = s_perm[k];
+#pragma unroll
+    for (int j = 0; j < SRC_MAXR; ++j)
+      if (j < nrhs) x[(long long)j * NI + pk] = y[i][j];
+  }
+}
+
+int leaf_src_t_launch(const double* LU, const int* perm, const double* b, int NI, long long nl, int nrhs, int NRcap,
+                      double* x, hipStream_t st) {
+  if (nrhs > SRC_MAXR) {
+    set_error("leaf_src_t: at most 16 right-hand sides per pass");
+    return HPS_EINVAL;
+  }
+  const size_t shm = NI * sizeof(int);
+  const int rpt = (NI + SRC_THREADS - 1) / SRC_THREADS;
+  dim3 grid((unsigned)nl), block(SRC_THREADS);
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL(leaf_src_t_kernel<1>, grid, block, shm, st, LU, perm, b, NI, nrhs, NRcap, x); break;
+    case 2: hipLaunchKernelGGL(leaf_src_t_kernel<2>, grid, block, shm, st, LU, perm, b, NI, nrhs, NRcap, x); break;
+    default:
+      set_error("leaf_src_t: too many interior points");
+      return HPS_EUNSUPPORTED;
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve over several operators (one launch per pass stage).
+// ---------------------------------------------------------------------------
+template <class J>
+__device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, long long blk) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first_block <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(BC_THREADS) void block_copy_multi_kernel(const CopyJob* __restrict__ jobs, int njobs) {
+  const CopyJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const long long local = blockIdx.x - J.first_block;
+  const int task = (int)(local % J.ntasks);
+  const long long b = local / J.ntasks;
+  block_copy_body(J.ops, J.items, J.tasks[task], b, J.ncols_rt, J.dst, J.dst_stride, J.src0, J.s0_stride, J.src1,
+                  J.s1_stride);
+}
+
+// root boundary data of every job: g0[j][i] = bdry[j][i]
+__global__ __launch_bounds__(BC_THREADS) void root_gather_multi_kernel(const LeafJob* __restrict__ jobs) {
+  const LeafJob& J = jobs[blockIdx.z];
+  const int j = blockIdx.y;
+  if (j >= J.nrhs) return;
+  const double* src = J.bdry[0];
+#pragma unroll
+  for (int k = 1; k < kBatchMaxRhs; ++k)
+    if (k == j) src = J.bdry[k];
+  for (int i = blockIdx.x * BC_THREADS + threadIdx.x; i < J.nb0; i += gridDim.x * BC_THREADS)
+    J.g0[(long long)j * J.nb0 + i] = src[i];
+}
+
+__global__ __launch_bounds__(SRC_THREADS) void leaf_src_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
+  __shared__ double s_y[2][SRC_MAXR];
+  extern __shared__ int s_int[];
+  const LeafJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const long long leaf = blockIdx.x - J.first_block;
+  const int NI = J.NI, npts = J.npts;
+  const int* Ii = J.Ii;
+  auto at = [&](int j, int k) {
+    const double* f = J.src[j];
+    return f ? f[leaf * npts + Ii[k]] : 0.0;
+  };
+  leaf_src_body<1, double>(J.LU + leaf * (long long)NI * NI, J.perm + leaf * NI, J.pos + leaf * NI, at, NI, J.nrhs,
+                           J.v + leaf * (long long)J.NRcap * NI, s_int, s_int + NI, s_y);
+}
+
+__global__ __launch_bounds__(OUT_THREADS) void leaf_out_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
+  extern __shared__ double s_g[];
+  const LeafJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const long long leaf = blockIdx.x - J.first_block;
+  const int NI = J.NI, NB = J.NB, npts = J.npts;
+  auto out = [&](int j, int pt, double val) { J.u[j][leaf * npts + pt] = val; };
+  leaf_out_body(J.Y + leaf * (long long)NI * NB, J.P, J.g + leaf * (long long)J.NRcap * NB,
+                J.v ? J.v + leaf * (long long)J.NRcap * NI : nullptr, J.Ii, J.Ie, NI, J.NE, NB, npts, J.nrhs, out,
+                s_g);
+}
+
+int block_copy_multi_launch(const CopyJob* dev_jobs, int njobs, long long nblocks, hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return HPS_OK;
+  hipLaunchKernelGGL(block_copy_multi_kernel, dim3((unsigned)nblocks), dim3(BC_THREADS), 0, st, dev_jobs, njobs);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int root_gather_multi_launch(const LeafJob* dev_jobs, int njobs, int max_nb0, hipStream_t st) {
+  if (njobs <= 0) return HPS_OK;
+  dim3 grid((unsigned)std::min(64, (max_nb0 + BC_THREADS - 1) / BC_THREADS), kBatchMaxRhs, (unsigned)njobs);
+  hipLaunchKernelGGL(root_gather_multi_kernel, grid, dim3(BC_THREADS), 0, st, dev_jobs);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int leaf_src_multi_launch(const LeafJob* dev_jobs, int njobs, long long nblocks, int max_ni, hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return HPS_OK;
+  if (max_ni > SRC_THREADS) {
+    set_error("batched solve: at most 256 interior points per leaf");
+    return HPS_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(leaf_src_multi_kernel, dim3((unsigned)nblocks), dim3(SRC_THREADS), 2 * max_ni * sizeof(int), st,
+                     dev_jobs, njobs);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int leaf_out_multi_launch(const LeafJob* dev_jobs, int njobs, long long nblocks, int max_nb, hipStream_t st) {
+  if (njobs <= 0 || nblocks <= 0) return HPS_OK;
+  const size_t shm = (size_t)max_nb * OUT_MAXR * sizeof(double);
+  if (shm > 65536) {
+    set_error("batched solve: leaf boundary too large");
+    return HPS_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(leaf_out_multi_kernel, dim3((unsigned)nblocks), dim3(OUT_THREADS), shm, st, dev_jobs, njobs);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fp32 leaf solve of the refined (mixed-precision) solve: v = L_ii^{-1} r with
+// fp32 copies of the LU factors; r is an fp64 interior-point residual
+// [leaf][NRcap][NI].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SRC_THREADS) void leaf_src_f32_kernel(const float* __restrict__ LUall,
+                                                                   const int* __restrict__ permall,
+                                                                   const int* __restrict__ posall,
+                                                                   const double* __restrict__ r, int NI, int nrhs,
+                                                                   int NRcap, float* __restrict__ vout) {
+  __shared__ float s_y[2][SRC_MAXR];
+  extern __shared__ int s_int[];
+  const long long leaf = blockIdx.x;
+  const double* rl = r + leaf * (long long)NRcap * NI;
+  auto at = [=](int j, int k) { return rl[(long long)j * NI + k]; };
+  leaf_src_body<1, float>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
+                          vout + leaf * (long long)NRcap * NI, s_int, s_int + NI, s_y);
+}
+
+int leaf_src_f32_launch(const float* LU, const int* perm, const int* pos, const double* r, int NI, long long nl,
+                        int nrhs, int NRcap, float* v, hipStream_t st) {
+  if (nrhs > SRC_MAXR || NI > SRC_THREADS) {
+    set_error("leaf_src_f32: at most 16 right-hand sides and 256 interior points");
+    return HPS_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(leaf_src_f32_kernel, dim3((unsigned)nl), dim3(SRC_THREADS), 2 * NI * sizeof(int), st, LU, perm,
+                     pos, r, NI, nrhs, NRcap, v);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

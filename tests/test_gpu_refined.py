@@ -1,0 +1,87 @@
+"""Mixed-precision solve (fp32 operator copies, fp64 residual refinement) on
+the GPU against the CPU oracle: rel. l_inf <= 1e-8 per right-hand side after
+the default number of refinement sweeps, the error shrinking sweep by sweep,
+and the fp64 solve of the same operator unchanged by the fp32 copies."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import oracle_solve, rel_inf, rhs, say, var_coeffs
+from oracle import hps as ohps
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+TOL_REFINED = 1e-8
+
+
+def _refined(op, bd, src, sweeps):
+    import paper_2503_17535_amd as hp
+    op.refine_sweeps(sweeps)
+    return op.solve(bd, src, precision=hp.FP32_REFINED).cpu().numpy()
+
+
+@pytest.mark.parametrize("p,L,nrhs,k", [(8, 2, 2, 0.0), (12, 3, 3, 5.0), (16, 3, 2, 10.0)])
+def test_refined_matches_oracle(p, L, nrhs, k):
+    import paper_2503_17535_amd as hp
+    say(f"[case] refined p={p} L={L} nrhs={nrhs} k={k}")
+    tree = ohps.Tree(2, L)
+    disc = ohps.LeafDisc(2, p)
+    pts = tree.leaf_points(disc)
+    bpts = tree.root_boundary_points(disc)
+    c = var_coeffs(pts, seed=5, k=k)
+    bd, src = rhs(pts, bpts, nrhs, seed=5)
+    ref = oracle_solve(2, p, L, c, bd, src)
+    op = hp.build(hp.tree(2, L), p, torch.tensor(c, device=DEV), flags=hp.FLAG_FP32_COPY)
+    bd_t, src_t = torch.tensor(bd, device=DEV), torch.tensor(src, device=DEV)
+    errs = [rel_inf(_refined(op, bd_t, src_t, s), ref) for s in (1, 2, 4, 6)]
+    say("[case] rel err after 1/2/4/6 sweeps: " + " ".join(f"{e:.2e}" for e in errs))
+    u64 = op.solve(bd_t, src_t).cpu().numpy()
+    assert rel_inf(u64, ref) < 1e-10
+    assert errs[-1] < TOL_REFINED
+    assert errs[1] < errs[0]
+    op.free()
+
+
+def test_refined_no_source():
+    import paper_2503_17535_amd as hp
+    say("[case] refined, no source")
+    p, L = 10, 3
+    tree = ohps.Tree(2, L)
+    disc = ohps.LeafDisc(2, p)
+    pts = tree.leaf_points(disc)
+    bpts = tree.root_boundary_points(disc)
+    c = var_coeffs(pts, seed=6, k=3.0)
+    bd, _ = rhs(pts, bpts, 2, seed=6)
+    ref = oracle_solve(2, p, L, c, bd, None)
+    op = hp.build(hp.tree(2, L), p, torch.tensor(c, device=DEV), flags=hp.FLAG_FP32_COPY)
+    u = op.solve(torch.tensor(bd, device=DEV), None, precision=hp.FP32_REFINED).cpu().numpy()
+    err = rel_inf(u, ref)
+    say(f"[case] rel err {err:.2e}")
+    assert err < TOL_REFINED
+    op.free()
+
+
+def test_refined_full_size_helmholtz():
+    # 2D Helmholtz k = 40, depth 6 (4096 leaves), p = 16, 16 right-hand sides;
+    # two of them checked against the oracle
+    import paper_2503_17535_amd as hp
+    say("[case] refined, Helmholtz k=40 L=6 p=16, 16 rhs")
+    p, L, nrhs = 16, 6, 16
+    t = hp.tree(2, L)
+    pts = hp.leaf_points(t, p)
+    bpts = hp.boundary_points(t, p)
+    c, bd, src = W.helmholtz_inputs(pts, bpts, 40.0, nrhs)
+    op = hp.build(t, p, torch.tensor(c, device=DEV), flags=hp.FLAG_FP32_COPY)
+    bd_t, src_t = torch.tensor(bd, device=DEV), torch.tensor(src, device=DEV)
+    sel = [0, nrhs - 1]
+    ref = oracle_solve(2, p, L, c, bd[sel], src[sel])
+    errs = []
+    for s in (2, 4, 6, 8):
+        u = _refined(op, bd_t, src_t, s)
+        errs.append(rel_inf(u[sel], ref))
+    say("[case] rel err vs oracle after 2/4/6/8 sweeps: " + " ".join(f"{e:.2e}" for e in errs))
+    op.refine_sweeps(6)
+    assert errs[2] < TOL_REFINED
+    op.free()

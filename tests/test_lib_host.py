@@ -93,3 +93,28 @@ def test_invalid_p_and_null_pointers_rejected():
     assert rc == hp.HPS_EINVAL and not h.value
     assert b"NULL" in L.hps_last_error()
     assert L.hps_solve(None, None, None, None, 1, 0, None) == hp.HPS_EINVAL
+
+
+@pytest.mark.parametrize("d,p,L", [(2, 8, 2), (2, 16, 5), (3, 6, 1)])
+def test_interp_weights_match_oracle(d, p, L):
+    from oracle import adjoint as A
+    t = hp.tree(d, L)
+    g = np.random.default_rng(12)
+    xs = g.uniform(-0.9, 0.9, size=(40, d))
+    # points on leaf edges and corners: the lowest leaf index wins
+    h = 2.0 / 2 ** L
+    xs[0] = -1.0 + h
+    xs[1, 0] = -1.0 + 2 * h
+    xs[2] = 1.0
+    xs[3] = -1.0
+    leaf, w = hp.interp_weights(t, p, xs)
+    oleaf, ow = A.observation(ohps.Tree(d, L), p, xs)
+    assert np.array_equal(leaf, oleaf)
+    assert np.abs(w - ow).max() < 1e-13
+
+
+def test_interp_weights_reject_outside_points():
+    t = hp.tree(2, 2)
+    with pytest.raises(hp.HPSError) as e:
+        hp.interp_weights(t, 8, np.array([[0.0, 1.5]]))
+    assert e.value.code == hp.HPS_EINVAL

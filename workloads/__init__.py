@@ -286,3 +286,18 @@ def differentiation_inputs(leaf_pts: np.ndarray, bdry_pts: np.ndarray, k: float 
     src = eval_bumps(draw_source_bump(gr), leaf_pts, width=0.1)[None]
     return dict(q=q, q_star=eval_bumps(qs, leaf_pts, width=0.1), x_obs=x_obs,
                 bdry=bdry, src=src, k=float(k))
+
+
+
+def serving_arrivals(n: int = 4096, rate: float = 2000.0, nops: int = 8, pool: int = 8,
+                     config: int = 4):
+    """Open-loop request stream: exponential inter-arrival times at ``rate``
+    per second, target operator uniform over ``nops``, and which of the
+    operator's ``pool`` seeded right-hand sides the request carries.
+
+    Returns (t_arrival [n] seconds, op [n], rhs [n])."""
+    g = rng(config, 7)
+    t = np.cumsum(g.exponential(1.0 / rate, size=n))
+    ops = g.integers(0, nops, size=n)
+    rhs = g.integers(0, pool, size=n)
+    return t, ops, rhs

@@ -73,12 +73,119 @@ def cpu_baseline(seconds_budget: float = 30.0):
             "build_leaves_per_s": nl / (t1 - t0), "solves_per_s": NRHS / (t2 - t1)}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the leaf kernel from its committed rocprofv3
+    counter summary, if that summary was taken on the current source."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "leaf2d_factor_kernel_p16_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2503_17535_amd", "csrc", "leaf2d.hip")
+    try:
+        txt = open(prof).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if f"sha256 prefix: {h}" not in txt:
+            return None
+        for line in txt.splitlines():
+            if line.startswith("traffic_bytes_per_launch:"):
+                return float(line.split(":")[1])
+    except OSError:
+        pass
+    return None
+
+
+def _median_ms(fn, reps=5):
+    import numpy as np
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def solve_rates(hp, t, c_d, b_d, s_d, sz):
+    """Solve-only rates of one resident operator: 16 and 1 right-hand sides
+    (median of 5 after a warm-up)."""
+    op = hp.build(t, P, c_d)
+    u16 = op.solve(b_d, s_d)
+    ms16 = _median_ms(lambda: op.solve(b_d, s_d, out=u16))
+    b1, s1 = b_d[:1].contiguous(), s_d[:1].contiguous()
+    u1 = op.solve(b1, s1)
+    ms1 = _median_ms(lambda: op.solve(b1, s1, out=u1))
+    op.free()
+    return {"solve16_ms": ms16, "solves_per_s_nrhs16": NRHS * 1e3 / ms16,
+            "solve1_ms": ms1, "solves_per_s_nrhs1": 1e3 / ms1}
+
+
+def refined_solve(hp, t, c_d, b_d, s_d):
+    """Mixed-precision solve of the same workload (fp32 operator copies, fp64
+    residual refinement): time and the max relative difference to the fp64
+    solve of the same operator (the tests check both against the oracle)."""
+    import torch
+    op = hp.build(t, P, c_d, flags=hp.FLAG_FP32_COPY)
+    u64 = op.solve(b_d, s_d)
+    sweeps = op.refine_sweeps()
+    u = op.solve(b_d, s_d, precision=hp.FP32_REFINED)
+    ms = _median_ms(lambda: op.solve(b_d, s_d, out=u, precision=hp.FP32_REFINED))
+    diff = ((u - u64).abs().amax(dim=(1, 2)) / u64.abs().amax(dim=(1, 2))).max().item()
+    op.free()
+    torch.cuda.synchronize()
+    return {"sweeps": sweeps, "solve16_ms": ms, "solves_per_s": NRHS * 1e3 / ms,
+            "max_rel_diff_to_fp64": diff}
+
+
+def serving(hp, W, n_req=4096, rate=2000.0, pool=4):
+    """Continuous-batching serving: 8 resident Helmholtz operators (depths 4-7,
+    p 12/16, k 10-40), 4096 requests with exponential inter-arrival times at
+    2000/s replayed against the wall clock, each one right-hand side (Fourier
+    boundary data + one source bump) for a uniformly chosen operator; fp64.
+    Latency = device completion - scheduled arrival."""
+    import numpy as np
+    import torch
+    from paper_2503_17535_amd.serve import Request, Server, latency_stats
+    dev = torch.device("cuda:0")
+    ops, pools = [], []
+    for k, (L, p, kw) in enumerate(W.SERVING_OPS):
+        tt = hp.tree(2, L)
+        pts = hp.leaf_points(tt, p)
+        bpts = hp.boundary_points(tt, p)
+        c, bd, src = W.helmholtz_inputs(pts, bpts, kw, pool, config=4, op_seed=k)
+        ops.append(hp.build(tt, p, torch.tensor(c, device=dev)))
+        pools.append((torch.tensor(bd, device=dev), torch.tensor(src, device=dev)))
+    resident = sum(op.nbytes for op in ops)
+    ta, opi, rhs = W.serving_arrivals(n_req, rate, len(ops), pool)
+    # warm-up pass (not measured)
+    warm = [Request(op=i % len(ops), bdry=pools[i % len(ops)][0][0], src=pools[i % len(ops)][1][0],
+                    t_arrival=0.0) for i in range(2 * len(ops))]
+    srv = Server(ops)
+    srv.run(warm)
+    srv.batches.clear()
+    reqs = [Request(op=int(opi[i]), bdry=pools[opi[i]][0][rhs[i]], src=pools[opi[i]][1][rhs[i]],
+                    t_arrival=float(ta[i])) for i in range(n_req)]
+    srv.run(reqs)
+    torch.cuda.synchronize()
+    st = latency_stats(reqs)
+    st.update({"rate_per_s": rate, "operators": len(ops), "resident_GB": resident / 1e9,
+               "batches": len(srv.batches), "mean_batch": float(np.mean(srv.batches)), "precision": "fp64"})
+    srv.free()
+    for op in ops:
+        op.free()
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -87,6 +194,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        n = 256 * 2 ** 20 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}), flush=True)
+        return
 
     import paper_2503_17535_amd as hp
     import workloads as W
@@ -145,7 +262,7 @@ def main():
     achieved = flops / (leaf_ms * 1e-3) / 1e12
     roofline = {"kernel": "leaf2d_factor_kernel<16>", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "algorithmic_flops_per_launch": flops, "avg_launch_ms": leaf_ms}
+                "traffic": measured_traffic(), "algorithmic_flops_per_launch": flops, "avg_launch_ms": leaf_ms}
 
     out = {
         "metric": METRIC,
@@ -164,6 +281,10 @@ def main():
         "stages_ms": stages,
         "roofline": roofline,
     }
+    out.update(solve_rates(hp, t, c_d, b_d, s_d, sz))
+    out["refined"] = refined_solve(hp, t, c_d, b_d, s_d)
+    if not args.no_serving:
+        out["serving"] = serving(hp, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -373,6 +373,107 @@ int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
   return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
 }
 
+// Block inversion of the merge matrix D (m = 2s + r) with interfaces ordered
+// [P1 | P2 | R], D(P1, P2) = D(P2, P1) = 0:
+//   A_b^{-1} = D(P_b, P_b)^{-1}                    (batched Gauss-Jordan, 2 per node)
+//   X_b = A_b^{-1} D(P_b, R),  Y_b = D(R, P_b) A_b^{-1}
+//   Sc  = D(R, R) - sum_b D(R, P_b) X_b,  Sc^{-1}  (Gauss-Jordan)
+//   Z(R, R) = Sc^{-1},  Z(P_b, R) = -X_b Sc^{-1},  Z(R, P_b) = -Sc^{-1} Y_b,
+//   Z(P_b, P_b') = delta_bb' A_b^{-1} - Z(P_b, R) Y_b'
+// It is exact block elimination of D in an order that skips D's zero
+// blocks; pivoting happens inside A_b and Sc.
+int plan_schur(hps_op* op, LevelPlan& P, int schur_p) {
+  const int n = P.n, m = P.m;
+  const long long nm = P.nm, mm = (long long)m * m;
+  const int s = schur_p * n, r = m - 2 * s;
+  P.schur = true;
+  P.sP = s;
+  P.sR = r;
+  P.Ablk = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * s, false);
+  P.Ainv = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * s, false);
+  P.Xs = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * r, false);
+  P.Ys = (double*)op_alloc(op, sizeof(double) * nm * 2 * r * s, false);
+  P.Sc = (double*)op_alloc(op, sizeof(double) * nm * r * r, false);
+  P.Scinv = (double*)op_alloc(op, sizeof(double) * nm * r * r, false);
+  if (!P.Ablk || !P.Ainv || !P.Xs || !P.Ys || !P.Sc || !P.Scinv) {
+    set_error("device allocation failed (block inversion workspace)");
+    return HPS_ENOMEM;
+  }
+  HPS_TRY(plan_gj(op, &P.gjA, P.Ablk, P.Ainv, s, 2 * nm));
+  HPS_TRY(plan_gj(op, &P.gjS, P.Sc, P.Scinv, r, nm));
+  const long long s2 = 2LL * s * s, sr2 = 2LL * s * r, r2 = (long long)r * r;
+  {  // A_b = D(P_b, P_b)
+    std::vector<BlockOp> ops;
+    for (int b = 0; b < 2; ++b) {
+      BlockOp o = make_op((long long)b * s * s, s, s, s);
+      op_src(o, 0, (long long)b * s + (long long)b * s * m, m);
+      ops.push_back(o);
+    }
+    add_copy(op, ops, &P.copyA);
+  }
+  {  // X_b = A_b^{-1} D(P_b, R);  Y_b = D(R, P_b) A_b^{-1}
+    std::vector<GemmGroup> gs;
+    for (int b = 0; b < 2; ++b) {
+      gs.push_back(make_group(P.Ainv + (long long)b * s * s, s2, s, P.Dbuf + (long long)b * s + 2LL * s * m, mm, m,
+                              P.Xs + (long long)b * s * r, sr2, s, s, r, s, 1.0, 0.0, nm));
+      gs.push_back(make_group(P.Dbuf + 2LL * s + (long long)b * s * m, mm, m, P.Ainv + (long long)b * s * s, s2, s,
+                              P.Ys + (long long)b * r * s, sr2, r, r, s, s, 1.0, 0.0, nm));
+    }
+    add_gemm(op, gs, &P.gemmXY);
+  }
+  {  // Sc = D(R, R) - sum_b D(R, P_b) X_b
+    GemmGroup g = make_group(P.Dbuf + 2LL * s, mm, m, P.Xs, sr2, s, P.Sc, r2, r, r, r, s, -1.0, 1.0, nm,
+                             P.Dbuf + 2LL * s + 2LL * s * m, mm, m);
+    g.nseg = 2;
+    for (int b = 0; b < 2; ++b) {
+      g.aseg[b] = (long long)b * s * m;
+      g.bseg[b] = (long long)b * s * r;
+    }
+    add_gemm(op, {g}, &P.gemmSc);
+  }
+  {  // Z(P_b, R) = -X_b Sc^{-1};  Z(R, P_b) = -Sc^{-1} Y_b
+    std::vector<GemmGroup> gs;
+    for (int b = 0; b < 2; ++b) {
+      gs.push_back(make_group(P.Xs + (long long)b * s * r, sr2, s, P.Scinv, r2, r,
+                              P.Z + (long long)b * s + 2LL * s * m, mm, m, s, r, r, -1.0, 0.0, nm));
+      gs.push_back(make_group(P.Scinv, r2, r, P.Ys + (long long)b * r * s, sr2, r,
+                              P.Z + 2LL * s + (long long)b * s * m, mm, m, r, s, r, -1.0, 0.0, nm));
+    }
+    add_gemm(op, gs, &P.gemmZ1);
+  }
+  {  // Z(R, R) = Sc^{-1}
+    BlockOp o = make_op(2LL * s + 2LL * s * m, m, r, r);
+    op_src(o, 0, 0, r);
+    add_copy(op, {o}, &P.copyScZ);
+  }
+  {  // Z(P_b, P_b') = delta_bb' A_b^{-1} - Z(P_b, R) Y_b'
+    std::vector<GemmGroup> gs;
+    for (int b = 0; b < 2; ++b)
+      for (int c = 0; c < 2; ++c) {
+        GemmGroup g = make_group(P.Z + (long long)b * s + 2LL * s * m, mm, m, P.Ys + (long long)c * r * s, sr2, r,
+                                 P.Z + (long long)b * s + (long long)c * s * m, mm, m, s, s, r, -1.0,
+                                 b == c ? 1.0 : 0.0, nm, b == c ? P.Ainv + (long long)b * s * s : nullptr,
+                                 b == c ? s2 : 0, b == c ? s : 0);
+        gs.push_back(g);
+      }
+    add_gemm(op, gs, &P.gemmZPP);
+  }
+  return HPS_OK;
+}
+
+int run_schur(hps_op* op, LevelPlan& P, hipStream_t st) {
+  const long long mm = (long long)P.m * P.m, s2 = 2LL * P.sP * P.sP, r2 = (long long)P.sR * P.sR;
+  HPS_TRY(run_copy(op, P.copyA, 0, P.Ablk, s2, P.Dbuf, mm, nullptr, 0, P.nm, st));
+  HPS_TRY(run_gj(op, P.gjA, st));
+  HPS_TRY(run_gemm(op, P.gemmXY, st));
+  HPS_TRY(run_gemm(op, P.gemmSc, st));
+  HPS_TRY(run_gj(op, P.gjS, st));
+  HPS_TRY(run_gemm(op, P.gemmZ1, st));
+  HPS_TRY(run_copy(op, P.copyScZ, 0, P.Z, mm, P.Scinv, r2, nullptr, 0, P.nm, st));
+  HPS_TRY(run_gemm(op, P.gemmZPP, st));
+  return HPS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // plan: allocations + every descriptor table
 // ---------------------------------------------------------------------------
@@ -489,7 +590,11 @@ int plan_op(hps_op* op) {
       set_error("device allocation failed (merge level)");
       return HPS_ENOMEM;
     }
-    HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));
+    if (m > gj_small_max()) {
+      HPS_TRY(plan_schur(op, P, G.schur_p));
+    } else {
+      HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));
+    }
     // --- D = sum over children touching interfaces i and j of T_c(face_i, face_j)
     {
       std::vector<BlockOp> ops;
@@ -706,7 +811,11 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
     const long long childstride = (long long)nd * P.nbc * P.nbc;
     stage_begin(op, names[lev < 12 ? lev : 11], st);
     HPS_TRY(run_copy(op, P.copyD, 0, P.Dbuf, (long long)P.m * P.m, Tchild, childstride, nullptr, 0, P.nm, st));
-    HPS_TRY(run_gj(op, P.gj, st));
+    if (P.schur) {
+      HPS_TRY(run_schur(op, P, st));
+    } else {
+      HPS_TRY(run_gj(op, P.gj, st));
+    }
     HPS_TRY(run_gemm(op, P.gemmS, st));
     HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)nd * P.dn * P.dn, Tchild, childstride, nullptr, 0, P.nm, st));
     if (P.Tp) {

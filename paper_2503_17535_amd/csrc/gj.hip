@@ -32,6 +32,7 @@ template <int TR, int TC, int RI, int RJ>
 __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restrict__ Din, double* __restrict__ Zout,
                                                            int m, int* __restrict__ flag) {
   constexpr int NT = TR * TC;
+  static_assert(64 % TR == 0, "a column group of TR lanes lies inside one wavefront");
   __shared__ double s_lcol[2][RI * TR];
   __shared__ double s_urow[2][RJ * TC];
   __shared__ int s_perm[RJ * TC], s_pos[RI * TR];
@@ -104,7 +105,12 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
             }
           }
       }
-      __syncthreads();
+      // s_urow entries of column tc + TC*s are read only by this thread's
+      // column group (TR lanes of one wavefront): a wavefront-level barrier
+      // orders the owner's LDS write before their reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int s = 0; s < RJ; ++s) {
         const double u = s_urow[buf][tc + TC * s];
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
   constexpr int NW = PANEL_THREADS / 64;
   __shared__ double s_ck[2][NW], s_cv[2][NW];
   __shared__ int s_cr[2][NW];
-  __shared__ double s_prow[2][NB];
+  __shared__ double s_cand[2][NW][NB];  // each wavefront's candidate pivot row
   __shared__ int s_piv[NB];
 
   const long long b = blockIdx.x;
@@ -231,28 +237,47 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
       for (int i = 0; i < RPT; ++i)
         if (!((used >> i) & 1u)) amax_merge(key, brow, val, pivot_key(a[i][0]), tid + PANEL_THREADS * i, a[i][0]);
       wave_argmax(key, brow, val);
+      // the lane holding this wavefront's candidate row publishes the row's
+      // panel entries with the candidate, so one barrier serves both the
+      // cross-wavefront argmax and the pivot-row broadcast
+      const int crow = __builtin_amdgcn_readfirstlane(brow);
       if (lane == 0) { s_ck[buf][wave] = key; s_cr[buf][wave] = brow; s_cv[buf][wave] = val; }
+      if (crow < m && tid == crow % PANEL_THREADS) {
+        const int ip = crow / PANEL_THREADS;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (i == ip) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) s_cand[buf][wave][cc] = a[i][cc];
+          }
+      }
       __syncthreads();
       key = s_ck[buf][0]; brow = s_cr[buf][0]; val = s_cv[buf][0];
+      int wbest = 0;
 #pragma unroll
-      for (int w = 1; w < NW; ++w) amax_merge(key, brow, val, s_ck[buf][w], s_cr[buf][w], s_cv[buf][w]);
+      for (int w = 1; w < NW; ++w) {
+        const double ok = s_ck[buf][w];
+        const int orow = s_cr[buf][w];
+        if (ok > key || (ok == key && orow < brow)) {
+          key = ok;
+          brow = orow;
+          val = s_cv[buf][w];
+          wbest = w;
+        }
+      }
       const int pr = __builtin_amdgcn_readfirstlane(brow);  // uniform: scalar branches below
+      const int wb = __builtin_amdgcn_readfirstlane(wbest);
       const double pv = val;
       if (tid == pr % PANEL_THREADS) {
         const int ip = pr / PANEL_THREADS;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
-          if (i == ip) {
-#pragma unroll
-            for (int cc = 0; cc < NB; ++cc) s_prow[buf][cc] = a[i][cc];
-            used |= 1u << i;
-          }
+          if (i == ip) used |= 1u << i;
         pos[pr] = k;
         piv[k] = pr;
         s_piv[c] = pr;
         if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
       }
-      __syncthreads();
       const double pinv = 1.0 / pv;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
@@ -261,7 +286,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
         const bool isp = row == pr;
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) {
-          const double u = (cc == 0 ? 1.0 : s_prow[buf][cc]) * pinv;
+          const double u = (cc == 0 ? 1.0 : s_cand[buf][wb][cc]) * pinv;
           a[i][cc] = isp ? u : ((cc == 0 ? 0.0 : a[i][cc]) - l * u);
         }
       }

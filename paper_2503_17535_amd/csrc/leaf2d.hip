@@ -50,6 +50,7 @@ struct Leaf2DCfg {
   static constexpr int AUG_LATE = EXTRA ? NC - RJ * TC : 0;
   static constexpr int SAUG = AUG_IN_SLOTS > AUG_LATE ? AUG_IN_SLOTS : AUG_LATE;
   static_assert(RJALL <= RJ + 1, "at most one late column block");
+  static_assert(64 % TR == 0, "a column group of TR lanes lies inside one wavefront");
   static_assert(!EXTRA || RJP >= 2, "late block needs a first pivot block to replay");
 };
 
@@ -206,7 +207,12 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
               if (r + s < NBLK) s_urow[buf][tc + TC * s] = a[ri][s];
           }
       }
-      __syncthreads();
+      // the pivot row's entries of column tc + TC*s are read only by the TR
+      // lanes of this thread's column group, which share its wavefront: a
+      // wavefront-level barrier orders the LDS write before their reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int s = 0; s < RJ; ++s) {
         if (r + s >= NBLK) break;

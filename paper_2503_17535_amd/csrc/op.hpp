@@ -58,6 +58,14 @@ struct LevelPlan {
   // adjoint
   CopyCall copyPext;
   GemmCall gemmSt, gemmBt1, gemmBt2, gemmZt;
+  // block inversion of D for large merges: interfaces ordered [P1 | P2 | R]
+  // with D(P1, P2) = 0; sizes s = |P_b| n, r = |R| n
+  bool schur = false;
+  int sP = 0, sR = 0;
+  double *Ablk = nullptr, *Ainv = nullptr, *Xs = nullptr, *Ys = nullptr, *Sc = nullptr, *Scinv = nullptr;
+  GJPlan gjA, gjS;
+  CopyCall copyA, copyScZ;
+  GemmCall gemmXY, gemmSc, gemmZ1, gemmZPP;
   // fp32 copies for the mixed-precision solve
   float *Z32 = nullptr, *S32 = nullptr, *Bnz32 = nullptr;
   float *hint32 = nullptr, *gt32 = nullptr, *gint32 = nullptr;

@@ -26,8 +26,10 @@ static MergeGeom make_geom(int d) {
     for (int i = 0; i < 4; ++i) g.faces[i] = f[i];
     const int off[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};   // a b c d = SW SE NE NW
     for (int c = 0; c < 4; ++c) { g.child_off[c][0] = off[c][0]; g.child_off[c][1] = off[c][1]; g.child_off[c][2] = 0; }
-    // interfaces 5..8 of the 2D merge
-    const int it[4][4] = {{0, 1, 1, 3}, {1, 2, 2, 0}, {2, 3, 3, 1}, {3, 0, 0, 2}};
+    // interfaces 5, 7, 6, 8 of the 2D merge (a|b, c|d, b|c, d|a): 5 and 7
+    // share no child, so D's leading 2 x 2 interface blocks are block diagonal
+    const int it[4][4] = {{0, 1, 1, 3}, {2, 3, 3, 1}, {1, 2, 2, 0}, {3, 0, 0, 2}};
+    g.schur_p = 1;
     g.nint = 4;
     for (int i = 0; i < 4; ++i) for (int k = 0; k < 4; ++k) g.iface[i][k] = it[i][k];
   } else {
@@ -38,7 +40,10 @@ static MergeGeom make_geom(int d) {
     const int off[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
                            {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
     for (int c = 0; c < 8; ++c) for (int a = 0; a < 3; ++a) g.child_off[c][a] = off[c][a];
-    // interfaces 9..20 of the 3D merge
+    // interfaces 9..20 of the 3D merge: the lower ring (a..d), the upper
+    // ring (e..h), then the four horizontal ones; the two rings share no
+    // child, so D's leading 8 x 8 interface blocks are block diagonal
+    g.schur_p = 4;
     const int it[12][4] = {{0, 1, 1, 0}, {1, 3, 2, 2}, {2, 0, 3, 1}, {3, 2, 0, 3},
                            {4, 1, 5, 0}, {5, 3, 6, 2}, {6, 0, 7, 1}, {7, 2, 4, 3},
                            {0, 5, 4, 4}, {1, 5, 5, 4}, {2, 5, 6, 4}, {3, 5, 7, 4}};

@@ -43,6 +43,9 @@ struct MergeGeom {
   // child c: its exterior faces (face order) and touched interfaces (increasing)
   int ext_face[8][3], int_list[8][3];
   int face_on_iface[8][12];  // face of child c on interface i, or -1
+  // interfaces [0, schur_p) and [schur_p, 2 schur_p) share no child (the
+  // D blocks between them are zero); the rest follow
+  int schur_p = 0;
   int group_of[8][6];        // parent group of (child, exterior face), or -1
 };
 const MergeGeom& merge_geom(int d);

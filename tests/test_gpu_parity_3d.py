@@ -72,3 +72,60 @@ def test_3d_manufactured_solution_accuracy():
     err = np.abs(u - ue).max() / np.abs(ue).max()
     say(f"[case] error vs exact {err:.3e}")
     assert err < 1e-3
+
+
+def _poly3(pts, deg):
+    """u = prod_a P_a(x_a) with per-variable degree `deg`, its gradient and
+    Laplacian (closed form)."""
+    from numpy.polynomial import polynomial as npoly
+    coefs = [np.array([0.2, -0.3, 0.1, 0.05] + [0.0] * (deg - 4) + [0.4 + 0.1 * a]) for a in range(3)]
+    vals = [npoly.polyval(pts[..., a], coefs[a]) for a in range(3)]
+    d1 = [npoly.polyval(pts[..., a], npoly.polyder(coefs[a])) for a in range(3)]
+    d2 = [npoly.polyval(pts[..., a], npoly.polyder(coefs[a], 2)) for a in range(3)]
+    u = vals[0] * vals[1] * vals[2]
+    grad = np.stack([d1[0] * vals[1] * vals[2], vals[0] * d1[1] * vals[2], vals[0] * vals[1] * d1[2]], axis=-1)
+    lap = d2[0] * vals[1] * vals[2] + vals[0] * d2[1] * vals[2] + vals[0] * vals[1] * d2[2]
+    return u, grad, lap
+
+
+def _divgrad_full(kind):
+    # the 3D workload at full size: div(a grad u) = f on [-1,1]^3, a = 1 + 0.5
+    # sin-product, depth 3 (512 leaves), p = 12; root D = 19,200 (block inversion)
+    import paper_2503_17535_amd as hp
+    p, L = 12, 3
+    t = hp.tree(3, L)
+    pts = hp.leaf_points(t, p)
+    bpts = hp.boundary_points(t, p)
+    prm = W.draw_sinprod(W.rng(3, 0))
+    c = W.coeffs_divgrad(pts, prm)
+    a, ga = W.eval_sinprod(prm, pts)
+    if kind == "poly":
+        ue, gu, lap = _poly3(pts, p - 3)
+        g = _poly3(bpts, p - 3)[0]
+    else:
+        ue, gu, lap = W.sin3_plus_xyz(pts)
+        g = W.sin3_plus_xyz(bpts)[0]
+    f = a * lap + np.sum(ga * gu, axis=-1)
+    dev = torch.device("cuda:0")
+    op = hp.build(t, p, torch.tensor(c, device=dev))
+    say(f"[case] built: {op.nbytes / 1e9:.2f} GB resident")
+    u = op.solve(torch.tensor(g[None], device=dev), torch.tensor(f[None], device=dev)).cpu().numpy()[0]
+    op.free()
+    return np.abs(u - ue).max() / np.abs(ue).max()
+
+
+def test_3d_full_size_polynomial_exactness():
+    """For u polynomial of per-variable degree p-3 every interpolation and
+    differentiation of the discretization is exact, so the discrete solution
+    is u up to rounding at any size (here the 3D workload's full size)."""
+    say("[case] 3D full size p=12 L=3, polynomial u")
+    err = _divgrad_full("poly")
+    say(f"[case] rel error vs exact polynomial {err:.3e}")
+    assert err < 1e-10
+
+
+def test_3d_full_size_manufactured_solution():
+    say("[case] 3D full size p=12 L=3, u = sin sin sin + xyz")
+    err = _divgrad_full("sin")
+    say(f"[case] rel error vs exact {err:.3e}")
+    assert err < 1e-5

@@ -30,9 +30,6 @@
 namespace hps {
 
 // launchers (kernels in the .hip files)
-long long gemm_prepare(std::vector<GemmGroup>& groups);
-int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
-                int n_override);
 int leaf2d_launch(int p, const double* coeffs, const double* D1, const double* D2, const double* Mt, double* LU,
                   int* perm, int* pos, double* Y, int* flag, long long nl, hipStream_t st);
 int gj_small_max();
@@ -214,7 +211,9 @@ void* op_alloc(hps_op* op, size_t bytes, bool resident = true) {
 int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta = false, bool tb = false) {
   call->first = (int)op->hgroups.size();
   call->count = (int)groups.size();
+  op->split_elems = std::max(op->split_elems, gemm_plan_split(groups));
   call->nblocks = gemm_prepare(groups);
+  call->nrblocks = gemm_rblocks(groups);
   call->ta = ta;
   call->tb = tb;
   op->hgroups.insert(op->hgroups.end(), groups.begin(), groups.end());
@@ -291,7 +290,7 @@ void op_src(BlockOp& o, int buf, long long off, int ld) {
 }
 
 int run_gemm(hps_op* op, const GemmCall& c, hipStream_t st, int n_override = 0) {
-  return gemm_launch(op->dgroups + c.first, c.count, c.nblocks, c.ta, c.tb, st, n_override);
+  return gemm_launch(op->dgroups + c.first, c.count, c.nblocks, c.nrblocks, c.ta, c.tb, st, n_override);
 }
 
 int run_copy(hps_op* op, const CopyCall& c, int ncols_rt, double* dst, long long dst_stride, const double* s0,
@@ -770,6 +769,12 @@ int plan_op(hps_op* op) {
                              (long long)NR * m, m, m, NR, m, -1.0, 0.0, nm)},
              &P.gemmZt, true, false);
   }
+  // split-K workspace, shared by all calls (they run one after another)
+  if (op->split_elems > 0) {
+    op->splitws = (double*)op_alloc(op, sizeof(double) * op->split_elems, false);
+    if (!op->splitws) { set_error("device allocation failed (split-K workspace)"); return HPS_ENOMEM; }
+  }
+  for (auto& g : op->hgroups) g.part = g.ksplit > 1 ? op->splitws + g.part_off : nullptr;
   // upload descriptor tables
   op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
   op->dops = (BlockOp*)op_alloc(op, sizeof(BlockOp) * std::max<size_t>(1, op->hops.size()), false);
@@ -944,6 +949,10 @@ int to_group32(const GemmGroup& g, const Map32& m, GemmGroupF32* out) {
   f.M = g.M; f.N = g.N; f.K = g.K; f.nseg = g.nseg;
   f.alpha = (float)g.alpha; f.beta = (float)g.beta;
   f.batch = g.batch;
+  f.ksplit = g.ksplit;
+  f.kchunk = g.kchunk;
+  f.part_off = g.part_off;
+  f.part = nullptr;
   *out = f;
   return HPS_OK;
 }
@@ -954,6 +963,7 @@ int add_gemm32(hps_op* op, const GemmCall& c, const Map32& m, GemmCall* out) {
   out->first = (int)op->hgroups32.size();
   out->count = c.count;
   out->nblocks = gemm_prepare_f32(gs);
+  out->nrblocks = gemm_rblocks_f32(gs);
   out->ta = c.ta;
   out->tb = c.tb;
   op->hgroups32.insert(op->hgroups32.end(), gs.begin(), gs.end());
@@ -1040,6 +1050,11 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
     if (P.lev > 0) HPS_TRY(add_gemm32(op, P.gemmHp, m, &P.gemmHp32));
     HPS_TRY(add_gemm32(op, P.gemmDown, m, &P.gemmDown32));
   }
+  if (op->split_elems > 0) {
+    op->splitws32 = alloc32(op, op->split_elems);
+    if (!op->splitws32) { set_error("device allocation failed (split-K workspace)"); return HPS_ENOMEM; }
+  }
+  for (auto& g : op->hgroups32) g.part = g.ksplit > 1 ? op->splitws32 + g.part_off : nullptr;
   op->dgroups32 = (GemmGroupF32*)op_alloc(op, sizeof(GemmGroupF32) * std::max<size_t>(1, op->hgroups32.size()), false);
   if (!op->dgroups32) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
   HPS_HIP_TRY(hipMemcpy(op->dgroups32, op->hgroups32.data(), sizeof(GemmGroupF32) * op->hgroups32.size(),
@@ -1057,7 +1072,7 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
 }
 
 int run_gemm32(hps_op* op, const GemmCall& c, hipStream_t st, int n_override) {
-  return gemm_launch_f32(op->dgroups32 + c.first, c.count, c.nblocks, c.ta, c.tb, st, n_override);
+  return gemm_launch_f32(op->dgroups32 + c.first, c.count, c.nblocks, c.nrblocks, c.ta, c.tb, st, n_override);
 }
 
 int run_copy32(hps_op* op, const CopyCall& c, int ncols_rt, float* dst, long long dst_stride, const float* s0,
@@ -1322,15 +1337,25 @@ int hps_debug_gemm_f32(int m, int n, int k, float alpha, const float* a, int lda
   g.M = m; g.N = n; g.K = k; g.nseg = 1;
   g.alpha = alpha; g.beta = beta; g.batch = 1;
   std::vector<GemmGroupF32> gs = {g};
+  const long long ws = gemm_plan_split_f32(gs);
   const long long nblocks = gemm_prepare_f32(gs);
+  const long long nrblocks = gemm_rblocks_f32(gs);
   GemmGroupF32* dg = nullptr;
+  float* part = nullptr;
   HPS_HIP_TRY(hipMalloc(&dg, sizeof(GemmGroupF32)));
+  if (ws > 0 && hipMalloc(&part, sizeof(float) * ws) != hipSuccess) {
+    (void)hipFree(dg);
+    set_error("device allocation failed");
+    return HPS_ENOMEM;
+  }
+  if (gs[0].ksplit > 1) gs[0].part = part + gs[0].part_off;
   hipStream_t st = (hipStream_t)stream;
   int rc = HPS_OK;
   if (hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroupF32), hipMemcpyHostToDevice, st) != hipSuccess) rc = HPS_EDEVICE;
-  if (rc == HPS_OK) rc = gemm_launch_f32(dg, 1, nblocks, trans_a != 0, trans_b != 0, st, 0);
+  if (rc == HPS_OK) rc = gemm_launch_f32(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, 0);
   (void)hipStreamSynchronize(st);
   (void)hipFree(dg);
+  if (part) (void)hipFree(part);
   return rc;
 }
 
@@ -1338,14 +1363,25 @@ int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, 
                    int trans_b, double beta, double* c, int ldc, void* stream) {
   if (m < 0 || n < 0 || k < 0 || !a || !b || !c) { set_error("bad GEMM arguments"); return HPS_EINVAL; }
   std::vector<GemmGroup> gs = {make_group(a, 0, lda, b, 0, ldb, c, 0, ldc, m, n, k, alpha, beta, 1, c, 0, ldc)};
+  const long long ws = gemm_plan_split(gs);
   const long long nblocks = gemm_prepare(gs);
+  const long long nrblocks = gemm_rblocks(gs);
   GemmGroup* dg = nullptr;
+  double* part = nullptr;
   HPS_HIP_TRY(hipMalloc(&dg, sizeof(GemmGroup)));
+  if (ws > 0 && hipMalloc(&part, sizeof(double) * ws) != hipSuccess) {
+    (void)hipFree(dg);
+    set_error("device allocation failed");
+    return HPS_ENOMEM;
+  }
+  if (gs[0].ksplit > 1) gs[0].part = part + gs[0].part_off;
   hipStream_t st = (hipStream_t)stream;
-  HPS_HIP_TRY(hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroup), hipMemcpyHostToDevice, st));
-  int rc = gemm_launch(dg, 1, nblocks, trans_a != 0, trans_b != 0, st, 0);
-  HPS_HIP_TRY(hipStreamSynchronize(st));
-  HPS_HIP_TRY(hipFree(dg));
+  int rc = HPS_OK;
+  if (hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroup), hipMemcpyHostToDevice, st) != hipSuccess) rc = HPS_EDEVICE;
+  if (rc == HPS_OK) rc = gemm_launch(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, 0);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dg);
+  if (part) (void)hipFree(part);
   return rc;
 }
 

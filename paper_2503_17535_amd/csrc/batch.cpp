@@ -51,6 +51,7 @@ struct Launch {
   size_t off = 0;          // byte offset of the descriptor array in the block
   int count = 0;           // number of descriptors
   long long nblocks = 0;   // grid size
+  long long nrblocks = 0;  // split-K reduction grid (GEMM)
   int aux = 0;             // max n_i / n_b / root size
   double* zdst = nullptr;  // Zero: memset target
   size_t zbytes = 0;
@@ -111,6 +112,7 @@ void add_gemm_launch(Packer& pk, std::vector<Launch>& out, std::vector<GemmGroup
   l.off = pk.put(groups);
   l.count = (int)groups.size();
   l.nblocks = nb;
+  l.nrblocks = gemm_rblocks(groups);
   out.push_back(l);
 }
 
@@ -335,7 +337,7 @@ int hps_solve_batch(hps_batcher_t* b, const hps_batch_item_t* items, int nitems,
         HPS_TRY(leaf_out_multi_launch((const LeafJob*)(base + l.off), l.count, l.nblocks, l.aux, st));
         break;
       case Kind::Gemm:
-        HPS_TRY(gemm_launch((const GemmGroup*)(base + l.off), l.count, l.nblocks, false, false, st, 0));
+        HPS_TRY(gemm_launch((const GemmGroup*)(base + l.off), l.count, l.nblocks, l.nrblocks, false, false, st, 0));
         break;
       case Kind::Copy:
         HPS_TRY(block_copy_multi_launch((const CopyJob*)(base + l.off), l.count, l.nblocks, st));

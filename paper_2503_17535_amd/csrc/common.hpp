@@ -26,9 +26,15 @@ struct GemmGroup {
   int M, N, K, nseg;
   double alpha, beta;
   int batch;
+  // split-K: ksplit workgroups per tile each sum a K range of kchunk; their
+  // partial products go to part (+ batch item * ksplit * M * N) and a second
+  // pass adds them in a fixed order (ksplit <= 1: no split)
+  int ksplit, kchunk;
+  long long part_off;
+  double* part;
   // filled by the launcher
   int tiles_m, tiles_n;
-  long long first_block;
+  long long first_block, first_rblock;
 };
 
 // Same for fp32 operands with fp32 accumulation (mixed-precision solve).
@@ -43,8 +49,11 @@ struct GemmGroupF32 {
   int M, N, K, nseg;
   float alpha, beta;
   int batch;
+  int ksplit, kchunk;
+  long long part_off;
+  float* part;
   int tiles_m, tiles_n;
-  long long first_block;
+  long long first_block, first_rblock;
 };
 
 // ---------------------------------------------------------------------------

@@ -23,13 +23,32 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// (key, row, val): keep the larger key; ties go to the lower row.
+// |x| as a pivot key: NaN and inf map to +inf so that some unused row is
+// always chosen.
+__device__ __forceinline__ double pivot_key(double x) {
+  double v = fabs(x);
+  return (v <= 1.7976931348623157e308) ? v : __builtin_inf();
+}
+
+// (key, row, val): keep the larger key; ties go to the lower row.  Written
+// with selects, not branches: this sits on the critical path of every
+// elimination step.
 __device__ __forceinline__ void amax_merge(double& key, int& row, double& val, double ok, int orow, double oval) {
-  if (ok > key || (ok == key && orow < row)) {
-    key = ok;
-    row = orow;
-    val = oval;
-  }
+  const bool take = (ok > key) | ((ok == key) & (orow < row));
+  key = take ? ok : key;
+  row = take ? orow : row;
+  val = take ? oval : val;
+}
+
+// Local scan step over a thread's own rows, visited in increasing row order:
+// an equal key never replaces the earlier (lower) row.  Rows already used as
+// pivots carry key -1 and never win.
+__device__ __forceinline__ void amax_scan(double& key, int& row, double& val, double x, int xrow, bool used) {
+  const double k = used ? -1.0 : pivot_key(x);
+  const bool take = k > key;
+  key = take ? k : key;
+  row = take ? xrow : row;
+  val = take ? x : val;
 }
 
 template <int CTRL>
@@ -71,11 +90,5 @@ __device__ __forceinline__ void wave_argmax(double& key, int& row, double& val) 
   }
 }
 
-// |x| as a pivot key: NaN and inf map to +inf so that some unused row is
-// always chosen.
-__device__ __forceinline__ double pivot_key(double x) {
-  double v = fabs(x);
-  return (v <= 1.7976931348623157e308) ? v : __builtin_inf();
-}
 
 }  // namespace hps

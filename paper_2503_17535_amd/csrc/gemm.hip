@@ -15,6 +15,7 @@
 // tiles of one product, which keeps their shared A/B panels in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -75,7 +76,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
 
   const long long lb = xcd_remap(blockIdx.x, nblocks);
   const G* g = find_group(groups, ngroups, lb);
-  const long long rel = lb - g->first_block;
+  const int ks_n = g->ksplit > 1 ? g->ksplit : 1;
+  const long long rel0 = lb - g->first_block;
+  const int ks = (int)(rel0 % ks_n);
+  const long long rel = rel0 / ks_n;
   const int tiles = g->tiles_m * g->tiles_n;
   const long long bat = rel / tiles;
   const int tile = (int)(rel - bat * tiles);
@@ -100,7 +104,9 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
   for (int s = 0; s < g->nseg; ++s) {
     const T* A = Abase + g->aseg[s];
     const T* B = Bbase + g->bseg[s];
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kbeg = ks_n > 1 ? ks * g->kchunk : 0;
+    const int kend = ks_n > 1 ? min(K, kbeg + g->kchunk) : K;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
       // ---- stage op(A) tile (BM x BK) as As[k][i]
       if (!TA) {
         const int i = tid & 63, kk = tid >> 6;
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
         for (int r = 0; r < 4; ++r) {
           const int k = kk + 4 * r;
           const int gi = i0 + i, gk = k0 + k;
-          As[k][i] = (gi < M && gk < K) ? A[gi + (long long)gk * lda] : T(0);
+          As[k][i] = (gi < M && gk < kend) ? A[gi + (long long)gk * lda] : T(0);
         }
       } else {
         const int k = tid & 15, ii = tid >> 4;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
         for (int r = 0; r < 4; ++r) {
           const int i = ii + 16 * r;
           const int gi = i0 + i, gk = k0 + k;
-          As[k][i] = (gi < M && gk < K) ? A[gk + (long long)gi * lda] : T(0);
+          As[k][i] = (gi < M && gk < kend) ? A[gk + (long long)gi * lda] : T(0);
         }
       }
       // ---- stage op(B) tile (BK x BN) as Bs[k][j]
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
         for (int r = 0; r < 4; ++r) {
           const int j = jj + 16 * r;
           const int gj = j0 + j, gk = k0 + k;
-          Bs[k][j] = (gj < N && gk < K) ? B[gk + (long long)gj * ldb] : T(0);
+          Bs[k][j] = (gj < N && gk < kend) ? B[gk + (long long)gj * ldb] : T(0);
         }
       } else {
         const int j = tid & 63, kk = tid >> 6;
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
         for (int r = 0; r < 4; ++r) {
           const int k = kk + 4 * r;
           const int gj = j0 + j, gk = k0 + k;
-          Bs[k][j] = (gj < N && gk < K) ? B[gj + (long long)gk * ldb] : T(0);
+          Bs[k][j] = (gj < N && gk < kend) ? B[gj + (long long)gk * ldb] : T(0);
         }
       }
       __syncthreads();
@@ -155,6 +161,22 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
     }
   }
   // ---- epilogue: acc[a][b][v] = C(row = .. + lane%16, col = .. + MfmaOp<T>::col(lane, v))
+  if (ks_n > 1) {  // split-K: store the raw partial product of this K range
+    T* W = g->part + (bat * ks_n + ks) * (long long)M * g->N;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+      if (row >= M) continue;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = j0 + wc * 32 + b * 16 + MfmaOp<T>::col(lane, v);
+          if (col < N) W[row + (long long)col * M] = acc[a][b][v];
+        }
+    }
+    return;
+  }
   T* C = g->C + bat * g->sC;
   const T* C0 = g->C0 ? g->C0 + bat * g->sC0 : nullptr;
   const T alpha = g->alpha, beta = g->beta;
@@ -177,16 +199,92 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
   }
 }
 
+// Second pass of a split-K product: C = alpha * sum_ks part_ks + beta * C0,
+// the partials added in ks order (deterministic).  One thread per element.
+constexpr int RED_THREADS = 256;
+template <typename T, typename G>
+__global__ __launch_bounds__(RED_THREADS) void gemm_splitk_reduce_kernel(const G* __restrict__ groups, int ngroups,
+                                                                         int n_override) {
+  const long long rb = blockIdx.x;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {  // last group with first_rblock <= rb
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].first_rblock <= rb) lo = mid;
+    else hi = mid - 1;
+  }
+  const G* g = groups + lo;
+  const int M = g->M, Nf = g->N, ks_n = g->ksplit;
+  const int N = (n_override > 0 && n_override < Nf) ? n_override : Nf;
+  const long long e = (rb - g->first_rblock) * RED_THREADS + threadIdx.x;
+  const long long mn = (long long)M * Nf;
+  const long long bat = e / mn;
+  if (bat >= g->batch) return;
+  const int rem = (int)(e - bat * mn);
+  const int col = rem / M, row = rem - col * M;
+  if (col >= N) return;
+  const T* W = g->part + bat * ks_n * mn + row + (long long)col * M;
+  T sum = T(0);
+  for (int k = 0; k < ks_n; ++k) sum += W[k * mn];
+  T val = g->alpha * sum;
+  if (g->beta != T(0)) val += g->beta * g->C0[bat * g->sC0 + row + (long long)col * g->ldc0];
+  g->C[bat * g->sC + row + (long long)col * g->ldc] = val;
+}
+
 template <typename G>
 static long long prepare_groups(std::vector<G>& groups) {
-  long long total = 0;
+  long long total = 0, rtotal = 0;
   for (auto& g : groups) {
     g.tiles_m = (g.M + BM - 1) / BM;
     g.tiles_n = (g.N + BN - 1) / BN;
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
     g.first_block = total;
-    if (g.M > 0 && g.N > 0) total += (long long)g.tiles_m * g.tiles_n * g.batch;
+    g.first_rblock = rtotal;
+    if (g.M > 0 && g.N > 0) {
+      total += (long long)g.tiles_m * g.tiles_n * g.batch * ks;
+      if (ks > 1) rtotal += ((long long)g.batch * g.M * g.N + RED_THREADS - 1) / RED_THREADS;
+    }
   }
   return total;
+}
+
+template <typename G>
+static long long rblocks_of(const std::vector<G>& groups) {
+  long long r = 0;
+  for (const auto& g : groups)
+    if (g.ksplit > 1 && g.M > 0 && g.N > 0) r += ((long long)g.batch * g.M * g.N + RED_THREADS - 1) / RED_THREADS;
+  return r;
+}
+
+// Choose split-K factors for a launch that would otherwise fill few
+// workgroups (skinny products: the solve's N <= 16 right-hand sides against
+// large operators): aim at ~1024 workgroups, K ranges of >= 256.  Assigns
+// each split group a workspace offset (consecutive from 0) and returns the
+// workspace elements the launch needs.
+template <typename G>
+static long long plan_split(std::vector<G>& groups) {
+  long long tiles = 0;
+  for (auto& g : groups) {
+    g.ksplit = 1;
+    g.kchunk = 0;
+    g.part_off = 0;
+    tiles += (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
+  }
+  if (tiles == 0 || tiles >= 512) return 0;
+  const long long want = (1024 + tiles - 1) / tiles;
+  long long off = 0;
+  for (auto& g : groups) {
+    long long ks = std::min<long long>(want, g.K / 256);
+    if (ks < 2) continue;
+    int kchunk = (int)((g.K + ks - 1) / ks);
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    ks = (g.K + kchunk - 1) / kchunk;
+    if (ks < 2) continue;
+    g.ksplit = (int)ks;
+    g.kchunk = kchunk;
+    g.part_off = off;
+    off += (long long)g.batch * ks * g.M * g.N;
+  }
+  return off;
 }
 
 // Launch a grouped GEMM whose descriptors already live in device memory
@@ -194,8 +292,12 @@ static long long prepare_groups(std::vector<G>& groups) {
 // gemm_prepare) is `groups`.
 long long gemm_prepare(std::vector<GemmGroup>& groups) { return prepare_groups(groups); }
 long long gemm_prepare_f32(std::vector<GemmGroupF32>& groups) { return prepare_groups(groups); }
+long long gemm_rblocks(const std::vector<GemmGroup>& groups) { return rblocks_of(groups); }
+long long gemm_rblocks_f32(const std::vector<GemmGroupF32>& groups) { return rblocks_of(groups); }
+long long gemm_plan_split(std::vector<GemmGroup>& groups) { return plan_split(groups); }
+long long gemm_plan_split_f32(std::vector<GemmGroupF32>& groups) { return plan_split(groups); }
 
-int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb,
+int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, long long nrblocks, bool ta, bool tb,
                 hipStream_t st, int n_override) {
   if (nblocks <= 0) return HPS_OK;
   dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
@@ -208,11 +310,16 @@ int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, boo
   else
     hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, true, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
   HPS_HIP_TRY(hipGetLastError());
+  if (nrblocks > 0) {
+    hipLaunchKernelGGL((gemm_splitk_reduce_kernel<double, GemmGroup>), dim3((unsigned)nrblocks), dim3(RED_THREADS), 0,
+                       st, dev_groups, ngroups, n_override);
+    HPS_HIP_TRY(hipGetLastError());
+  }
   return HPS_OK;
 }
 
-int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, bool ta, bool tb,
-                    hipStream_t st, int n_override) {
+int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, long long nrblocks, bool ta,
+                    bool tb, hipStream_t st, int n_override) {
   if (nblocks <= 0) return HPS_OK;
   dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
   if (!ta && !tb)
@@ -224,6 +331,11 @@ int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nbloc
   else
     hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, true, true>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
   HPS_HIP_TRY(hipGetLastError());
+  if (nrblocks > 0) {
+    hipLaunchKernelGGL((gemm_splitk_reduce_kernel<float, GemmGroupF32>), dim3((unsigned)nrblocks), dim3(RED_THREADS),
+                       0, st, dev_groups, ngroups, n_override);
+    HPS_HIP_TRY(hipGetLastError());
+  }
   return HPS_OK;
 }
 

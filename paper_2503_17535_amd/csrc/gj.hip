@@ -72,8 +72,7 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
         double key = -1.0, pv = 0.0;
         int brow = 0x7fffffff;
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri)
-          if (!((used >> ri) & 1u)) amax_merge(key, brow, pv, pivot_key(a[ri][0]), tr + TR * ri, a[ri][0]);
+        for (int ri = 0; ri < RI; ++ri) amax_scan(key, brow, pv, a[ri][0], tr + TR * ri, (used >> ri) & 1u);
         group_argmax<TR>(key, brow, pv);
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
@@ -111,16 +110,22 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // multipliers of this thread's rows, read once per step (the pivot
+      // row's entry is 0, so the update leaves that row unchanged)
+      double lc[RI];
+#pragma unroll
+      for (int ri = 0; ri < RI; ++ri) lc[ri] = s_lcol[buf][tr + TR * ri];
 #pragma unroll
       for (int s = 0; s < RJ; ++s) {
         const double u = s_urow[buf][tc + TC * s];
-        const bool colk = (s == 0 && tc == t);
+        if (s == 0 && tc == t) {
+          // column k becomes the k-th column of the elimination operator
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri) {
-          const int row = tr + TR * ri;
-          if (row == pr) continue;
-          const double base = colk ? 0.0 : a[ri][s];
-          a[ri][s] = base - s_lcol[buf][row] * u;
+          for (int ri = 0; ri < RI; ++ri)
+            if (tr + TR * ri != pr) a[ri][0] = -lc[ri] * u;
+        } else {
+#pragma unroll
+          for (int ri = 0; ri < RI; ++ri) a[ri][s] -= lc[ri] * u;
         }
       }
     }
@@ -234,8 +239,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
       double key = -1.0, val = 0.0;
       int brow = 0x7fffffff;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i)
-        if (!((used >> i) & 1u)) amax_merge(key, brow, val, pivot_key(a[i][0]), tid + PANEL_THREADS * i, a[i][0]);
+      for (int i = 0; i < RPT; ++i) amax_scan(key, brow, val, a[i][0], tid + PANEL_THREADS * i, (used >> i) & 1u);
       wave_argmax(key, brow, val);
       // the lane holding this wavefront's candidate row publishes the row's
       // panel entries with the candidate, so one barrier serves both the
@@ -273,9 +277,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
           if (i == ip) used |= 1u << i;
-        pos[pr] = k;
-        piv[k] = pr;
-        s_piv[c] = pr;
+        s_piv[c] = pr;  // pos / piv go to global memory after the panel
         if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
       }
       const double pinv = 1.0 / pv;
@@ -300,6 +302,10 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
     }
   }
   __syncthreads();
+  if (tid < nbw) {
+    pos[s_piv[tid]] = j0 + tid;
+    piv[j0 + tid] = s_piv[tid];
+  }
   // write the panel back (its columns are final for this panel) and W = panel - E_P
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {

@@ -22,12 +22,22 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "dpp.hpp"
 #include "../../include/hps.h"
 
 namespace hps {
+
+// Compile-time loop: f(integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 template <int P>
 struct Leaf2DCfg {
@@ -162,8 +172,12 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   double* LUl = LU + leaf * (long long)NI * NI;
 
   // ---- forward elimination with implicit partial pivoting
-  int r = 0;  // rotations done
-  for (int kb = 0; kb < RJP; ++kb, ++r) {
+  // the block loop is expanded at compile time (static_for) so that the
+  // rotation count r = kb is a constant: slot rotation becomes register
+  // renaming and the number of live slots is known in every step
+  static_for<0, RJP>([&](auto kbc) {
+    constexpr int kb = decltype(kbc)::value;
+    constexpr int r = kb;  // rotations done
     for (int t = 0; t < TC; ++t) {
       const int k = kb * TC + t;
       if (k >= NI) break;
@@ -172,8 +186,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         double key = -1.0, pv = 0.0;
         int brow = 0x7fffffff;
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri)
-          if (!((used >> ri) & 1u)) amax_merge(key, brow, pv, pivot_key(a[ri][0]), tr + TR * ri, a[ri][0]);
+        for (int ri = 0; ri < RI; ++ri) amax_scan(key, brow, pv, a[ri][0], tr + TR * ri, (used >> ri) & 1u);
         group_argmax<TR>(key, brow, pv);
         const double pinv = 1.0 / pv;
 #pragma unroll
@@ -229,8 +242,8 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         for (int ri = 0; ri < RI; ++ri)
           if (tr + TR * ri < NI) LUl[tr + TR * ri + (long long)col * NI] = a[ri][0];
     }
-    if (kb == RJP - 1) break;  // keep the last pivot block (it also holds augmented columns)
-    if (C::EXTRA && kb == 0) {
+    if constexpr (kb == RJP - 1) return;  // keep the last pivot block (it also holds augmented columns)
+    if constexpr (C::EXTRA && kb == 0) {
 #pragma unroll
       for (int ri = 0; ri < RI; ++ri) s_L0[tc][tr + TR * ri] = a[ri][0];
     }
@@ -241,7 +254,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       for (int s = 0; s + 1 < RJ; ++s) a[ri][s] = a[ri][s + 1];
       a[ri][RJ - 1] = 0.0;
     }
-    if (C::EXTRA && kb == 0) {
+    if constexpr (C::EXTRA && kb == 0) {
       // the late column block enters slot RJ-1 and replays the TC steps of
       // block 0: x_row -= L(row, j) * x_perm[j] for rows pivoted after step j
       leaf2d_stage_aug<P>(s_aug, RJ * TC, C::AUG_LATE, s_coef, s_active, Mt, tid, NT);
@@ -266,7 +279,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         }
       }
     }
-  }
+  });
   __syncthreads();
 
   // ---- back substitution of the augmented columns:  U X = (forward-eliminated L_ie P)

@@ -24,7 +24,7 @@ struct DevConsts {
 
 struct GemmCall {
   int first = 0, count = 0;
-  long long nblocks = 0;
+  long long nblocks = 0, nrblocks = 0;  // GEMM and split-K reduction workgroups
   bool ta = false, tb = false;
 };
 struct CopyCall {
@@ -119,7 +119,7 @@ struct hps_op {
   // mixed-precision solve (HPS_FLAG_FP32_COPY): fp32 operator copies and
   // workspaces, fp64 iterate and residuals, leaf adjacency
   bool fp32 = false;
-  int refine_sweeps = 6;
+  int refine_sweeps = 3;
   double* coef = nullptr;                      // [nl][n_terms][npts]
   double* C2G = nullptr;                       // q x p row-major
   float *LU32 = nullptr, *Y32 = nullptr, *Qi32 = nullptr;
@@ -131,6 +131,9 @@ struct hps_op {
   std::vector<hps::GemmGroupF32> hgroups32;
   hps::GemmGroupF32* dgroups32 = nullptr;
   hps::GemmCall gemmHleaf32;
+  long long split_elems = 0;                   // split-K workspace (elements), fp64 and fp32
+  double* splitws = nullptr;
+  float* splitws32 = nullptr;
   std::vector<hps::Alloc> allocs;
   size_t resident = 0;
   std::vector<hps::TimedStage> stages;
@@ -139,8 +142,12 @@ struct hps_op {
 namespace hps {
 long long gemm_prepare(std::vector<GemmGroup>& groups);
 long long gemm_prepare_f32(std::vector<GemmGroupF32>& groups);
-int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
-                    int n_override);
-int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, bool ta, bool tb, hipStream_t st,
-                int n_override);
+long long gemm_rblocks(const std::vector<GemmGroup>& groups);
+long long gemm_rblocks_f32(const std::vector<GemmGroupF32>& groups);
+long long gemm_plan_split(std::vector<GemmGroup>& groups);
+long long gemm_plan_split_f32(std::vector<GemmGroupF32>& groups);
+int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nblocks, long long nrblocks, bool ta,
+                    bool tb, hipStream_t st, int n_override);
+int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, long long nrblocks, bool ta, bool tb,
+                hipStream_t st, int n_override);
 }  // namespace hps

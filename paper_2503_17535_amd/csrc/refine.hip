@@ -56,77 +56,100 @@ int refine_init_launch(const double* bdry, const long long* bidx, int q, int nb0
   return HPS_OK;
 }
 
-// One workgroup per leaf, right-hand sides in turn:
+// One workgroup per leaf, all right-hand sides at once (thread work items
+// are (rhs, point) pairs):
 //   u(I_e) = P gamma (written to u), r1 = f - L u at interior points,
 //   Qu = outgoing normal derivative at the Gauss points of every face.
 // D1, D2 row-major p x p (scaled to the leaf), P column-major n_e x n_b,
-// C2G row-major q x p, coef [leaf][6][p^2].
+// C2G row-major q x p, coef [leaf][6][p^2].  The mixed derivative is formed
+// separably: ux = D1 along x on the whole grid (LDS), then D1 along y of ux.
+// D1 and D2 are kept transposed (DxT[a * p + i] = D(i, a)) so that lanes of
+// consecutive x index read consecutive LDS words.
+struct RfShared {
+  double D1[RF_MAXP * RF_MAXP], D2[RF_MAXP * RF_MAXP], D1T[RF_MAXP * RF_MAXP], D2T[RF_MAXP * RF_MAXP];
+  double C2G[RF_MAXP * RF_MAXP];
+  double u[RF_MAXR][RF_MAXP * RF_MAXP];
+  double ux[RF_MAXR][RF_MAXP * RF_MAXP];
+  double uy[RF_MAXR][RF_MAXP * RF_MAXP];
+  double g[RF_MAXR][4 * RF_MAXP];
+};
+
 __global__ __launch_bounds__(RF_THREADS) void refine_residual_kernel(
     const double* __restrict__ coef, const double* __restrict__ src, const double* __restrict__ gam,
     const double* __restrict__ D1g, const double* __restrict__ D2g, const double* __restrict__ P,
     const double* __restrict__ C2G, const int* __restrict__ Ii, const int* __restrict__ Ie, int p, long long nl,
     int nrhs, int NRcap, double* __restrict__ u, double* __restrict__ r1, double* __restrict__ Qu) {
-  __shared__ double sD1[RF_MAXP * RF_MAXP], sD2[RF_MAXP * RF_MAXP], sC2G[RF_MAXP * RF_MAXP];
-  __shared__ double su[RF_MAXP * RF_MAXP], sg[4 * RF_MAXP], snd[4 * RF_MAXP];
+  extern __shared__ double smem[];
+  RfShared& S = *reinterpret_cast<RfShared*>(smem);
   const int q = p - 2, npts = p * p, ni = q * q, ne = npts - ni, nb = 4 * q;
   const long long leaf = blockIdx.x;
   const int tid = threadIdx.x;
   for (int i = tid; i < p * p; i += RF_THREADS) {
-    sD1[i] = D1g[i];
-    sD2[i] = D2g[i];
+    S.D1[i] = D1g[i];
+    S.D2[i] = D2g[i];
+    S.D1T[(i % p) * p + i / p] = D1g[i];
+    S.D2T[(i % p) * p + i / p] = D2g[i];
   }
-  for (int i = tid; i < q * p; i += RF_THREADS) sC2G[i] = C2G[i];
+  for (int i = tid; i < q * p; i += RF_THREADS) S.C2G[i] = C2G[i];
+  for (int e = tid; e < nrhs * nb; e += RF_THREADS) {
+    const int r = e / nb, k = e % nb;
+    S.g[r][k] = gam[(leaf * NRcap + r) * nb + k];
+  }
+  for (int e = tid; e < nrhs * ni; e += RF_THREADS) {
+    const int r = e / ni, k = e % ni;
+    S.u[r][Ii[k]] = u[((long long)r * nl + leaf) * npts + Ii[k]];
+  }
+  __syncthreads();
+  // exterior points: u = P gamma
+  for (int e = tid; e < nrhs * ne; e += RF_THREADS) {
+    const int r = e / ne, k = e % ne;
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += P[k + (long long)b * ne] * S.g[r][b];
+    S.u[r][Ie[k]] = v;
+    u[((long long)r * nl + leaf) * npts + Ie[k]] = v;
+  }
+  __syncthreads();
+  // ux and uy on the whole grid
+  for (int e = tid; e < nrhs * npts; e += RF_THREADS) {
+    const int r = e / npts, pt = e % npts, ix = pt % p, iy = pt / p;
+    double vx = 0.0, vy = 0.0;
+    for (int a = 0; a < p; ++a) {
+      vx += S.D1T[a * p + ix] * S.u[r][a + p * iy];
+      vy += S.D1[iy * p + a] * S.u[r][ix + p * a];
+    }
+    S.ux[r][pt] = vx;
+    S.uy[r][pt] = vy;
+  }
+  __syncthreads();
+  // collocation residual at interior points
   const double* c = coef + leaf * 6 * (long long)npts;
-  for (int r = 0; r < nrhs; ++r) {
-    __syncthreads();  // the previous right-hand side is done with su, sg, snd
-    double* ur = u + ((long long)r * nl + leaf) * npts;
-    for (int k = tid; k < nb; k += RF_THREADS) sg[k] = gam[(leaf * NRcap + r) * nb + k];
-    for (int k = tid; k < ni; k += RF_THREADS) su[Ii[k]] = ur[Ii[k]];
-    __syncthreads();
-    for (int e = tid; e < ne; e += RF_THREADS) {
-      double v = 0.0;
-      for (int b = 0; b < nb; ++b) v += P[e + (long long)b * ne] * sg[b];
-      su[Ie[e]] = v;
-      ur[Ie[e]] = v;
+  for (int e = tid; e < nrhs * ni; e += RF_THREADS) {
+    const int r = e / ni, k = e % ni;
+    const int pt = Ii[k], ix = pt % p, iy = pt / p;
+    double dxx = 0.0, dyy = 0.0, dxy = 0.0;
+    for (int a = 0; a < p; ++a) {
+      dxx += S.D2T[a * p + ix] * S.u[r][a + p * iy];
+      dyy += S.D2[iy * p + a] * S.u[r][ix + p * a];
+      dxy += S.D1[iy * p + a] * S.ux[r][ix + p * a];
     }
-    __syncthreads();
-    // collocation residual at interior points
-    const double* fr = src ? src + ((long long)r * nl + leaf) * npts : nullptr;
-    for (int k = tid; k < ni; k += RF_THREADS) {
-      const int pt = Ii[k], ix = pt % p, iy = pt / p;
-      double dx = 0.0, dy = 0.0, dxx = 0.0, dyy = 0.0, dxy = 0.0;
-      for (int a = 0; a < p; ++a) {
-        const double ux = su[a + p * iy], uy = su[ix + p * a];
-        dx += sD1[ix * p + a] * ux;
-        dxx += sD2[ix * p + a] * ux;
-        dy += sD1[iy * p + a] * uy;
-        dyy += sD2[iy * p + a] * uy;
-        double s = 0.0;
-        for (int b = 0; b < p; ++b) s += sD1[ix * p + b] * su[b + p * a];
-        dxy += sD1[iy * p + a] * s;
-      }
-      const double Lu = c[pt] * dxx + c[npts + pt] * dxy + c[2 * npts + pt] * dyy + c[3 * npts + pt] * dx +
-                        c[4 * npts + pt] * dy + c[5 * npts + pt] * su[pt];
-      r1[(leaf * NRcap + r) * ni + k] = (fr ? fr[pt] : 0.0) - Lu;
+    const double Lu = c[pt] * dxx + c[npts + pt] * dxy + c[2 * npts + pt] * dyy + c[3 * npts + pt] * S.ux[r][pt] +
+                      c[4 * npts + pt] * S.uy[r][pt] + c[5 * npts + pt] * S.u[r][pt];
+    const double f = src ? src[((long long)r * nl + leaf) * npts + pt] : 0.0;
+    r1[(leaf * NRcap + r) * ni + k] = f - Lu;
+  }
+  // outgoing fluxes: normal derivative at the face's Chebyshev points (faces
+  // S, E, N, W; tangential coordinate ascending), then Chebyshev -> Gauss
+  for (int e = tid; e < nrhs * nb; e += RF_THREADS) {
+    const int r = e / nb, cg = e % nb, f = cg / q, j = cg % q;
+    const int axis = (f == 1 || f == 3) ? 0 : 1;
+    const int side = (f == 1 || f == 2) ? 1 : 0;
+    const int in = side ? p - 1 : 0;
+    double v = 0.0;
+    for (int t = 0; t < p; ++t) {
+      const double d = axis == 0 ? S.ux[r][in + p * t] : S.uy[r][t + p * in];
+      v += S.C2G[j * p + t] * d;
     }
-    // outgoing normal derivative at the Chebyshev points of every face
-    // (faces S, E, N, W; tangential coordinate ascending)
-    for (int e = tid; e < 4 * p; e += RF_THREADS) {
-      const int f = e / p, t = e % p;
-      const int axis = (f == 1 || f == 3) ? 0 : 1;
-      const int side = (f == 1 || f == 2) ? 1 : 0;
-      const int in = side ? p - 1 : 0;
-      double d = 0.0;
-      for (int m = 0; m < p; ++m) d += sD1[in * p + m] * (axis == 0 ? su[m + p * t] : su[t + p * m]);
-      snd[e] = side ? d : -d;
-    }
-    __syncthreads();
-    for (int e = tid; e < nb; e += RF_THREADS) {
-      const int f = e / q, j = e % q;
-      double v = 0.0;
-      for (int t = 0; t < p; ++t) v += sC2G[j * p + t] * snd[f * p + t];
-      Qu[(leaf * NRcap + r) * nb + e] = v;
-    }
+    Qu[(leaf * NRcap + r) * nb + cg] = side ? v : -v;
   }
 }
 
@@ -137,7 +160,14 @@ int refine_residual_launch(const double* coef, const double* src, const double* 
     set_error("refined solve: p <= 16 and at most 16 right-hand sides per pass");
     return HPS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(refine_residual_kernel, dim3((unsigned)nl), dim3(RF_THREADS), 0, st, coef, src, gam, D1, D2, P,
+  const size_t shm = sizeof(RfShared);
+  static bool attr = false;
+  if (!attr) {
+    HPS_HIP_TRY(hipFuncSetAttribute((const void*)refine_residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+    attr = true;
+  }
+  hipLaunchKernelGGL(refine_residual_kernel, dim3((unsigned)nl), dim3(RF_THREADS), shm, st, coef, src, gam, D1, D2, P,
                      C2G, Ii, Ie, p, nl, nrhs, NRcap, u, r1, Qu);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;

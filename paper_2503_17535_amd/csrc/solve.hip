@@ -93,87 +93,137 @@ constexpr int SRC_THREADS = 256;
 constexpr int SRC_MAXR = 16;
 
 // Body shared by the single-operator, the batched (cross-operator) and the
-// fp32 launches: one workgroup solves one leaf in precision T.  src(j, k) is
-// the source of rhs j at interior point k (as double); the result for rhs j
-// goes to v[j * NI + k].
+// fp32 launches: one wavefront solves one leaf in precision T, so the
+// column-by-column substitution needs no workgroup barrier.  Lane l owns rows
+// l + 64 i; src(j, k) is the source of rhs j at interior point k (as double);
+// the result for rhs j goes to v[j * NI + k].  The LU columns (and pivot
+// rows / diagonal entries) of the next PF steps are in flight in a register
+// ring, so the step chain does not wait on HBM.
+constexpr int SRCW_THREADS = 64;
+constexpr int SRC_PF = 4;
 template <int RPT, typename T, class Src>
-__device__ __forceinline__ void leaf_src_body(const T* __restrict__ LU, const int* __restrict__ perm_g,
+__device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const int* __restrict__ perm_g,
                                               const int* __restrict__ pos_g, Src src, int NI, int nrhs,
-                                              T* __restrict__ v, int* s_perm, int* s_pos, T (*s_y)[SRC_MAXR]) {
-  const int tid = threadIdx.x;
-  for (int i = tid; i < NI; i += SRC_THREADS) {
-    s_perm[i] = perm_g[i];
-    s_pos[i] = pos_g[i];
-  }
+                                              T* __restrict__ v, T* s_y) {
+  constexpr int PF = SRC_PF;
+  const int lane = threadIdx.x;
   T b[RPT][SRC_MAXR];
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int row = tid + SRC_THREADS * i;
-#pragma unroll
-    for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? (T)src(j, row) : T(0);
-  }
-  __syncthreads();
   int mypos[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int row = tid + SRC_THREADS * i;
-    mypos[i] = row < NI ? s_pos[row] : -1;
+    const int row = lane + SRCW_THREADS * i;
+    mypos[i] = row < NI ? pos_g[row] : -1;
+#pragma unroll
+    for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? (T)src(j, row) : T(0);
   }
-  // forward: y_s = b[perm[s]];  b[r] -= L(r, s) y_s for pos[r] > s
-  for (int s = 0; s < NI; ++s) {
-    const int buf = s & 1;
-    const int pr = __builtin_amdgcn_readfirstlane(s_perm[s]);  // uniform: scalar branches below
-    if (tid == pr % SRC_THREADS) {
-      const int ip = pr / SRC_THREADS;
+  T ring[PF][RPT];
+  int pring[PF];
+  T dring[PF];
+  // ---- forward: y_s = b[perm[s]];  b[r] -= L(r, s) y_s for pos[r] > s
 #pragma unroll
-      for (int i = 0; i < RPT; ++i)
-        if (i == ip)
-#pragma unroll
-          for (int j = 0; j < SRC_MAXR; ++j) s_y[buf][j] = b[i][j];
-    }
-    __syncthreads();
+  for (int u = 0; u < PF; ++u) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + SRC_THREADS * i;
-      if (row < NI && mypos[i] > s) {
-        const T l = LU[row + (long long)s * NI];
-#pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= l * s_y[buf][j];
-      }
+      const int row = lane + SRCW_THREADS * i;
+      ring[u][i] = (row < NI && u < NI) ? LU[row + (long long)u * NI] : T(0);
     }
+    pring[u] = u < NI ? perm_g[u] : 0;
   }
-  // backward: x_s = b[perm[s]] / U(s, s);  b[r] -= U(pos[r], s) x_s for pos[r] < s
-  for (int s = NI - 1; s >= 0; --s) {
-    const int buf = s & 1;
-    const int pr = __builtin_amdgcn_readfirstlane(s_perm[s]);  // uniform: scalar branches below
-    if (tid == pr % SRC_THREADS) {
-      const int ip = pr / SRC_THREADS;
-      const T dinv = T(1) / LU[pr + (long long)s * NI];
+  for (int s0 = 0; s0 < NI; s0 += PF) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i)
-        if (i == ip)
+    for (int u = 0; u < PF; ++u) {
+      const int s = s0 + u;
+      if (s < NI) {
+        const int pr = pring[u];
+        if (lane == pr % SRCW_THREADS) {
+          const int ip = pr / SRCW_THREADS;
 #pragma unroll
-          for (int j = 0; j < SRC_MAXR; ++j) {
-            b[i][j] *= dinv;
-            s_y[buf][j] = b[i][j];
+          for (int i = 0; i < RPT; ++i)
+            if (i == ip)
+#pragma unroll
+              for (int j = 0; j < SRC_MAXR; ++j) s_y[j] = b[i][j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        T y[SRC_MAXR];
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) y[j] = s_y[j];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (mypos[i] > s) {
+#pragma unroll
+            for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= ring[u][i] * y[j];
           }
+        __builtin_amdgcn_wave_barrier();  // s_y is rewritten next step
+      }
+      const int sn = s + PF;  // refill this slot
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = lane + SRCW_THREADS * i;
+        ring[u][i] = (row < NI && sn < NI) ? LU[row + (long long)sn * NI] : T(0);
+      }
+      pring[u] = sn < NI ? perm_g[sn] : 0;
     }
-    __syncthreads();
+  }
+  // ---- backward: x_s = b[perm[s]] / U(s, s);  b[r] -= U(pos[r], s) x_s for pos[r] < s
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int s = NI - 1 - u;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = tid + SRC_THREADS * i;
-      if (row < NI && mypos[i] < s) {
-        const T u = LU[row + (long long)s * NI];
+      const int row = lane + SRCW_THREADS * i;
+      ring[u][i] = (row < NI && s >= 0) ? LU[row + (long long)s * NI] : T(0);
+    }
+    pring[u] = s >= 0 ? perm_g[s] : 0;
+    dring[u] = s >= 0 ? LU[pring[u] + (long long)s * NI] : T(1);
+  }
+  for (int s0 = 0; s0 < NI; s0 += PF) {
 #pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= u * s_y[buf][j];
+    for (int u = 0; u < PF; ++u) {
+      const int s = NI - 1 - (s0 + u);
+      if (s >= 0) {
+        const int pr = pring[u];
+        const T dinv = T(1) / dring[u];
+        if (lane == pr % SRCW_THREADS) {
+          const int ip = pr / SRCW_THREADS;
+#pragma unroll
+          for (int i = 0; i < RPT; ++i)
+            if (i == ip)
+#pragma unroll
+              for (int j = 0; j < SRC_MAXR; ++j) {
+                b[i][j] *= dinv;
+                s_y[j] = b[i][j];
+              }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        T y[SRC_MAXR];
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) y[j] = s_y[j];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+          if (mypos[i] >= 0 && mypos[i] < s) {
+#pragma unroll
+            for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= ring[u][i] * y[j];
+          }
+        __builtin_amdgcn_wave_barrier();
       }
+      const int sn = s - PF;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = lane + SRCW_THREADS * i;
+        ring[u][i] = (row < NI && sn >= 0) ? LU[row + (long long)sn * NI] : T(0);
+      }
+      pring[u] = sn >= 0 ? perm_g[sn] : 0;
+      dring[u] = sn >= 0 ? LU[pring[u] + (long long)sn * NI] : T(1);
     }
   }
   // unknown pos[r] sits in row r
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int row = tid + SRC_THREADS * i;
-    if (row >= NI) continue;
+    if (mypos[i] < 0) continue;
 #pragma unroll
     for (int j = 0; j < SRC_MAXR; ++j)
       if (j < nrhs) v[(long long)j * NI + mypos[i]] = b[i][j];
@@ -181,20 +231,19 @@ __device__ __forceinline__ void leaf_src_body(const T* __restrict__ LU, const in
 }
 
 template <int RPT>
-__global__ __launch_bounds__(SRC_THREADS) void leaf_src_kernel(const double* __restrict__ LUall,
-                                                               const int* __restrict__ permall,
-                                                               const int* __restrict__ posall,
-                                                               const double* __restrict__ src, const int* __restrict__ Ii,
-                                                               int NI, int npts, long long nl, int nrhs,
-                                                               double* __restrict__ vout, int NRcap) {
-  __shared__ double s_y[2][SRC_MAXR];
-  extern __shared__ int s_int[];  // perm[NI], pos[NI]
+__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_kernel(const double* __restrict__ LUall,
+                                                                const int* __restrict__ permall,
+                                                                const int* __restrict__ posall,
+                                                                const double* __restrict__ src, const int* __restrict__ Ii,
+                                                                int NI, int npts, long long nl, int nrhs,
+                                                                double* __restrict__ vout, int NRcap) {
+  __shared__ double s_y[SRC_MAXR];
   const long long leaf = blockIdx.x;
   const double* f = src + leaf * npts;
   const long long rstride = nl * npts;
   auto at = [=](int j, int k) { return f[(long long)j * rstride + Ii[k]]; };
-  leaf_src_body<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI,
-                             nrhs, vout + leaf * (long long)NRcap * NI, s_int, s_int + NI, s_y);
+  leaf_src_wave<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
+                             vout + leaf * (long long)NRcap * NI, s_y);
 }
 
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
@@ -203,14 +252,13 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
     set_error("leaf_src: at most 16 right-hand sides per pass");
     return HPS_EINVAL;
   }
-  const size_t shm = 2 * NI * sizeof(int);
-  const int rpt = (NI + SRC_THREADS - 1) / SRC_THREADS;
-  dim3 grid((unsigned)nl), block(SRC_THREADS);
+  const int rpt = (NI + SRCW_THREADS - 1) / SRCW_THREADS;
+  dim3 grid((unsigned)nl), block(SRCW_THREADS);
   switch (rpt) {
-    case 1: hipLaunchKernelGGL(leaf_src_kernel<1>, grid, block, shm, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 2: hipLaunchKernelGGL(leaf_src_kernel<2>, grid, block, shm, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 3: hipLaunchKernelGGL(leaf_src_kernel<3>, grid, block, shm, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 4: hipLaunchKernelGGL(leaf_src_kernel<4>, grid, block, shm, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
+    case 1: hipLaunchKernelGGL(leaf_src_kernel<1>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
+    case 2: hipLaunchKernelGGL(leaf_src_kernel<2>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
+    case 3: hipLaunchKernelGGL(leaf_src_kernel<3>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
+    case 4: hipLaunchKernelGGL(leaf_src_kernel<4>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
     default:
       set_error("leaf_src: too many interior points");
       return HPS_EUNSUPPORTED;
@@ -487,9 +535,8 @@ __global__ __launch_bounds__(BC_THREADS) void root_gather_multi_kernel(const Lea
     J.g0[(long long)j * J.nb0 + i] = src[i];
 }
 
-__global__ __launch_bounds__(SRC_THREADS) void leaf_src_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
-  __shared__ double s_y[2][SRC_MAXR];
-  extern __shared__ int s_int[];
+__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
+  __shared__ double s_y[SRC_MAXR];
   const LeafJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
   const long long leaf = blockIdx.x - J.first_block;
   const int NI = J.NI, npts = J.npts;
@@ -498,8 +545,8 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_multi_kernel(const LeafJ
     const double* f = J.src[j];
     return f ? f[leaf * npts + Ii[k]] : 0.0;
   };
-  leaf_src_body<1, double>(J.LU + leaf * (long long)NI * NI, J.perm + leaf * NI, J.pos + leaf * NI, at, NI, J.nrhs,
-                           J.v + leaf * (long long)J.NRcap * NI, s_int, s_int + NI, s_y);
+  leaf_src_wave<4, double>(J.LU + leaf * (long long)NI * NI, J.perm + leaf * NI, J.pos + leaf * NI, at, NI, J.nrhs,
+                           J.v + leaf * (long long)J.NRcap * NI, s_y);
 }
 
 __global__ __launch_bounds__(OUT_THREADS) void leaf_out_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
@@ -530,12 +577,11 @@ int root_gather_multi_launch(const LeafJob* dev_jobs, int njobs, int max_nb0, hi
 
 int leaf_src_multi_launch(const LeafJob* dev_jobs, int njobs, long long nblocks, int max_ni, hipStream_t st) {
   if (njobs <= 0 || nblocks <= 0) return HPS_OK;
-  if (max_ni > SRC_THREADS) {
+  if (max_ni > 4 * SRCW_THREADS) {
     set_error("batched solve: at most 256 interior points per leaf");
     return HPS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(leaf_src_multi_kernel, dim3((unsigned)nblocks), dim3(SRC_THREADS), 2 * max_ni * sizeof(int), st,
-                     dev_jobs, njobs);
+  hipLaunchKernelGGL(leaf_src_multi_kernel, dim3((unsigned)nblocks), dim3(SRCW_THREADS), 0, st, dev_jobs, njobs);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
@@ -557,28 +603,27 @@ int leaf_out_multi_launch(const LeafJob* dev_jobs, int njobs, long long nblocks,
 // fp32 copies of the LU factors; r is an fp64 interior-point residual
 // [leaf][NRcap][NI].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SRC_THREADS) void leaf_src_f32_kernel(const float* __restrict__ LUall,
-                                                                   const int* __restrict__ permall,
-                                                                   const int* __restrict__ posall,
-                                                                   const double* __restrict__ r, int NI, int nrhs,
-                                                                   int NRcap, float* __restrict__ vout) {
-  __shared__ float s_y[2][SRC_MAXR];
-  extern __shared__ int s_int[];
+__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_f32_kernel(const float* __restrict__ LUall,
+                                                                    const int* __restrict__ permall,
+                                                                    const int* __restrict__ posall,
+                                                                    const double* __restrict__ r, int NI, int nrhs,
+                                                                    int NRcap, float* __restrict__ vout) {
+  __shared__ float s_y[SRC_MAXR];
   const long long leaf = blockIdx.x;
   const double* rl = r + leaf * (long long)NRcap * NI;
   auto at = [=](int j, int k) { return rl[(long long)j * NI + k]; };
-  leaf_src_body<1, float>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
-                          vout + leaf * (long long)NRcap * NI, s_int, s_int + NI, s_y);
+  leaf_src_wave<4, float>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
+                          vout + leaf * (long long)NRcap * NI, s_y);
 }
 
 int leaf_src_f32_launch(const float* LU, const int* perm, const int* pos, const double* r, int NI, long long nl,
                         int nrhs, int NRcap, float* v, hipStream_t st) {
-  if (nrhs > SRC_MAXR || NI > SRC_THREADS) {
+  if (nrhs > SRC_MAXR || NI > 4 * SRCW_THREADS) {
     set_error("leaf_src_f32: at most 16 right-hand sides and 256 interior points");
     return HPS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(leaf_src_f32_kernel, dim3((unsigned)nl), dim3(SRC_THREADS), 2 * NI * sizeof(int), st, LU, perm,
-                     pos, r, NI, nrhs, NRcap, v);
+  hipLaunchKernelGGL(leaf_src_f32_kernel, dim3((unsigned)nl), dim3(SRCW_THREADS), 0, st, LU, perm, pos, r, NI, nrhs,
+                     NRcap, v);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

@@ -51,6 +51,49 @@ __device__ __forceinline__ void amax_scan(double& key, int& row, double& val, do
   val = take ? x : val;
 }
 
+// Packed 32-bit pivot key of an unused row: |x| with 13 mantissa bits kept
+// (exponent and leading mantissa bits of the high word, bits 31..8) above the
+// row's rank code (bits 7..0, larger for a lower row, code > 0).  An unsigned
+// max over keys picks the largest |x| up to a relative 2^-13, ties going to
+// the lower row; NaN and inf keys exceed every finite one.  Used rows take
+// key 0 and so never win against an unused row.
+__device__ __forceinline__ unsigned pivot_key32(double x, int code) {
+  const unsigned hi = (unsigned)__double2hiint(x);
+  return ((hi & 0x7fffff80u) << 1) + (unsigned)code;
+}
+
+// Unsigned max over each aligned group of G = 8 or 16 lanes; every lane of
+// the group ends with it.
+template <int G>
+__device__ __forceinline__ unsigned group_max(unsigned k) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  if (G == 16) {
+    k = max(k, (unsigned)dpp_i<DPP_ROW_ROR8>((int)k));
+    k = max(k, (unsigned)dpp_i<DPP_ROW_ROR4>((int)k));
+  } else {
+    k = max(k, (unsigned)dpp_i<DPP_HALF_MIRROR>((int)k));
+  }
+  k = max(k, (unsigned)dpp_i<DPP_QUAD_XOR2>((int)k));
+  k = max(k, (unsigned)dpp_i<DPP_QUAD_XOR1>((int)k));
+  return k;
+}
+
+// A double from one lane (uniform lane index) to every lane.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// 1/x from the hardware reciprocal estimate and two Newton steps
+// r <- r + r (1 - x r), each taking the relative error e to about e^2.
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 template <int CTRL>
 __device__ __forceinline__ void amax_step(double& key, int& row, double& val) {
   const double ok = dpp_d<CTRL>(key);

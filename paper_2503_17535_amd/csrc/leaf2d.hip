@@ -61,6 +61,7 @@ struct Leaf2DCfg {
   static constexpr int SAUG = AUG_IN_SLOTS > AUG_LATE ? AUG_IN_SLOTS : AUG_LATE;
   static_assert(RJALL <= RJ + 1, "at most one late column block");
   static_assert(64 % TR == 0, "a column group of TR lanes lies inside one wavefront");
+  static_assert(RI * TR <= 255, "row rank codes fit in the 8 low bits of a pivot key");
   static_assert(!EXTRA || RJP >= 2, "late block needs a first pivot block to replay");
 };
 
@@ -122,9 +123,11 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   __shared__ double s_lcol[2][RI * TR];
   __shared__ double s_urow[2][RJ * TC];
   __shared__ double s_xrow[2][NB];
-  __shared__ double s_L0[C::EXTRA ? TC : 1][C::EXTRA ? RI * TR : 1];
+  // block 0's L columns for the late block's replay; later the staged U
+  // columns of the back substitution
+  __shared__ double s_L0[TC][RI * TR];
   __shared__ double s_aug[C::SAUG > 0 ? NI * C::SAUG : 1];
-  __shared__ double s_diag[NI];
+  __shared__ double s_dinv[NI];
   __shared__ int s_perm[NI], s_pos[RI * TR];
   __shared__ int s_piv[2];
   __shared__ int s_active[6];
@@ -134,7 +137,6 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   const int tr = tid % TR, tc = tid / TR;
   const int lane = tid & 63;
   const int gbase = lane - tr;  // first lane of this thread's column group
-  (void)gbase;
 
   // ---- stage coefficients and 1D operators
   const double* cf = coeffs + leaf * 6 * C::NPTS;
@@ -183,28 +185,36 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       if (k >= NI) break;
       const int buf = k & 1;
       if (tc == t) {
-        double key = -1.0, pv = 0.0;
-        int brow = 0x7fffffff;
-#pragma unroll
-        for (int ri = 0; ri < RI; ++ri) amax_scan(key, brow, pv, a[ri][0], tr + TR * ri, (used >> ri) & 1u);
-        group_argmax<TR>(key, brow, pv);
-        const double pinv = 1.0 / pv;
+        // pivot search: the largest |x| over the group's unused rows, as one
+        // unsigned max of packed keys (see pivot_key32), ties to the lower row
+        unsigned key = 0;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
-          const int row = tr + TR * ri;
-          double l = 0.0;
-          if (!((used >> ri) & 1u) && row != brow) {
-            l = a[ri][0] * pinv;
-            a[ri][0] = l;
-          }
-          s_lcol[buf][row] = l;
+          const unsigned kk = pivot_key32(a[ri][0], 255 - tr - TR * ri);
+          key = max(key, ((used >> ri) & 1u) ? 0u : kk);
+        }
+        key = group_max<TR>(key);
+        const int brow = __builtin_amdgcn_readfirstlane(255 - (int)(key & 255u));  // uniform in the group
+        const int bri = brow / TR, btr = brow % TR;
+        double v = 0.0;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri)
+          if (ri == bri) v = a[ri][0];
+        const double pv = readlane_d(v, __builtin_amdgcn_readfirstlane(gbase) + btr);
+        const double pinv = recip_nr(pv);
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+          const bool keep = ((used >> ri) & 1u) || (ri == bri && tr == btr);
+          const double l = keep ? 0.0 : a[ri][0] * pinv;
+          if (!keep) a[ri][0] = l;
+          s_lcol[buf][tr + TR * ri] = l;
         }
         if (tr == 0) {
           s_piv[buf] = brow;
           s_perm[k] = brow;
           s_pos[brow] = k;
-          s_diag[k] = pv;
-          if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 1);
+          s_dinv[k] = pinv;
+          if (!(pv != 0.0) || !isfinite(pv) || !isfinite(pinv)) atomicOr(flag, 1);
         }
       }
       __syncthreads();
@@ -284,58 +294,46 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
 
   // ---- back substitution of the augmented columns:  U X = (forward-eliminated L_ie P)
   // After the forward pass slot s holds block RF + s (RF = RJP - 1 rotations);
-  // only NLB slots are live.  A row with pos < k holds the U entry of column k.
+  // only NLB slots are live.  Blocked by TC columns: the block's U columns
+  // (entries of rows pivoted before the column, zero elsewhere) are staged in
+  // LDS once; then each column group, whose TR lanes hold every row of its
+  // columns, runs the block's steps on its own with x_k broadcast inside the
+  // group, so a block costs two workgroup barriers instead of one per step.
   constexpr int RF = RJP - 1;
   constexpr int NLB = (NBLK - RF) < RJ ? (NBLK - RF) : RJ;
-  double ub[RI];
+  constexpr int RT = RI * TR;
   for (int kb = RJP - 1; kb >= 0; --kb) {
-    if (kb < RJP - 1) {
-      const int col = kb * TC + tc;
-#pragma unroll
-      for (int ri = 0; ri < RI; ++ri)
-        ub[ri] = (tr + TR * ri < NI) ? LUl[tr + TR * ri + (long long)col * NI] : 0.0;
-    } else {
-#pragma unroll
-      for (int ri = 0; ri < RI; ++ri) ub[ri] = a[ri][0];
+    if (kb < RJP - 1) __syncthreads();  // the previous block's reads are done
+    for (int e = tid; e < TC * RT; e += NT) {
+      const int c = e / RT, row = e % RT, k = kb * TC + c;
+      double u = 0.0;
+      if (k < NI && row < NI && s_pos[row] < k) u = LUl[row + (long long)k * NI];
+      s_L0[c][row] = u;
     }
+    __syncthreads();
     for (int t = TC - 1; t >= 0; --t) {
       const int k = kb * TC + t;
       if (k >= NI) continue;
-      const int buf = k & 1;
-      const int pr = __builtin_amdgcn_readfirstlane(s_perm[k]);  // uniform: scalar branches below
-      if (tc == t) {
+      const int pr = __builtin_amdgcn_readfirstlane(s_perm[k]);  // uniform
+      const int rip = pr / TR, trp = pr % TR;
+      const double dinv = s_dinv[k];
+      double x[NLB];
+      // x_k of each live column: the pivot row's entry, scaled, from lane trp;
+      // the uniform register index becomes a scalar branch
+      static_for<0, RI>([&](auto ric) {
+        constexpr int R = decltype(ric)::value;
+        if (R == rip) {
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri) {
-          const int row = tr + TR * ri;
-          const int pk = s_pos[row];
-          s_lcol[buf][row] = (pk >= 0 && pk < k) ? ub[ri] : 0.0;
-        }
-      }
-      if (tr == pr % TR) {
-        const int rip = pr / TR;  // uniform: one scalar branch is taken
-        const double dinv = 1.0 / s_diag[k];
-#pragma unroll
-        for (int ri = 0; ri < RI; ++ri)
-          if (ri == rip) {
-#pragma unroll
-            for (int s = 0; s < NLB; ++s) {
-              const int col = (RF + s) * TC + tc;
-              if (col < NI || col >= NC) continue;
-              const double x = a[ri][s] * dinv;
-              a[ri][s] = x;
-              s_xrow[buf][col - NI] = x;
-            }
+          for (int s = 0; s < NLB; ++s) {
+            x[s] = __shfl(a[R][s] * dinv, gbase + trp);
+            if (tr == trp) a[R][s] = x[s];
           }
-      }
-      __syncthreads();
+        }
+      });
 #pragma unroll
-      for (int s = 0; s < NLB; ++s) {
-        const int col = (RF + s) * TC + tc;
-        if (col < NI || col >= NC) continue;
-        const double x = s_xrow[buf][col - NI];
+      for (int s = 0; s < NLB; ++s)
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri) a[ri][s] -= s_lcol[buf][tr + TR * ri] * x;
-      }
+        for (int ri = 0; ri < RI; ++ri) a[ri][s] -= s_L0[t][tr + TR * ri] * x[s];
     }
   }
 

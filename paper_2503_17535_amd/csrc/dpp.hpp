@@ -51,15 +51,17 @@ __device__ __forceinline__ void amax_scan(double& key, int& row, double& val, do
   val = take ? x : val;
 }
 
-// Packed 32-bit pivot key of an unused row: |x| with 13 mantissa bits kept
-// (exponent and leading mantissa bits of the high word, bits 31..8) above the
-// row's rank code (bits 7..0, larger for a lower row, code > 0).  An unsigned
-// max over keys picks the largest |x| up to a relative 2^-13, ties going to
-// the lower row; NaN and inf keys exceed every finite one.  Used rows take
-// key 0 and so never win against an unused row.
+// Packed 32-bit pivot key of an unused row: |x| above the row's rank code
+// (the B low bits, larger for a lower row, code > 0).  The high word of |x|
+// keeps its exponent and leading 21 - B mantissa bits (13 for B = 8).  An
+// unsigned max over keys picks the largest |x| up to a relative 2^(B-21),
+// ties going to the lower row; NaN and inf keys exceed every finite one.
+// Used rows take key 0 and so never win against an unused row.
+template <int B = 8>
 __device__ __forceinline__ unsigned pivot_key32(double x, int code) {
+  static_assert(B >= 8 && B <= 16, "code bits");
   const unsigned hi = (unsigned)__double2hiint(x);
-  return ((hi & 0x7fffff80u) << 1) + (unsigned)code;
+  return ((hi & (0x7fffffffu & ~((1u << (B - 1)) - 1u))) << 1) + (unsigned)code;
 }
 
 // Unsigned max over each aligned group of G = 8 or 16 lanes; every lane of
@@ -76,6 +78,14 @@ __device__ __forceinline__ unsigned group_max(unsigned k) {
   k = max(k, (unsigned)dpp_i<DPP_QUAD_XOR2>((int)k));
   k = max(k, (unsigned)dpp_i<DPP_QUAD_XOR1>((int)k));
   return k;
+}
+
+// Unsigned max over the whole wavefront (uniform result).
+__device__ __forceinline__ unsigned wave_max(unsigned k) {
+  k = group_max<16>(k);
+  const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)k, 0), (unsigned)__builtin_amdgcn_readlane((int)k, 16));
+  const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)k, 32), (unsigned)__builtin_amdgcn_readlane((int)k, 48));
+  return max(a, b);
 }
 
 // A double from one lane (uniform lane index) to every lane.

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "dpp.hpp"
@@ -33,11 +34,12 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
                                                            int m, int* __restrict__ flag) {
   constexpr int NT = TR * TC;
   static_assert(64 % TR == 0, "a column group of TR lanes lies inside one wavefront");
+  static_assert(RI * TR <= 255, "row rank codes fit in the 8 low bits of a pivot key");
   __shared__ double s_lcol[2][RI * TR];
   __shared__ double s_urow[2][RJ * TC];
   __shared__ int s_perm[RJ * TC], s_pos[RI * TR];
   __shared__ int s_piv[2];
-  __shared__ double s_pv[2];
+  __shared__ double s_pinv[2];
 
   const long long b = blockIdx.x;
   const double* D = Din + b * (long long)m * m;
@@ -69,22 +71,32 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
       if (k >= m) break;
       const int buf = k & 1;
       if (tc == t) {
-        double key = -1.0, pv = 0.0;
-        int brow = 0x7fffffff;
-#pragma unroll
-        for (int ri = 0; ri < RI; ++ri) amax_scan(key, brow, pv, a[ri][0], tr + TR * ri, (used >> ri) & 1u);
-        group_argmax<TR>(key, brow, pv);
+        // pivot search: unsigned max of packed keys (pivot_key32), ties to
+        // the lower row; the pivot value comes from its lane by readlane
+        unsigned key = 0;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
-          const int row = tr + TR * ri;
-          s_lcol[buf][row] = (row == brow) ? 0.0 : a[ri][0];
+          const unsigned kk = pivot_key32(a[ri][0], 255 - tr - TR * ri);
+          key = max(key, ((used >> ri) & 1u) ? 0u : kk);
         }
+        key = group_max<TR>(key);
+        const int brow = __builtin_amdgcn_readfirstlane(255 - (int)(key & 255u));  // uniform in the group
+        const int bri = brow / TR, btr = brow % TR;
+        double v = 0.0;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri)
+          if (ri == bri) v = a[ri][0];
+        const double pv = readlane_d(v, __builtin_amdgcn_readfirstlane(gbase) + btr);
+        const double pinv = recip_nr(pv);
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri)
+          s_lcol[buf][tr + TR * ri] = (ri == bri && tr == btr) ? 0.0 : a[ri][0];
         if (tr == 0) {
           s_piv[buf] = brow;
-          s_pv[buf] = pv;
+          s_pinv[buf] = pinv;
           s_perm[k] = brow;
           s_pos[brow] = k;
-          if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
+          if (!(pv != 0.0) || !isfinite(pv) || !isfinite(pinv)) atomicOr(flag, 2);
         }
       }
       __syncthreads();
@@ -92,7 +104,7 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
       if (tr == pr % TR) {
         const int rip = pr / TR;  // uniform: one scalar branch is taken
         used |= 1u << rip;
-        const double pinv = 1.0 / s_pv[buf];
+        const double pinv = s_pinv[buf];
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri)
           if (ri == rip) {
@@ -198,17 +210,37 @@ __global__ void gj_init_kernel(int* pos, long long n) {
   if (i < n) pos[i] = -1;
 }
 
+// Compile-time loop: f(integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void gj_static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    gj_static_for<B + 1, E>(f);
+  }
+}
+
+// bits of a row rank code for n rows: codes 2^b - 1 - row stay >= 1
+constexpr int rank_code_bits(int n) { return n < 256 ? 8 : 1 + rank_code_bits(n / 2); }
+
 // One Gauss-Jordan panel: columns [j0, j0+nbw) of every row, rows
 // distributed cyclically over the workgroup (row = tid + 512 i), in registers.
+// The column loop is expanded at compile time, so panel column c stays in
+// register slot c.  Per column: each wavefront finds its best unused row
+// (packed keys, pivot_key32) and publishes that row's panel entries already
+// scaled by its own reciprocal pivot; one barrier; every thread takes the
+// best of the NW candidates and applies the rank-1 Gauss-Jordan update.
 template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                   int* __restrict__ posall, int* __restrict__ pivall,
                                                                   double* __restrict__ Wall, double* __restrict__ snapall,
                                                                   int* __restrict__ flag) {
   constexpr int NW = PANEL_THREADS / 64;
-  __shared__ double s_ck[2][NW], s_cv[2][NW];
-  __shared__ int s_cr[2][NW];
-  __shared__ double s_cand[2][NW][NB];  // each wavefront's candidate pivot row
+  constexpr int CB = rank_code_bits(RPT * PANEL_THREADS);
+  constexpr int CMAX = (1 << CB) - 1;
+  static_assert(CB <= 16, "row codes fit a pivot key");
+  __shared__ unsigned s_key[2][NW];
+  __shared__ double s_cpinv[2][NW];
+  __shared__ double s_cand[2][NW][NB];  // each wavefront's candidate pivot row, scaled
   __shared__ int s_piv[NB];
 
   const long long b = blockIdx.x;
@@ -230,77 +262,69 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
     if (row >= m || pos[row] >= 0) used |= 1u << i;
   }
 
-  // column c of the panel sits in register slot 0 while it is the pivot
-  // column: the slots rotate left once per column (a full cycle per panel)
-  for (int c = 0; c < NB; ++c) {
-    if (c < nbw) {
-      const int k = j0 + c;
-      const int buf = c & 1;
-      double key = -1.0, val = 0.0;
-      int brow = 0x7fffffff;
+  gj_static_for<0, NB>([&](auto cc_) __attribute__((always_inline)) {
+    constexpr int c = decltype(cc_)::value;
+    if (c >= nbw) return;
+    constexpr int buf = c & 1;
+    unsigned key = 0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) amax_scan(key, brow, val, a[i][0], tid + PANEL_THREADS * i, (used >> i) & 1u);
-      wave_argmax(key, brow, val);
-      // the lane holding this wavefront's candidate row publishes the row's
-      // panel entries with the candidate, so one barrier serves both the
-      // cross-wavefront argmax and the pivot-row broadcast
-      const int crow = __builtin_amdgcn_readfirstlane(brow);
-      if (lane == 0) { s_ck[buf][wave] = key; s_cr[buf][wave] = brow; s_cv[buf][wave] = val; }
-      if (crow < m && tid == crow % PANEL_THREADS) {
-        const int ip = crow / PANEL_THREADS;
+    for (int i = 0; i < RPT; ++i) {
+      const unsigned kk = pivot_key32<CB>(a[i][c], CMAX - (tid + PANEL_THREADS * i));
+      key = max(key, ((used >> i) & 1u) ? 0u : kk);
+    }
+    const unsigned wkey = wave_max(key);  // uniform
+    const int crow = CMAX - (int)(wkey & (unsigned)CMAX);
+    if (lane == 0) s_key[buf][wave] = wkey;
+    if (tid == crow % PANEL_THREADS) {
+      const int ip = crow / PANEL_THREADS;  // uniform: one scalar branch is taken
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
-          if (i == ip) {
+      for (int i = 0; i < RPT; ++i)
+        if (i == ip) {
+          const double cpinv = recip_nr(a[i][c]);
+          s_cpinv[buf][wave] = cpinv;
 #pragma unroll
-            for (int cc = 0; cc < NB; ++cc) s_cand[buf][wave][cc] = a[i][cc];
-          }
-      }
-      __syncthreads();
-      key = s_ck[buf][0]; brow = s_cr[buf][0]; val = s_cv[buf][0];
-      int wbest = 0;
-#pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const double ok = s_ck[buf][w];
-        const int orow = s_cr[buf][w];
-        if (ok > key || (ok == key && orow < brow)) {
-          key = ok;
-          brow = orow;
-          val = s_cv[buf][w];
-          wbest = w;
+          for (int cc = 0; cc < NB; ++cc) s_cand[buf][wave][cc] = a[i][cc] * cpinv;
+          // a distinct marker closing each branch keeps the compiler from
+          // sinking the branches into one dynamically indexed access, which
+          // would move the register array to scratch memory
+          __asm__ volatile("; candidate row slot %0" ::"n"(i));
         }
-      }
-      const int pr = __builtin_amdgcn_readfirstlane(brow);  // uniform: scalar branches below
-      const int wb = __builtin_amdgcn_readfirstlane(wbest);
-      const double pv = val;
-      if (tid == pr % PANEL_THREADS) {
-        const int ip = pr / PANEL_THREADS;
+    }
+    __syncthreads();
+    unsigned best = s_key[buf][0];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
-          if (i == ip) used |= 1u << i;
-        s_piv[c] = pr;  // pos / piv go to global memory after the panel
-        if (!(pv != 0.0) || !isfinite(pv)) atomicOr(flag, 2);
-      }
-      const double pinv = 1.0 / pv;
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int row = tid + PANEL_THREADS * i;
-        const double l = a[i][0];
-        const bool isp = row == pr;
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) {
-          const double u = (cc == 0 ? 1.0 : s_cand[buf][wb][cc]) * pinv;
-          a[i][cc] = isp ? u : ((cc == 0 ? 0.0 : a[i][cc]) - l * u);
-        }
-      }
+    for (int w = 1; w < NW; ++w) best = max(best, s_key[buf][w]);
+    const int pr = __builtin_amdgcn_readfirstlane(CMAX - (int)(best & (unsigned)CMAX));  // uniform
+    const int wb = (pr % PANEL_THREADS) / 64;
+    const double pinv = s_cpinv[buf][wb];
+    const bool owner = tid == pr % PANEL_THREADS;
+    if (owner) {
+      used |= 1u << (pr / PANEL_THREADS);
+      s_piv[c] = pr;  // pos / piv go to global memory after the panel
+      if (!(pinv != 0.0) || !isfinite(pinv)) atomicOr(flag, 2);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const double first = a[i][0];
+      const double l = a[i][c];
 #pragma unroll
-      for (int cc = 0; cc + 1 < NB; ++cc) a[i][cc] = a[i][cc + 1];
-      a[i][NB - 1] = first;
+      for (int cc = 0; cc < NB; ++cc) {
+        if (cc == c)
+          a[i][cc] = -l * pinv;  // column k becomes the k-th column of the elimination operator
+        else
+          a[i][cc] -= l * s_cand[buf][wb][cc];
+      }
     }
-  }
+    if (owner) {
+      const int ip = pr / PANEL_THREADS;  // uniform: one scalar branch is taken
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == ip) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) a[i][cc] = cc == c ? pinv : s_cand[buf][wb][cc];
+          __asm__ volatile("; pivot row slot %0" ::"n"(i));
+        }
+    }
+  });
   __syncthreads();
   if (tid < nbw) {
     pos[s_piv[tid]] = j0 + tid;

@@ -36,7 +36,9 @@ int gj_small_max();
 int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batch, hipStream_t st);
 int gj_panel_width(int m);
 int gj_panel_max_nb();
-int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
+int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, int w, long long batch,
+                     hipStream_t st);
+int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, int* flag,
                     long long batch, hipStream_t st);
 int gj_init_launch(int* pos, long long n, hipStream_t st);
 int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
@@ -339,23 +341,9 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
   g->pos = (int*)op_alloc(op, sizeof(int) * batch * m, false);
   g->piv = (int*)op_alloc(op, sizeof(int) * batch * m, false);
   g->W = (double*)op_alloc(op, sizeof(double) * batch * m * mnb, false);
-  g->snap = (double*)op_alloc(op, sizeof(double) * batch * m * mnb, false);
-  if (!g->pos || !g->piv || !g->W || !g->snap) {
+  if (!g->pos || !g->piv || !g->W) {
     set_error("device allocation failed (Gauss-Jordan workspace)");
     return HPS_ENOMEM;
-  }
-  const long long sw = (long long)m * mnb;  // W: m x mnb (ld m); snapshot: mnb x m (ld mnb)
-  const long long sm = (long long)m * m;
-  for (int j0 = 0; j0 < m; j0 += g->nb) {
-    const int w = std::min(g->nb, m - j0);
-    std::vector<GemmGroup> gs;
-    if (j0 > 0) gs.push_back(make_group(g->W, sw, m, g->snap, sw, mnb, A, sm, m, m, j0, w, 1.0, 1.0, batch, A, sm, m));
-    if (j0 + w < m)
-      gs.push_back(make_group(g->W, sw, m, g->snap + (long long)(j0 + w) * mnb, sw, mnb, A + (long long)(j0 + w) * m,
-                              sm, m, m, m - j0 - w, w, 1.0, 1.0, batch, A + (long long)(j0 + w) * m, sm, m));
-    GemmCall c;
-    add_gemm(op, gs, &c);
-    g->upd.push_back(c);
   }
   return HPS_OK;
 }
@@ -363,11 +351,10 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
 int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
   if (g.small) return gj_small_launch(g.A, g.Z, g.m, op->flag, g.batch, st);
   HPS_TRY(gj_init_launch(g.pos, g.batch * g.m, st));
-  int step = 0;
-  for (int j0 = 0; j0 < g.m; j0 += g.nb, ++step) {
+  for (int j0 = 0; j0 < g.m; j0 += g.nb) {
     const int w = std::min(g.nb, g.m - j0);
-    HPS_TRY(gj_panel_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W, g.snap, op->flag, g.batch, st));
-    HPS_TRY(run_gemm(op, g.upd[step], st));
+    HPS_TRY(gj_panel_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W, op->flag, g.batch, st));
+    HPS_TRY(gj_update_launch(g.A, g.W, g.piv, g.m, j0, w, g.batch, st));
   }
   return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
 }

@@ -232,8 +232,7 @@ constexpr int rank_code_bits(int n) { return n < 256 ? 8 : 1 + rank_code_bits(n 
 template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                   int* __restrict__ posall, int* __restrict__ pivall,
-                                                                  double* __restrict__ Wall, double* __restrict__ snapall,
-                                                                  int* __restrict__ flag) {
+                                                                  double* __restrict__ Wall, int* __restrict__ flag) {
   constexpr int NW = PANEL_THREADS / 64;
   constexpr int CB = rank_code_bits(RPT * PANEL_THREADS);
   constexpr int CMAX = (1 << CB) - 1;
@@ -248,7 +247,6 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
   int* pos = posall + b * (long long)m;
   int* piv = pivall + b * (long long)m;
   double* W = Wall + b * (long long)m * PANEL_MAX_NB;
-  double* snap = snapall + b * (long long)m * PANEL_MAX_NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   double a[RPT][NB];
@@ -345,14 +343,76 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
       }
     }
   }
-  // snapshot of the pivot rows outside the panel (before the GEMM updates them)
-  for (long long e = tid; e < (long long)NB * m; e += PANEL_THREADS) {
-    const int c = (int)(e % NB);
-    const int col = (int)(e / NB);
-    double v = 0.0;
-    if (c < nbw && (col < j0 || col >= j0 + nbw)) v = A[s_piv[c] + (long long)col * m];
-    snap[c + (long long)col * PANEL_MAX_NB] = v;
+}
+
+// Gauss-Jordan update of the columns outside the panel [j0, j0 + w):
+//   A(:, j) += W A(piv[j0 .. j0+w), j)   (W = panel - E_P, written by the panel kernel)
+// A workgroup owns GU_COLS whole columns: it first stages the (old) pivot-row
+// entries of its columns in LDS, then rewrites its columns, so no other
+// workgroup can overwrite a pivot row before it is read.
+constexpr int GU_THREADS = 256;
+constexpr int GU_COLS = 8;
+constexpr int GU_ROWS = 4;  // rows per thread and pass
+__global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restrict__ Aall, const double* __restrict__ Wall,
+                                                               const int* __restrict__ pivall, int m, int j0, int w) {
+  __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
+  const long long b = blockIdx.y;
+  double* A = Aall + b * (long long)m * m;
+  const double* W = Wall + b * (long long)m * PANEL_MAX_NB;
+  const int* piv = pivall + b * (long long)m;
+  const int tid = threadIdx.x;
+  const int nout = m - w;                  // columns outside the panel
+  const int q0 = blockIdx.x * GU_COLS;     // first outside column of this workgroup
+  auto colof = [&](int q) { return q < j0 ? q : q + w; };
+  for (int e = tid; e < PANEL_MAX_NB * GU_COLS; e += GU_THREADS) {
+    const int c = e / GU_COLS, jj = e % GU_COLS, q = q0 + jj;
+    s_p[c][jj] = (c < w && q < nout) ? A[piv[j0 + c] + (long long)colof(q) * m] : 0.0;
   }
+  __syncthreads();
+  double* colp[GU_COLS];
+#pragma unroll
+  for (int jj = 0; jj < GU_COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
+  for (int r0 = 0; r0 < m; r0 += GU_THREADS * GU_ROWS) {
+    double acc[GU_ROWS][GU_COLS];
+#pragma unroll
+    for (int i = 0; i < GU_ROWS; ++i) {
+      const int r = r0 + tid + GU_THREADS * i;
+#pragma unroll
+      for (int jj = 0; jj < GU_COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
+    }
+    for (int c = 0; c < w; ++c) {
+      double wr[GU_ROWS];
+#pragma unroll
+      for (int i = 0; i < GU_ROWS; ++i) {
+        const int r = r0 + tid + GU_THREADS * i;
+        wr[i] = r < m ? W[r + (long long)c * m] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < GU_COLS; ++jj) {
+        const double pc = s_p[c][jj];
+#pragma unroll
+        for (int i = 0; i < GU_ROWS; ++i) acc[i][jj] += wr[i] * pc;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < GU_ROWS; ++i) {
+      const int r = r0 + tid + GU_THREADS * i;
+      if (r >= m) continue;
+#pragma unroll
+      for (int jj = 0; jj < GU_COLS; ++jj)
+        if (q0 + jj < nout) colp[jj][r] = acc[i][jj];
+    }
+  }
+}
+
+int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, int w, long long batch,
+                     hipStream_t st) {
+  const int nout = m - w;
+  if (nout <= 0) return HPS_OK;
+  dim3 grid((unsigned)((nout + GU_COLS - 1) / GU_COLS), (unsigned)batch);
+  hipLaunchKernelGGL(gj_update_kernel, grid, dim3(GU_THREADS), 0, st, A, W, piv, m, j0, w);
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
 }
 
 int gj_panel_width(int m) {
@@ -364,19 +424,19 @@ int gj_panel_width(int m) {
 }
 int gj_panel_max_nb() { return PANEL_MAX_NB; }
 
-int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, double* snap, int* flag,
-                    long long batch, hipStream_t st) {
+int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, int* flag, long long batch,
+                    hipStream_t st) {
   dim3 grid((unsigned)batch), block(PANEL_THREADS);
   if (m <= 512)
-    hipLaunchKernelGGL((gj_panel_kernel<1, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<1, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 1024)
-    hipLaunchKernelGGL((gj_panel_kernel<2, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<2, 32>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 2048)
-    hipLaunchKernelGGL((gj_panel_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 4096)
-    hipLaunchKernelGGL((gj_panel_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 8192)
-    hipLaunchKernelGGL((gj_panel_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, snap, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else {
     set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
     return HPS_EUNSUPPORTED;

@@ -39,8 +39,7 @@ struct GJPlan {
   bool small = true;
   int nb = 0;
   int *pos = nullptr, *piv = nullptr;
-  double *W = nullptr, *snap = nullptr;
-  std::vector<GemmCall> upd;
+  double* W = nullptr;
 };
 
 struct LevelPlan {

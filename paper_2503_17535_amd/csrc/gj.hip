@@ -353,6 +353,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
 constexpr int GU_THREADS = 256;
 constexpr int GU_COLS = 8;
 constexpr int GU_ROWS = 4;  // rows per thread and pass
+constexpr int GU_KC = 8;    // panel columns per chunk of W loads
 __global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restrict__ Aall, const double* __restrict__ Wall,
                                                                const int* __restrict__ pivall, int m, int j0, int w) {
   __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
@@ -380,19 +381,24 @@ __global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restric
 #pragma unroll
       for (int jj = 0; jj < GU_COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
     }
-    for (int c = 0; c < w; ++c) {
-      double wr[GU_ROWS];
+    // K loop in chunks of GU_KC with every W load of a chunk issued first
+    for (int c0 = 0; c0 < w; c0 += GU_KC) {
+      double wr[GU_KC][GU_ROWS];
 #pragma unroll
-      for (int i = 0; i < GU_ROWS; ++i) {
-        const int r = r0 + tid + GU_THREADS * i;
-        wr[i] = r < m ? W[r + (long long)c * m] : 0.0;
-      }
+      for (int cc = 0; cc < GU_KC; ++cc)
 #pragma unroll
-      for (int jj = 0; jj < GU_COLS; ++jj) {
-        const double pc = s_p[c][jj];
+        for (int i = 0; i < GU_ROWS; ++i) {
+          const int r = r0 + tid + GU_THREADS * i;
+          wr[cc][i] = (r < m && c0 + cc < w) ? W[r + (long long)(c0 + cc) * m] : 0.0;
+        }
 #pragma unroll
-        for (int i = 0; i < GU_ROWS; ++i) acc[i][jj] += wr[i] * pc;
-      }
+      for (int cc = 0; cc < GU_KC; ++cc)
+#pragma unroll
+        for (int jj = 0; jj < GU_COLS; ++jj) {
+          const double pc = s_p[c0 + cc][jj];
+#pragma unroll
+          for (int i = 0; i < GU_ROWS; ++i) acc[i][jj] += wr[cc][i] * pc;
+        }
     }
 #pragma unroll
     for (int i = 0; i < GU_ROWS; ++i) {

@@ -64,6 +64,13 @@ __device__ __forceinline__ unsigned pivot_key32(double x, int code) {
   return ((hi & (0x7fffffffu & ~((1u << (B - 1)) - 1u))) << 1) + (unsigned)code;
 }
 
+// The same key for codes below 256 in two instructions (and-or): the high
+// word of |x| with its low 8 bits (the lowest mantissa bits) replaced by the
+// code, i.e. |x| to 12 mantissa bits.
+__device__ __forceinline__ unsigned pivot_key32_c8(double x, int code) {
+  return ((unsigned)__double2hiint(x) & 0x7fffff00u) | (unsigned)code;
+}
+
 // Unsigned max over each aligned group of G = 8 or 16 lanes; every lane of
 // the group ends with it.
 template <int G>

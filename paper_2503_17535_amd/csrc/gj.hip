@@ -71,12 +71,12 @@ __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restri
       if (k >= m) break;
       const int buf = k & 1;
       if (tc == t) {
-        // pivot search: unsigned max of packed keys (pivot_key32), ties to
-        // the lower row; the pivot value comes from its lane by readlane
+        // pivot search: unsigned max of packed keys (pivot_key32_c8), ties
+        // to the lower row; the pivot value comes from its lane by readlane
         unsigned key = 0;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
-          const unsigned kk = pivot_key32(a[ri][0], 255 - tr - TR * ri);
+          const unsigned kk = pivot_key32_c8(a[ri][0], 255 - tr - TR * ri);
           key = max(key, ((used >> ri) & 1u) ? 0u : kk);
         }
         key = group_max<TR>(key);

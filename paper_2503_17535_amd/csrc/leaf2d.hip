@@ -186,11 +186,12 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       const int buf = k & 1;
       if (tc == t) {
         // pivot search: the largest |x| over the group's unused rows, as one
-        // unsigned max of packed keys (see pivot_key32), ties to the lower row
+        // unsigned max of packed keys (pivot_key32_c8: |x| to 12 mantissa bits
+        // above the row's rank code 255 - row), ties to the lower row
         unsigned key = 0;
 #pragma unroll
         for (int ri = 0; ri < RI; ++ri) {
-          const unsigned kk = pivot_key32(a[ri][0], 255 - tr - TR * ri);
+          const unsigned kk = pivot_key32_c8(a[ri][0], 255 - tr - TR * ri);
           key = max(key, ((used >> ri) & 1u) ? 0u : kk);
         }
         key = group_max<TR>(key);
@@ -311,12 +312,18 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
       s_L0[c][row] = u;
     }
     __syncthreads();
-    for (int t = TC - 1; t >= 0; --t) {
+    const int tlast = (NI - kb * TC) < TC ? (NI - kb * TC) : TC;  // steps in this block
+    int pr_n = s_perm[kb * TC + tlast - 1];
+    double dinv_n = s_dinv[kb * TC + tlast - 1];
+    for (int t = tlast - 1; t >= 0; --t) {
       const int k = kb * TC + t;
-      if (k >= NI) continue;
-      const int pr = __builtin_amdgcn_readfirstlane(s_perm[k]);  // uniform
+      const int pr = __builtin_amdgcn_readfirstlane(pr_n);  // uniform
       const int rip = pr / TR, trp = pr % TR;
-      const double dinv = s_dinv[k];
+      const double dinv = dinv_n;
+      if (t > 0) {  // the next step's pivot row and reciprocal, ahead of time
+        pr_n = s_perm[k - 1];
+        dinv_n = s_dinv[k - 1];
+      }
       double x[NLB];
       // x_k of each live column: the pivot row's entry, scaled, from lane trp;
       // the uniform register index becomes a scalar branch

@@ -223,9 +223,11 @@ int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta 
 }
 
 // Split a table of block ops into workgroup tasks of about kTaskElems elements
-// (runtime-column ops count as 16 columns).
+// (runtime-column ops count as 16 columns); long ops are cut by rows and
+// columns, so no workgroup copies more than about kTaskElems elements.
 void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
   constexpr long long kTaskElems = 16384;
+  constexpr int kRtCols = 16;
   const int op0 = (int)op->hops.size();
   op->hops.insert(op->hops.end(), ops.begin(), ops.end());
   call->first_task = (int)op->htasks.size();
@@ -236,24 +238,31 @@ void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
     cur.begin = cur.end = (int)op->hitems.size();
     load = 0;
   };
+  auto push = [&](int opi, int r0, int r1, int c0, int c1, long long e) {
+    if (load + e > kTaskElems) flush();
+    op->hitems.push_back({opi, r0, r1, c0, c1});
+    cur.end = (int)op->hitems.size();
+    load += e;
+  };
   for (size_t i = 0; i < ops.size(); ++i) {
     const BlockOp& o = ops[i];
+    const int opi = op0 + (int)i;
     if (o.cols <= 0) {
-      const long long e = (long long)o.rows * 16;
-      if (load + e > kTaskElems) flush();
-      op->hitems.push_back({op0 + (int)i, 0, -1});
-      cur.end = (int)op->hitems.size();
-      load += e;
+      const int rchunk = (int)std::max<long long>(1, kTaskElems / kRtCols);
+      for (int r0 = 0; r0 < o.rows; r0 += rchunk) {
+        const int r1 = std::min(o.rows, r0 + rchunk);
+        push(opi, r0, r1, 0, -1, (long long)(r1 - r0) * kRtCols);
+      }
       continue;
     }
-    const int chunk = (int)std::max<long long>(1, kTaskElems / std::max(1, o.rows));
-    for (int c0 = 0; c0 < o.cols; c0 += chunk) {
-      const int c1 = std::min(o.cols, c0 + chunk);
-      const long long e = (long long)o.rows * (c1 - c0);
-      if (load + e > kTaskElems) flush();
-      op->hitems.push_back({op0 + (int)i, c0, c1});
-      cur.end = (int)op->hitems.size();
-      load += e;
+    const int rchunk = (int)std::min<long long>(std::max(1, o.rows), kTaskElems);
+    const int cchunk = (int)std::max<long long>(1, kTaskElems / rchunk);
+    for (int r0 = 0; r0 < o.rows; r0 += rchunk) {
+      const int r1 = std::min(o.rows, r0 + rchunk);
+      for (int c0 = 0; c0 < o.cols; c0 += cchunk) {
+        const int c1 = std::min(o.cols, c0 + cchunk);
+        push(opi, r0, r1, c0, c1, (long long)(r1 - r0) * (c1 - c0));
+      }
     }
   }
   flush();

@@ -77,7 +77,7 @@ struct BlockOp {
 // run of consecutive items, sized so that every workgroup moves a similar
 // number of elements.
 struct CopyItem {
-  int op, c0, c1;
+  int op, r0, r1, c0, c1;  // rows [r0, r1), columns [c0, c1) (c1 < 0: the run-time column count)
 };
 struct CopyTask {
   int begin, end;

@@ -38,10 +38,10 @@ __device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops,
     const T* S1 = nullptr;
     if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
     if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
-    const int rows = op.rows;
+    const int rows = item.r1 - item.r0;
     const int n = rows * (c1 - c0);
     for (int e = threadIdx.x; e < n; e += BC_THREADS) {
-      const int r = e % rows, c = c0 + e / rows;
+      const int r = item.r0 + e % rows, c = c0 + e / rows;
       T v = T(0);
       if (S0) v = S0[r + (long long)c * op.src_ld[0]];
       if (S1) v += S1[r + (long long)c * op.src_ld[1]];

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -211,6 +213,12 @@ void* op_alloc(hps_op* op, size_t bytes, bool resident = true) {
 }
 
 int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta = false, bool tb = false) {
+  static const bool dump = std::getenv("HPS_PLAN_DUMP") != nullptr;  // diagnostic: the planned GEMM table
+  if (dump) {
+    std::fprintf(stderr, "gemm call %zu: %zu groups ta=%d tb=%d\n", op->hgroups.size(), groups.size(), (int)ta, (int)tb);
+    for (const GemmGroup& g : groups)
+      std::fprintf(stderr, "  M=%d N=%d K=%d batch=%d nseg=%d beta=%g\n", g.M, g.N, g.K, g.batch, g.nseg, g.beta);
+  }
   call->first = (int)op->hgroups.size();
   call->count = (int)groups.size();
   op->split_elems = std::max(op->split_elems, gemm_plan_split(groups));

@@ -101,49 +101,72 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
+  // The next k-tile's global loads are issued into registers before the
+  // current tile's MFMAs, so their latency overlaps the math.
+  T ra[4], rb[4];
+  auto load_tiles = [&](const T* A, const T* B, int k0, int kend) {
+    if (!TA) {
+      const int i = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + i, gk = k0 + kk + 4 * r;
+        ra[r] = (gi < M && gk < kend) ? A[gi + (long long)gk * lda] : T(0);
+      }
+    } else {
+      const int k = tid & 15, ii = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + ii + 16 * r, gk = k0 + k;
+        ra[r] = (gi < M && gk < kend) ? A[gk + (long long)gi * lda] : T(0);
+      }
+    }
+    if (!TB) {
+      const int k = tid & 15, jj = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gj = j0 + jj + 16 * r, gk = k0 + k;
+        rb[r] = (gj < N && gk < kend) ? B[gk + (long long)gj * ldb] : T(0);
+      }
+    } else {
+      const int j = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gj = j0 + j, gk = k0 + kk + 4 * r;
+        rb[r] = (gj < N && gk < kend) ? B[gj + (long long)gk * ldb] : T(0);
+      }
+    }
+  };
+  auto store_tiles = [&]() {
+    if (!TA) {
+      const int i = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) As[kk + 4 * r][i] = ra[r];
+    } else {
+      const int k = tid & 15, ii = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) As[k][ii + 16 * r] = ra[r];
+    }
+    if (!TB) {
+      const int k = tid & 15, jj = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Bs[k][jj + 16 * r] = rb[r];
+    } else {
+      const int j = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Bs[kk + 4 * r][j] = rb[r];
+    }
+  };
+
+  const int kbeg = ks_n > 1 ? ks * g->kchunk : 0;
+  const int kend = ks_n > 1 ? min(K, kbeg + g->kchunk) : K;
   for (int s = 0; s < g->nseg; ++s) {
     const T* A = Abase + g->aseg[s];
     const T* B = Bbase + g->bseg[s];
-    const int kbeg = ks_n > 1 ? ks * g->kchunk : 0;
-    const int kend = ks_n > 1 ? min(K, kbeg + g->kchunk) : K;
+    if (kbeg < kend) load_tiles(A, B, kbeg, kend);
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-      // ---- stage op(A) tile (BM x BK) as As[k][i]
-      if (!TA) {
-        const int i = tid & 63, kk = tid >> 6;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = kk + 4 * r;
-          const int gi = i0 + i, gk = k0 + k;
-          As[k][i] = (gi < M && gk < kend) ? A[gi + (long long)gk * lda] : T(0);
-        }
-      } else {
-        const int k = tid & 15, ii = tid >> 4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = ii + 16 * r;
-          const int gi = i0 + i, gk = k0 + k;
-          As[k][i] = (gi < M && gk < kend) ? A[gk + (long long)gi * lda] : T(0);
-        }
-      }
-      // ---- stage op(B) tile (BK x BN) as Bs[k][j]
-      if (!TB) {
-        const int k = tid & 15, jj = tid >> 4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = jj + 16 * r;
-          const int gj = j0 + j, gk = k0 + k;
-          Bs[k][j] = (gj < N && gk < kend) ? B[gk + (long long)gj * ldb] : T(0);
-        }
-      } else {
-        const int j = tid & 63, kk = tid >> 6;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = kk + 4 * r;
-          const int gj = j0 + j, gk = k0 + k;
-          Bs[k][j] = (gj < N && gk < kend) ? B[gj + (long long)gk * ldb] : T(0);
-        }
-      }
+      store_tiles();
       __syncthreads();
+      if (k0 + BK < kend) load_tiles(A, B, k0 + BK, kend);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int k = 4 * ks + (lane >> 4);
@@ -181,6 +204,20 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
   const T* C0 = g->C0 ? g->C0 + bat * g->sC0 : nullptr;
   const T alpha = g->alpha, beta = g->beta;
   const int ldc = g->ldc, ldc0 = g->ldc0;
+  // C0 may alias C: every C0 value of the tile is loaded (all loads in
+  // flight together) before the first store
+  T c0v[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int row = i0 + wr * 32 + a * 16 + (lane & 15);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + wc * 32 + b * 16 + MfmaOp<T>::col(lane, v);
+        c0v[a][b][v] = (beta != T(0) && row < M && col < N) ? C0[row + (long long)col * ldc0] : T(0);
+      }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int row = i0 + wr * 32 + a * 16 + (lane & 15);
@@ -192,7 +229,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
         const int col = j0 + wc * 32 + b * 16 + MfmaOp<T>::col(lane, v);
         if (col >= N) continue;
         T val = alpha * acc[a][b][v];
-        if (beta != T(0)) val += beta * C0[row + (long long)col * ldc0];
+        if (beta != T(0)) val += beta * c0v[a][b][v];
         C[row + (long long)col * ldc] = val;
       }
     }

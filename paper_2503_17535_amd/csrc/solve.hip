@@ -39,13 +39,22 @@ __device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops,
     if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
     if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
     const int rows = item.r1 - item.r0;
-    const int n = rows * (c1 - c0);
-    for (int e = threadIdx.x; e < n; e += BC_THREADS) {
-      const int r = item.r0 + e % rows, c = c0 + e / rows;
+    if (rows <= 0 || c1 <= c0) continue;
+    // walk the (row, column) pairs of this thread with one division up front
+    const int dq = BC_THREADS / rows, dr = BC_THREADS % rows;
+    int r = threadIdx.x % rows, c = c0 + threadIdx.x / rows;
+    while (c < c1) {
+      const int gr = item.r0 + r;
       T v = T(0);
-      if (S0) v = S0[r + (long long)c * op.src_ld[0]];
-      if (S1) v += S1[r + (long long)c * op.src_ld[1]];
-      D[r + (long long)c * op.dst_ld] = v;
+      if (S0) v = S0[gr + (long long)c * op.src_ld[0]];
+      if (S1) v += S1[gr + (long long)c * op.src_ld[1]];
+      D[gr + (long long)c * op.dst_ld] = v;
+      r += dr;
+      c += dq;
+      if (r >= rows) {
+        r -= rows;
+        ++c;
+      }
     }
   }
 }

@@ -73,16 +73,22 @@ def cpu_baseline(seconds_budget: float = 30.0):
             "build_leaves_per_s": nl / (t1 - t0), "solves_per_s": NRHS / (t2 - t1)}
 
 
+def _leaf_source_hash():
+    """sha256 prefix over the sources of the leaf kernel (kernel + helpers)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("leaf2d.hip", "dpp.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2503_17535_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per launch of the leaf kernel from its committed rocprofv3
-    counter summary, if that summary was taken on the current source."""
-    import hashlib
+    counter summary, if that summary was taken on the current sources."""
     prof = os.path.join(ROOT, "profiles", "leaf2d_factor_kernel_p16_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_2503_17535_amd", "csrc", "leaf2d.hip")
     try:
         txt = open(prof).read()
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if f"sha256 prefix: {h}" not in txt:
+        if f"sources sha256 prefix: {_leaf_source_hash()}" not in txt:
             return None
         for line in txt.splitlines():
             if line.startswith("traffic_bytes_per_launch:"):

@@ -8,8 +8,10 @@
 //   2. factors L_ii by Gaussian elimination with partial pivoting, carrying the
 //      augmented columns along (forward elimination),
 //   3. back-substitutes the augmented columns:  X = L_ii^{-1} L_ie P,
-// and writes the LU factors (for sources at solve time), the pivot order,
-// and Y_int = -X (the interior rows of Y = [I; -L_ii^{-1} L_ie] P).
+// and writes the LU factors (for sources at solve time; column s holds the U
+// entries in pivot order, then the L entries of the rows not yet pivoted, in
+// row order), the pivot order, and Y_int = -X (the interior rows of
+// Y = [I; -L_ii^{-1} L_ie] P).
 // T = Q Y is one batched GEMM after this kernel.
 //
 // Layout: the threads form a TR x TC grid (thread id = tc * TR + tr); thread
@@ -245,13 +247,26 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
         for (int ri = 0; ri < RI; ++ri) a[ri][s] -= s_lcol[buf][tr + TR * ri] * u;
       }
     }
-    // pivot block finished: its columns are final L / U entries
+    // pivot block finished: its columns are final L / U entries.  Column col
+    // is stored as [U entries in pivot order | L entries of the rows not yet
+    // pivoted after step col, in row order]; an L row's slot is col + 1 plus
+    // the number of L rows above it, counted by ballots over the column group
     {
       const int col = kb * TC + tc;
-      if (col < NI)
+      const unsigned lanes_below = (1u << tr) - 1u;
+      int above = 0;  // L rows in the earlier row slots of this column
 #pragma unroll
-        for (int ri = 0; ri < RI; ++ri)
-          if (tr + TR * ri < NI) LUl[tr + TR * ri + (long long)col * NI] = a[ri][0];
+      for (int ri = 0; ri < RI; ++ri) {
+        const int row = tr + TR * ri;
+        const int pk = row < NI ? s_pos[row] : 0;
+        const bool lrow = row < NI && (pk < 0 || pk > col);
+        const unsigned gm = (unsigned)(__ballot(lrow) >> gbase) & ((1u << TR) - 1u);
+        if (col < NI && row < NI) {
+          const int slot = lrow ? col + 1 + above + __popc(gm & lanes_below) : pk;
+          LUl[(long long)col * NI + min(slot, NI - 1)] = a[ri][0];
+        }
+        above += __popc(gm);
+      }
     }
     if constexpr (kb == RJP - 1) return;  // keep the last pivot block (it also holds augmented columns)
     if constexpr (C::EXTRA && kb == 0) {
@@ -308,7 +323,10 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
     for (int e = tid; e < TC * RT; e += NT) {
       const int c = e / RT, row = e % RT, k = kb * TC + c;
       double u = 0.0;
-      if (k < NI && row < NI && s_pos[row] < k) u = LUl[row + (long long)k * NI];
+      if (k < NI && row < NI) {
+        const int pk = s_pos[row];
+        if (pk < k) u = LUl[(long long)k * NI + pk];  // U part, pivot order
+      }
       s_L0[c][row] = u;
     }
     __syncthreads();

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "../../include/hps.h"
@@ -94,9 +95,13 @@ int block_copy_launch_f32(const BlockOp* dev_ops, const CopyItem* dev_items, con
 
 // ---------------------------------------------------------------------------
 // leaf_src: v_int[leaf][r][k] = (L_ii^{-1} f_int)[k] for rhs r < nrhs.
-// LU is stored with rows in original order: row perm[s] is the pivot row of
-// step s; a row r with pos[r] > s holds L(r, s) in column s, a row with
-// pos[r] <= s holds U(pos[r], s).
+// Factor layout (implicit pivoting: row perm[s] is the pivot row of step s,
+// pos = perm^{-1}): column s of LU holds, at positions 0 .. s, the U entries
+// U(j, s) in pivot order j, and at positions s+1 .. NI-1 the L entries of the
+// rows not yet pivoted after step s, in increasing row order.  Row r's L entry
+// sits at s + 1 + r - cnt_s(r), cnt_s(r) = #{j <= s : perm[j] < r}.  The
+// forward pass reads only the L part of each column and the backward pass only
+// the U part, so a solve reads the factor once.
 // ---------------------------------------------------------------------------
 constexpr int SRC_THREADS = 256;
 constexpr int SRC_MAXR = 16;
@@ -109,150 +114,214 @@ constexpr int SRC_MAXR = 16;
 // rows / diagonal entries) of the next PF steps are in flight in a register
 // ring, so the step chain does not wait on HBM.
 constexpr int SRCW_THREADS = 64;
-constexpr int SRC_PF = 4;
-template <int RPT, typename T, class Src>
+constexpr int SRC_PF = 2;
+constexpr int SRC_STAGE = 8;  // right-hand sides per pass of the pivot-order staging
+// src_key(row) gives a row's source key (loaded once per row), src(j, key)
+// the source of rhs j.
+template <int RPT, typename T, class SrcKey, class Src>
 __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const int* __restrict__ perm_g,
-                                              const int* __restrict__ pos_g, Src src, int NI, int nrhs,
-                                              T* __restrict__ v, T* s_y) {
+                                              const int* __restrict__ pos_g, SrcKey src_key, Src src, int NI,
+                                              int nrhs, T* __restrict__ v, T* s_y, T* s_stage) {
   constexpr int PF = SRC_PF;
   const int lane = threadIdx.x;
   T b[RPT][SRC_MAXR];
   int mypos[RPT];
+  int permv[RPT];  // perm[lane + 64 i]: any perm entry by readlane, without memory
+  int key[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = lane + SRCW_THREADS * i;
     mypos[i] = row < NI ? pos_g[row] : -1;
-#pragma unroll
-    for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? (T)src(j, row) : T(0);
+    permv[i] = row < NI ? perm_g[row] : 0;
+    key[i] = row < NI ? src_key(row) : 0;
   }
+  // the value loads depend only on the keys: all of them go out together
+  if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = lane + SRCW_THREADS * i;
+#pragma unroll
+      for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? src(j, key[i]) : 0.0;
+    }
+    // every load above completes here: otherwise the compiler cannot tell,
+    // in the step loops, whether b still has loads pending and waits for all
+    // outstanding loads (the ring prefetches included) at every step
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    // fp64 values first; the narrowing conversion comes after one wait for
+    // all of them (the empty asm keeps it from moving next to each load)
+    double b0[RPT][SRC_MAXR];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = lane + SRCW_THREADS * i;
+#pragma unroll
+      for (int j = 0; j < SRC_MAXR; ++j) b0[i][j] = (row < NI && j < nrhs) ? (double)src(j, key[i]) : 0.0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+      for (int j = 0; j < SRC_MAXR; ++j) {
+        __asm__ volatile("" : "+v"(b0[i][j]));
+        b[i][j] = (T)b0[i][j];
+      }
+  }
+  auto perm_at = [&](int s) {  // s uniform: readlane of every slot, then a scalar select
+    const int l = s % SRCW_THREADS;
+    int r = __builtin_amdgcn_readlane(permv[0], l);
+#pragma unroll
+    for (int i = 1; i < RPT; ++i) {
+      const int ri = __builtin_amdgcn_readlane(permv[i], l);
+      r = s >= SRCW_THREADS * i ? ri : r;
+    }
+    return r;
+  };
+  // The step loops are straight-line code: prefetch loads are unconditional
+  // (addresses clamped into the factor) and masked where they are used, and
+  // the LDS broadcast relies on the in-order LDS queue of one wavefront, so
+  // the compiler can keep the ring's loads in flight across steps.
   T ring[PF][RPT];
   int pring[PF];
   T dring[PF];
   // ---- forward: y_s = b[perm[s]];  b[r] -= L(r, s) y_s for pos[r] > s
+  // lidx[i] = sp + 1 + row - #{j <= sp : perm[j] < row}: row i's slot in
+  // column sp of the step sp being prefetched (advances by [perm[sp] >= row])
+  int lidx[RPT];
 #pragma unroll
-  for (int u = 0; u < PF; ++u) {
+  for (int i = 0; i < RPT; ++i) lidx[i] = lane + SRCW_THREADS * i;
+  auto fetch_l = [&](int u, int sp) {
+    const int spc = sp < NI ? sp : NI - 1;
+    const int p = perm_at(spc);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int row = lane + SRCW_THREADS * i;
-      ring[u][i] = (row < NI && u < NI) ? LU[row + (long long)u * NI] : T(0);
+      lidx[i] += (sp < NI && p >= row) ? 1 : 0;
+      ring[u][i] = LU[(long long)spc * NI + min(max(lidx[i], 0), NI - 1)];
     }
-    pring[u] = u < NI ? perm_g[u] : 0;
-  }
+    pring[u] = p;
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) fetch_l(u, u);
   for (int s0 = 0; s0 < NI; s0 += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int s = s0 + u;
-      if (s < NI) {
-        const int pr = pring[u];
-        if (lane == pr % SRCW_THREADS) {
-          const int ip = pr / SRCW_THREADS;
-#pragma unroll
-          for (int i = 0; i < RPT; ++i)
-            if (i == ip)
-#pragma unroll
-              for (int j = 0; j < SRC_MAXR; ++j) s_y[j] = b[i][j];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        T y[SRC_MAXR];
-#pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) y[j] = s_y[j];
+      const int pr = pring[u];
+      if (lane == pr % SRCW_THREADS) {
+        const int ip = pr / SRCW_THREADS;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
-          if (mypos[i] > s) {
+          if (i == ip)
 #pragma unroll
-            for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= ring[u][i] * y[j];
-          }
-        __builtin_amdgcn_wave_barrier();  // s_y is rewritten next step
+            for (int j = 0; j < SRC_MAXR; ++j) s_y[j] = b[i][j];
       }
-      const int sn = s + PF;  // refill this slot
+      __builtin_amdgcn_wave_barrier();
+      const bool live = s < NI;  // uniform: the tail of the last group does nothing
+      T y[SRC_MAXR];
+#pragma unroll
+      for (int j = 0; j < SRC_MAXR; ++j) y[j] = live ? s_y[j] : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int row = lane + SRCW_THREADS * i;
-        ring[u][i] = (row < NI && sn < NI) ? LU[row + (long long)sn * NI] : T(0);
+        const T l = mypos[i] > s ? ring[u][i] : T(0);
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= l * y[j];
       }
-      pring[u] = sn < NI ? perm_g[sn] : 0;
+      __builtin_amdgcn_wave_barrier();  // s_y is rewritten next step
+      fetch_l(u, s + PF);  // refill this slot
     }
   }
-  // ---- backward: x_s = b[perm[s]] / U(s, s);  b[r] -= U(pos[r], s) x_s for pos[r] < s
+  // ---- to pivot order: lane l takes unknowns k = l + 64 i (value of row
+  // perm[k]), staged through LDS SRC_STAGE right-hand sides at a time
 #pragma unroll
-  for (int u = 0; u < PF; ++u) {
-    const int s = NI - 1 - u;
+  for (int h = 0; h < SRC_MAXR; h += SRC_STAGE) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (mypos[i] >= 0)
+#pragma unroll
+        for (int jj = 0; jj < SRC_STAGE; ++jj) s_stage[mypos[i] * SRC_STAGE + jj] = b[i][h + jj];
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int row = lane + SRCW_THREADS * i;
-      ring[u][i] = (row < NI && s >= 0) ? LU[row + (long long)s * NI] : T(0);
+      const int k = lane + SRCW_THREADS * i;
+#pragma unroll
+      for (int jj = 0; jj < SRC_STAGE; ++jj) b[i][h + jj] = k < NI ? s_stage[k * SRC_STAGE + jj] : T(0);
     }
-    pring[u] = s >= 0 ? perm_g[s] : 0;
-    dring[u] = s >= 0 ? LU[pring[u] + (long long)s * NI] : T(1);
+    __builtin_amdgcn_wave_barrier();  // s_stage is rewritten by the next pass
   }
+  // ---- backward in pivot order: x_s = b_s / U(s, s);  b_k -= U(k, s) x_s for k < s
+  auto fetch_u = [&](int u, int s) {
+    const int sc = s >= 0 ? s : 0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int k = lane + SRCW_THREADS * i;
+      ring[u][i] = LU[(long long)sc * NI + min(k, NI - 1)];
+    }
+    dring[u] = LU[(long long)sc * NI + sc];
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) fetch_u(u, NI - 1 - u);
   for (int s0 = 0; s0 < NI; s0 += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int s = NI - 1 - (s0 + u);
-      if (s >= 0) {
-        const int pr = pring[u];
-        const T dinv = T(1) / dring[u];
-        if (lane == pr % SRCW_THREADS) {
-          const int ip = pr / SRCW_THREADS;
-#pragma unroll
-          for (int i = 0; i < RPT; ++i)
-            if (i == ip)
-#pragma unroll
-              for (int j = 0; j < SRC_MAXR; ++j) {
-                b[i][j] *= dinv;
-                s_y[j] = b[i][j];
-              }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        T y[SRC_MAXR];
-#pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) y[j] = s_y[j];
+      const bool live = s >= 0;  // uniform
+      const int sc = live ? s : 0;
+      const T dinv = T(1) / dring[u];
+      if (live && lane == sc % SRCW_THREADS) {
+        const int ip = sc / SRCW_THREADS;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
-          if (mypos[i] >= 0 && mypos[i] < s) {
+          if (i == ip)
 #pragma unroll
-            for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= ring[u][i] * y[j];
-          }
-        __builtin_amdgcn_wave_barrier();
+            for (int j = 0; j < SRC_MAXR; ++j) {
+              b[i][j] *= dinv;
+              s_y[j] = b[i][j];
+            }
       }
-      const int sn = s - PF;
+      __builtin_amdgcn_wave_barrier();
+      T y[SRC_MAXR];
+#pragma unroll
+      for (int j = 0; j < SRC_MAXR; ++j) y[j] = live ? s_y[j] : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int row = lane + SRCW_THREADS * i;
-        ring[u][i] = (row < NI && sn >= 0) ? LU[row + (long long)sn * NI] : T(0);
+        const int k = lane + SRCW_THREADS * i;
+        const T uu = k < s ? ring[u][i] : T(0);
+#pragma unroll
+        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= uu * y[j];
       }
-      pring[u] = sn >= 0 ? perm_g[sn] : 0;
-      dring[u] = sn >= 0 ? LU[pring[u] + (long long)sn * NI] : T(1);
+      __builtin_amdgcn_wave_barrier();
+      fetch_u(u, s - PF);
     }
   }
-  // unknown pos[r] sits in row r
+  // unknown k = lane + 64 i
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    if (mypos[i] < 0) continue;
+    const int k = lane + SRCW_THREADS * i;
+    if (k >= NI) continue;
 #pragma unroll
     for (int j = 0; j < SRC_MAXR; ++j)
-      if (j < nrhs) v[(long long)j * NI + mypos[i]] = b[i][j];
+      if (j < nrhs) v[(long long)j * NI + k] = b[i][j];
   }
 }
 
 template <int RPT>
-__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_kernel(const double* __restrict__ LUall,
+// at least two wavefronts per SIMD: the step loop's latency is hidden by
+// occupancy as much as by the prefetch ring
+__global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void leaf_src_kernel(const double* __restrict__ LUall,
                                                                 const int* __restrict__ permall,
                                                                 const int* __restrict__ posall,
                                                                 const double* __restrict__ src, const int* __restrict__ Ii,
                                                                 int NI, int npts, long long nl, int nrhs,
                                                                 double* __restrict__ vout, int NRcap) {
   __shared__ double s_y[SRC_MAXR];
+  __shared__ double s_stage[RPT * SRCW_THREADS * SRC_STAGE];
   const long long leaf = blockIdx.x;
   const double* f = src + leaf * npts;
   const long long rstride = nl * npts;
-  auto at = [=](int j, int k) { return f[(long long)j * rstride + Ii[k]]; };
-  leaf_src_wave<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
-                             vout + leaf * (long long)NRcap * NI, s_y);
+  auto key = [=](int k) { return Ii[k]; };
+  auto at = [=](int j, int ik) { return f[(long long)j * rstride + ik]; };
+  leaf_src_wave<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, key, at, NI, nrhs,
+                             vout + leaf * (long long)NRcap * NI, s_y, s_stage);
 }
 
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
@@ -424,13 +493,29 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_t_kernel(const double* _
 #pragma unroll
     for (int j = 0; j < SRC_MAXR; ++j) y[i][j] = (mm < NI && j < nrhs) ? b[(long long)j * NI + mm] : 0.0;
   }
+  // rows pivoted at steps <= m, as a bit mask over rows, for the thread's
+  // natural indices m: L(k, m) sits at m + 1 + rank_m(perm[k]) in column m,
+  // rank_m(r) = r - #{pivoted rows below r}
+  constexpr int MW = 8;  // NI <= 256
+  unsigned pmask[RPT][MW];
   __syncthreads();
-  // U^T y = b:  y_k = b_k / U(k,k);  b_m -= U(k, m) y_k  for m > k,  U(k, m) = LU[perm[k], m]
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int mm = tid + SRC_THREADS * i;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) pmask[i][w] = 0u;
+    for (int j = 0; j <= mm && j < NI; ++j) {
+      const int r = s_perm[j];
+#pragma unroll
+      for (int w = 0; w < MW; ++w)
+        if (w == (r >> 5)) pmask[i][w] |= 1u << (r & 31);
+    }
+  }
+  // U^T y = b:  y_k = b_k / U(k,k);  b_m -= U(k, m) y_k  for m > k,  U(k, m) = LU[m * NI + k]
   for (int k = 0; k < NI; ++k) {
     const int buf = k & 1;
-    const int pk = __builtin_amdgcn_readfirstlane(s_perm[k]);
     if (tid == k % SRC_THREADS) {
-      const double dinv = 1.0 / LU[pk + (long long)k * NI];
+      const double dinv = 1.0 / LU[(long long)k * NI + k];
       const int ik = k / SRC_THREADS;
 #pragma unroll
       for (int i = 0; i < RPT; ++i)
@@ -446,13 +531,13 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_t_kernel(const double* _
     for (int i = 0; i < RPT; ++i) {
       const int mm = tid + SRC_THREADS * i;
       if (mm > k && mm < NI) {
-        const double u = LU[pk + (long long)mm * NI];
+        const double u = LU[(long long)mm * NI + k];
 #pragma unroll
         for (int j = 0; j < SRC_MAXR; ++j) y[i][j] -= u * s_y[buf][j];
       }
     }
   }
-  // L^T z = y:  z_k = y_k;  y_m -= L(k, m) z_k  for m < k,  L(k, m) = LU[perm[k], m]
+  // L^T z = y:  z_k = y_k;  y_m -= L(k, m) z_k  for m < k (L(k, m): row perm[k] in column m)
   for (int k = NI - 1; k >= 0; --k) {
     const int buf = k & 1;
     const int pk = __builtin_amdgcn_readfirstlane(s_perm[k]);
@@ -469,7 +554,15 @@ __global__ __launch_bounds__(SRC_THREADS) void leaf_src_t_kernel(const double* _
     for (int i = 0; i < RPT; ++i) {
       const int mm = tid + SRC_THREADS * i;
       if (mm < k) {
-        const double l = LU[pk + (long long)mm * NI];
+        int below = 0;
+#pragma unroll
+        for (int w = 0; w < MW; ++w) {
+          const unsigned bits = w < (pk >> 5) ? pmask[i][w]
+                                : (w == (pk >> 5) ? (pmask[i][w] & ((1u << (pk & 31)) - 1u)) : 0u);
+          below += __popc(bits);
+        }
+        const int idx = min(mm + 1 + pk - below, NI - 1);
+        const double l = LU[(long long)mm * NI + idx];
 #pragma unroll
         for (int j = 0; j < SRC_MAXR; ++j) y[i][j] -= l * s_y[buf][j];
       }
@@ -493,6 +586,10 @@ int leaf_src_t_launch(const double* LU, const int* perm, const double* b, int NI
   if (nrhs > SRC_MAXR) {
     set_error("leaf_src_t: at most 16 right-hand sides per pass");
     return HPS_EINVAL;
+  }
+  if (NI > 256) {
+    set_error("leaf_src_t: at most 256 interior points per leaf");
+    return HPS_EUNSUPPORTED;
   }
   const size_t shm = NI * sizeof(int);
   const int rpt = (NI + SRC_THREADS - 1) / SRC_THREADS;
@@ -544,18 +641,20 @@ __global__ __launch_bounds__(BC_THREADS) void root_gather_multi_kernel(const Lea
     J.g0[(long long)j * J.nb0 + i] = src[i];
 }
 
-__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void leaf_src_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
   __shared__ double s_y[SRC_MAXR];
+  __shared__ double s_stage[4 * SRCW_THREADS * SRC_STAGE];
   const LeafJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
   const long long leaf = blockIdx.x - J.first_block;
   const int NI = J.NI, npts = J.npts;
   const int* Ii = J.Ii;
-  auto at = [&](int j, int k) {
+  auto key = [&](int k) { return Ii[k]; };
+  auto at = [&](int j, int ik) {
     const double* f = J.src[j];
-    return f ? f[leaf * npts + Ii[k]] : 0.0;
+    return f ? f[leaf * npts + ik] : 0.0;
   };
-  leaf_src_wave<4, double>(J.LU + leaf * (long long)NI * NI, J.perm + leaf * NI, J.pos + leaf * NI, at, NI, J.nrhs,
-                           J.v + leaf * (long long)J.NRcap * NI, s_y);
+  leaf_src_wave<4, double>(J.LU + leaf * (long long)NI * NI, J.perm + leaf * NI, J.pos + leaf * NI, key, at, NI, J.nrhs,
+                           J.v + leaf * (long long)J.NRcap * NI, s_y, s_stage);
 }
 
 __global__ __launch_bounds__(OUT_THREADS) void leaf_out_multi_kernel(const LeafJob* __restrict__ jobs, int njobs) {
@@ -612,17 +711,19 @@ int leaf_out_multi_launch(const LeafJob* dev_jobs, int njobs, long long nblocks,
 // fp32 copies of the LU factors; r is an fp64 interior-point residual
 // [leaf][NRcap][NI].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SRCW_THREADS) void leaf_src_f32_kernel(const float* __restrict__ LUall,
+__global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void leaf_src_f32_kernel(const float* __restrict__ LUall,
                                                                     const int* __restrict__ permall,
                                                                     const int* __restrict__ posall,
                                                                     const double* __restrict__ r, int NI, int nrhs,
                                                                     int NRcap, float* __restrict__ vout) {
   __shared__ float s_y[SRC_MAXR];
+  __shared__ float s_stage[4 * SRCW_THREADS * SRC_STAGE];
   const long long leaf = blockIdx.x;
   const double* rl = r + leaf * (long long)NRcap * NI;
+  auto key = [](int k) { return k; };
   auto at = [=](int j, int k) { return rl[(long long)j * NI + k]; };
-  leaf_src_wave<4, float>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, at, NI, nrhs,
-                          vout + leaf * (long long)NRcap * NI, s_y);
+  leaf_src_wave<4, float>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, key, at, NI, nrhs,
+                          vout + leaf * (long long)NRcap * NI, s_y, s_stage);
 }
 
 int leaf_src_f32_launch(const float* LU, const int* perm, const int* pos, const double* r, int NI, long long nl,

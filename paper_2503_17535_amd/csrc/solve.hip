@@ -354,6 +354,7 @@ constexpr int OUT_MAXR = 16;
 // Body shared by the single-operator and the batched launches: one
 // workgroup per leaf; g holds the leaf's boundary data [rhs][NB] (NRcap
 // stride), out(j, pt, value) stores u of rhs j at leaf point pt.
+constexpr int OUT_KB = 8;  // Y columns loaded together
 template <class Out>
 __device__ __forceinline__ void leaf_out_body(const double* __restrict__ Y, const double* __restrict__ P,
                                               const double* __restrict__ g, const double* __restrict__ v,
@@ -372,22 +373,38 @@ __device__ __forceinline__ void leaf_out_body(const double* __restrict__ Y, cons
     int pt;
     if (k < NI) {
       pt = Ii[k];
-      for (int c = 0; c < NB; ++c) {
-        const double y = Y[k + (long long)c * NI];
+      // Y loads in batches of OUT_KB, all in flight before their FMAs
+      for (int c0 = 0; c0 < NB; c0 += OUT_KB) {
+        double yv[OUT_KB];
 #pragma unroll
-        for (int j = 0; j < OUT_MAXR; ++j) acc[j] += y * s_g[c * OUT_MAXR + j];
+        for (int cc = 0; cc < OUT_KB; ++cc) yv[cc] = c0 + cc < NB ? Y[k + (long long)(c0 + cc) * NI] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc < OUT_KB; ++cc) {
+          const int c = min(c0 + cc, NB - 1);
+#pragma unroll
+          for (int j = 0; j < OUT_MAXR; ++j) acc[j] += yv[cc] * s_g[c * OUT_MAXR + j];
+        }
       }
-      if (v)
+      if (v) {
+        double vv[OUT_MAXR];  // all loads first, then the adds
 #pragma unroll
-        for (int j = 0; j < OUT_MAXR; ++j)
-          if (j < nrhs) acc[j] += v[(long long)j * NI + k];
+        for (int j = 0; j < OUT_MAXR; ++j) vv[j] = j < nrhs ? v[(long long)j * NI + k] : 0.0;
+#pragma unroll
+        for (int j = 0; j < OUT_MAXR; ++j) acc[j] += vv[j];
+      }
     } else {
       const int e = k - NI;
       pt = Ie[e];
-      for (int c = 0; c < NB; ++c) {
-        const double pv = P[e + (long long)c * NE];
+      for (int c0 = 0; c0 < NB; c0 += OUT_KB) {
+        double pvv[OUT_KB];
 #pragma unroll
-        for (int j = 0; j < OUT_MAXR; ++j) acc[j] += pv * s_g[c * OUT_MAXR + j];
+        for (int cc = 0; cc < OUT_KB; ++cc) pvv[cc] = c0 + cc < NB ? P[e + (long long)(c0 + cc) * NE] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc < OUT_KB; ++cc) {
+          const int c = min(c0 + cc, NB - 1);
+#pragma unroll
+          for (int j = 0; j < OUT_MAXR; ++j) acc[j] += pvv[cc] * s_g[c * OUT_MAXR + j];
+        }
       }
     }
 #pragma unroll

@@ -23,6 +23,7 @@
 namespace hps {
 
 constexpr int BC_THREADS = 256;
+constexpr int BC_UNROLL = 8;  // elements per thread whose loads are in flight together
 
 template <typename T>
 __device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops, const CopyItem* __restrict__ items,
@@ -41,21 +42,36 @@ __device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops,
     if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
     const int rows = item.r1 - item.r0;
     if (rows <= 0 || c1 <= c0) continue;
-    // walk the (row, column) pairs of this thread with one division up front
+    // walk the (row, column) pairs of this thread with one division up front,
+    // BC_UNROLL elements at a time: all their loads go out before the stores
     const int dq = BC_THREADS / rows, dr = BC_THREADS % rows;
     int r = threadIdx.x % rows, c = c0 + threadIdx.x / rows;
     while (c < c1) {
-      const int gr = item.r0 + r;
-      T v = T(0);
-      if (S0) v = S0[gr + (long long)c * op.src_ld[0]];
-      if (S1) v += S1[gr + (long long)c * op.src_ld[1]];
-      D[gr + (long long)c * op.dst_ld] = v;
-      r += dr;
-      c += dq;
-      if (r >= rows) {
-        r -= rows;
-        ++c;
+      int er[BC_UNROLL], ec[BC_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BC_UNROLL; ++u) {
+        er[u] = item.r0 + r;
+        ec[u] = c;
+        r += dr;
+        c += dq;
+        if (r >= rows) {
+          r -= rows;
+          ++c;
+        }
       }
+      T v[BC_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BC_UNROLL; ++u) {
+        const bool ok = ec[u] < c1;
+        const int cu = ok ? ec[u] : c0;  // a valid column for the unused tail
+        T x = T(0);
+        if (S0) x = S0[er[u] + (long long)cu * op.src_ld[0]];
+        if (S1) x += S1[er[u] + (long long)cu * op.src_ld[1]];
+        v[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < BC_UNROLL; ++u)
+        if (ec[u] < c1) D[er[u] + (long long)ec[u] * op.dst_ld] = v[u];
     }
   }
 }

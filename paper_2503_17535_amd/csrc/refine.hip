@@ -72,6 +72,7 @@ struct RfShared {
   double ux[RF_MAXR][RF_MAXP * RF_MAXP];
   double uy[RF_MAXR][RF_MAXP * RF_MAXP];
   double g[RF_MAXR][4 * RF_MAXP];
+  double P[(4 * RF_MAXP - 4) * 4 * (RF_MAXP - 2)];  // Gauss -> Chebyshev boundary interpolation
 };
 
 __global__ __launch_bounds__(RF_THREADS) void refine_residual_kernel(
@@ -91,20 +92,27 @@ __global__ __launch_bounds__(RF_THREADS) void refine_residual_kernel(
     S.D2T[(i % p) * p + i / p] = D2g[i];
   }
   for (int i = tid; i < q * p; i += RF_THREADS) S.C2G[i] = C2G[i];
+  for (int i = tid; i < ne * nb; i += RF_THREADS) S.P[i] = P[i];
   for (int e = tid; e < nrhs * nb; e += RF_THREADS) {
     const int r = e / nb, k = e % nb;
     S.g[r][k] = gam[(leaf * NRcap + r) * nb + k];
   }
-  for (int e = tid; e < nrhs * ni; e += RF_THREADS) {
-    const int r = e / ni, k = e % ni;
-    S.u[r][Ii[k]] = u[((long long)r * nl + leaf) * npts + Ii[k]];
+  // point outer, rhs inner: one index load per point, then the rhs loads together
+  for (int k = tid; k < ni; k += RF_THREADS) {
+    const int pt = Ii[k];
+    double uv[RF_MAXR];
+#pragma unroll
+    for (int r = 0; r < RF_MAXR; ++r) uv[r] = u[((long long)(r < nrhs ? r : 0) * nl + leaf) * npts + pt];
+#pragma unroll
+    for (int r = 0; r < RF_MAXR; ++r)
+      if (r < nrhs) S.u[r][pt] = uv[r];
   }
   __syncthreads();
   // exterior points: u = P gamma
   for (int e = tid; e < nrhs * ne; e += RF_THREADS) {
     const int r = e / ne, k = e % ne;
     double v = 0.0;
-    for (int b = 0; b < nb; ++b) v += P[k + (long long)b * ne] * S.g[r][b];
+    for (int b = 0; b < nb; ++b) v += S.P[k + b * ne] * S.g[r][b];
     S.u[r][Ie[k]] = v;
     u[((long long)r * nl + leaf) * npts + Ie[k]] = v;
   }
@@ -121,21 +129,28 @@ __global__ __launch_bounds__(RF_THREADS) void refine_residual_kernel(
     S.uy[r][pt] = vy;
   }
   __syncthreads();
-  // collocation residual at interior points
+  // collocation residual at interior points: point outer (its coefficients
+  // loaded once), rhs inner (the sources loaded together)
   const double* c = coef + leaf * 6 * (long long)npts;
-  for (int e = tid; e < nrhs * ni; e += RF_THREADS) {
-    const int r = e / ni, k = e % ni;
+  for (int k = tid; k < ni; k += RF_THREADS) {
     const int pt = Ii[k], ix = pt % p, iy = pt / p;
-    double dxx = 0.0, dyy = 0.0, dxy = 0.0;
-    for (int a = 0; a < p; ++a) {
-      dxx += S.D2T[a * p + ix] * S.u[r][a + p * iy];
-      dyy += S.D2[iy * p + a] * S.u[r][ix + p * a];
-      dxy += S.D1[iy * p + a] * S.ux[r][ix + p * a];
+    const double cxx = c[pt], cxy = c[npts + pt], cyy = c[2 * npts + pt], cx = c[3 * npts + pt],
+                 cy = c[4 * npts + pt], c0 = c[5 * npts + pt];
+    double fv[RF_MAXR];
+#pragma unroll
+    for (int r = 0; r < RF_MAXR; ++r) fv[r] = src ? src[((long long)(r < nrhs ? r : 0) * nl + leaf) * npts + pt] : 0.0;
+#pragma unroll
+    for (int r = 0; r < RF_MAXR; ++r) {
+      if (r >= nrhs) continue;
+      double dxx = 0.0, dyy = 0.0, dxy = 0.0;
+      for (int a = 0; a < p; ++a) {
+        dxx += S.D2T[a * p + ix] * S.u[r][a + p * iy];
+        dyy += S.D2[iy * p + a] * S.u[r][ix + p * a];
+        dxy += S.D1[iy * p + a] * S.ux[r][ix + p * a];
+      }
+      const double Lu = cxx * dxx + cxy * dxy + cyy * dyy + cx * S.ux[r][pt] + cy * S.uy[r][pt] + c0 * S.u[r][pt];
+      r1[(leaf * NRcap + r) * ni + k] = fv[r] - Lu;
     }
-    const double Lu = c[pt] * dxx + c[npts + pt] * dxy + c[2 * npts + pt] * dyy + c[3 * npts + pt] * S.ux[r][pt] +
-                      c[4 * npts + pt] * S.uy[r][pt] + c[5 * npts + pt] * S.u[r][pt];
-    const double f = src ? src[((long long)r * nl + leaf) * npts + pt] : 0.0;
-    r1[(leaf * NRcap + r) * ni + k] = f - Lu;
   }
   // outgoing fluxes: normal derivative at the face's Chebyshev points (faces
   // S, E, N, W; tangential coordinate ascending), then Chebyshev -> Gauss

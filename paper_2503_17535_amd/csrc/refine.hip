@@ -236,15 +236,31 @@ __global__ __launch_bounds__(RF_THREADS) void refine_update_kernel(const float* 
     float acc[RF_MAXR];
 #pragma unroll
     for (int j = 0; j < RF_MAXR; ++j) acc[j] = 0.0f;
-    for (int c = 0; c < nb; ++c) {
-      const float y = Y[k + (long long)c * ni];
+    // Y columns in batches of 8, all loads in flight before their FMAs
+    for (int c0 = 0; c0 < nb; c0 += 8) {
+      float yv[8];
 #pragma unroll
-      for (int j = 0; j < RF_MAXR; ++j) acc[j] += y * sdg[c * RF_MAXR + j];
+      for (int cc = 0; cc < 8; ++cc) yv[cc] = c0 + cc < nb ? Y[k + (long long)(c0 + cc) * ni] : 0.0f;
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int c = min(c0 + cc, nb - 1);
+#pragma unroll
+        for (int j = 0; j < RF_MAXR; ++j) acc[j] += yv[cc] * sdg[c * RF_MAXR + j];
+      }
     }
     const int pt = Ii[k];
+    // loads of v and u (clamped to a valid rhs) together, then the updates
+    float vv[RF_MAXR];
+    double uo[RF_MAXR];
+#pragma unroll
+    for (int j = 0; j < RF_MAXR; ++j) {
+      const int jj = j < nrhs ? j : 0;
+      vv[j] = v[(long long)jj * ni + k];
+      uo[j] = u[((long long)jj * nl + leaf) * npts + pt];
+    }
 #pragma unroll
     for (int j = 0; j < RF_MAXR; ++j)
-      if (j < nrhs) u[((long long)j * nl + leaf) * npts + pt] += (double)(acc[j] + v[(long long)j * ni + k]);
+      if (j < nrhs) u[((long long)j * nl + leaf) * npts + pt] = uo[j] + (double)(acc[j] + vv[j]);
   }
 }
 

@@ -215,7 +215,10 @@ const char* hps_last_error(void);
 
 /* Operator inspection, for tests: copies an internal device buffer of a
  * built operator to host memory (synchronizes the op's stream).  which:
- *   0 leaf LU factors   [n_leaves][n_i*n_i]  (rows in original order)
+ *   0 leaf LU factors   [n_leaves][n_i*n_i]  (2D: column s = U(0..s, s) in pivot order,
+ *                                              then the L entries of the rows not yet
+ *                                              pivoted after step s, in row order;
+ *                                              3D: L_ii^{-1}, column-major)
  *   1 leaf pivot order  [n_leaves][n_i]      (as doubles)
  *   2 leaf Y_int        [n_leaves][n_i*n_b]  (column-major)
  *   3 leaf T            [n_leaves][n_b*n_b]

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
     const double* __restrict__ D1g,     // [P*P] row-major, d/dx on the leaf
     const double* __restrict__ D2g,     // [P*P] row-major, d2/dx2 on the leaf
     const double* __restrict__ Mt,      // [6][NI x NB] column-major (ld NI)
-    double* __restrict__ LU,            // [nl][NI x NI] column-major, original row order
+    double* __restrict__ LU,            // [nl][NI x NI] per column: U part (pivot order), L part (row order)
     int* __restrict__ perm,             // [nl][NI]  row chosen at step k
     int* __restrict__ pos,              // [nl][NI]  step at which row was chosen
     double* __restrict__ Y,             // [nl][NI x NB] column-major

@@ -1356,7 +1356,7 @@ int hps_debug_gemm_f32(int m, int n, int k, float alpha, const float* a, int lda
   hipStream_t st = (hipStream_t)stream;
   int rc = HPS_OK;
   if (hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroupF32), hipMemcpyHostToDevice, st) != hipSuccess) rc = HPS_EDEVICE;
-  if (rc == HPS_OK) rc = gemm_launch_f32(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, 0);
+  if (rc == HPS_OK) rc = gemm_launch_f32(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, n);
   (void)hipStreamSynchronize(st);
   (void)hipFree(dg);
   if (part) (void)hipFree(part);
@@ -1382,7 +1382,7 @@ int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, 
   hipStream_t st = (hipStream_t)stream;
   int rc = HPS_OK;
   if (hipMemcpyAsync(dg, gs.data(), sizeof(GemmGroup), hipMemcpyHostToDevice, st) != hipSuccess) rc = HPS_EDEVICE;
-  if (rc == HPS_OK) rc = gemm_launch(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, 0);
+  if (rc == HPS_OK) rc = gemm_launch(dg, 1, nblocks, nrblocks, trans_a != 0, trans_b != 0, st, n);
   (void)hipStreamSynchronize(st);
   (void)hipFree(dg);
   if (part) (void)hipFree(part);

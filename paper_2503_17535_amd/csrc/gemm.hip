@@ -47,6 +47,16 @@ __device__ __forceinline__ long long xcd_remap(long long b, long long nblocks) {
   return start + local;
 }
 
+// Pointers read from the group table in memory are generic (flat) to the
+// compiler.  A flat load counts against both the vector-memory and the
+// LDS/scalar wait counters, and the compiler then tends to wait for all
+// outstanding loads at once; a cast to the global address space gives global
+// loads, whose waits count vector-memory operations only, so that loads
+// issued ahead stay in flight.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ const gmem<T>* gptr(const T* p) { return (const gmem<T>*)p; }
+template <typename T> __device__ __forceinline__ gmem<T>* gptr(T* p) { return (gmem<T>*)p; }
+
 template <typename T> struct MfmaOp;
 // col(lane, v): column of C (within the 16 x 16 block) that accumulator
 // element v of `lane` holds; its row is lane % 16 (see the feeding order).
@@ -236,6 +246,102 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
   }
 }
 
+// Skinny products (N <= 16, as in the solve: one column per right-hand side),
+// A and B not transposed.  The same block / tile / split-K decomposition as
+// gemm_grouped_kernel, but each wavefront owns 16 rows of the 64-row tile and
+// reads its MFMA fragments straight from memory: no LDS staging, no barriers.
+// Loads go out at clamped, valid addresses; out-of-range rows, columns and k
+// are masked where used.
+constexpr int SKK = 4;
+template <typename T, typename G>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(const G* __restrict__ groups, int ngroups,
+                                                                   long long nblocks, int n_override) {
+  typedef typename MfmaOp<T>::acc_t acc_t;
+  const long long lb = xcd_remap(blockIdx.x, nblocks);
+  const G* g = find_group(groups, ngroups, lb);
+  const int ks_n = g->ksplit > 1 ? g->ksplit : 1;
+  const long long rel0 = lb - g->first_block;
+  const int ks = (int)(rel0 % ks_n);
+  const long long rel = rel0 / ks_n;
+  const int tiles = g->tiles_m * g->tiles_n;
+  const long long bat = rel / tiles;
+  const int tile = (int)(rel - bat * tiles);
+  const int tm = tile % g->tiles_m, tn = tile / g->tiles_m;
+  if (tn > 0) return;  // columns past 64: none when N <= 16
+  const int M = g->M, K = g->K;
+  const int N = (n_override > 0 && n_override < g->N) ? n_override : g->N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = tm * BM + 16 * wave;  // this wavefront's rows r0 .. r0 + 15
+  if (r0 >= M) return;                 // wave-uniform
+  const int lda = g->lda, ldb = g->ldb;
+  const int arow = r0 + (lane & 15), bcol = lane & 15, kl = lane >> 4;
+  const bool arow_ok = arow < M, bcol_ok = bcol < N;
+  const int arow_c = arow_ok ? arow : M - 1, bcol_c = bcol_ok ? bcol : N - 1;
+  const int kbeg = ks_n > 1 ? ks * g->kchunk : 0;
+  const int kend = ks_n > 1 ? min(K, kbeg + g->kchunk) : K;
+  acc_t acc = acc_t{0, 0, 0, 0};
+  const int nseg = kbeg < kend ? g->nseg : 0;  // an empty K range reads nothing
+  for (int s = 0; s < nseg; ++s) {
+    const gmem<T>* A = gptr(g->A) + bat * g->sA + g->aseg[s];
+    const gmem<T>* B = gptr(g->B) + bat * g->sB + g->bseg[s];
+    // two register buffers of SKK k-steps each: the loads of one are in
+    // flight while the MFMAs of the other run.  Loads past the end of the K
+    // range re-read (clamped) the last k; their MFMAs add zeros.
+    T af[SKK], bf[SKK], an[SKK], bn[SKK];
+    auto load = [&](T* a_, T* b_, int k0) {
+#pragma unroll
+      for (int u = 0; u < SKK; ++u) {
+        const int k = min(k0 + 4 * u + kl, kend - 1);
+        a_[u] = A[arow_c + (long long)k * lda];
+        b_[u] = B[k + (long long)bcol_c * ldb];
+      }
+    };
+    auto mma = [&](const T* a_, const T* b_, int k0) {
+#pragma unroll
+      for (int u = 0; u < SKK; ++u) {
+        const bool kok = k0 + 4 * u + kl < kend;
+        acc = MfmaOp<T>::run((kok && bcol_ok) ? b_[u] : T(0), (kok && arow_ok) ? a_[u] : T(0), acc);
+      }
+    };
+    load(af, bf, kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += 8 * SKK) {
+      load(an, bn, k0 + 4 * SKK);
+      mma(af, bf, k0);
+      load(af, bf, k0 + 8 * SKK);
+      mma(an, bn, k0 + 4 * SKK);
+    }
+  }
+  // epilogue: acc[v] = C(row = arow, col = MfmaOp<T>::col(lane, v))
+  if (ks_n > 1) {
+    gmem<T>* W = gptr(g->part) + (bat * ks_n + ks) * (long long)M * g->N;
+    if (arow_ok)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = MfmaOp<T>::col(lane, v);
+        if (col < N) W[arow + (long long)col * M] = acc[v];
+      }
+    return;
+  }
+  gmem<T>* C = gptr(g->C) + bat * g->sC;
+  const gmem<T>* C0 = g->C0 ? gptr(g->C0) + bat * g->sC0 : nullptr;
+  const T alpha = g->alpha, beta = g->beta;
+  T c0v[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int col = MfmaOp<T>::col(lane, v);
+    c0v[v] = (beta != T(0) && arow_ok && col < N) ? C0[arow + (long long)col * g->ldc0] : T(0);
+  }
+  if (!arow_ok) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int col = MfmaOp<T>::col(lane, v);
+    if (col >= N) continue;
+    T val = alpha * acc[v];
+    if (beta != T(0)) val += beta * c0v[v];
+    C[arow + (long long)col * g->ldc] = val;
+  }
+}
+
 // Second pass of a split-K product: C = alpha * sum_ks part_ks + beta * C0,
 // the partials added in ks order (deterministic).  One thread per element.
 constexpr int RED_THREADS = 256;
@@ -259,12 +365,12 @@ __global__ __launch_bounds__(RED_THREADS) void gemm_splitk_reduce_kernel(const G
   const int rem = (int)(e - bat * mn);
   const int col = rem / M, row = rem - col * M;
   if (col >= N) return;
-  const T* W = g->part + bat * ks_n * mn + row + (long long)col * M;
+  const gmem<T>* W = gptr(g->part) + bat * ks_n * mn + row + (long long)col * M;
   T sum = T(0);
   for (int k = 0; k < ks_n; ++k) sum += W[k * mn];
   T val = g->alpha * sum;
-  if (g->beta != T(0)) val += g->beta * g->C0[bat * g->sC0 + row + (long long)col * g->ldc0];
-  g->C[bat * g->sC + row + (long long)col * g->ldc] = val;
+  if (g->beta != T(0)) val += g->beta * gptr(g->C0)[bat * g->sC0 + row + (long long)col * g->ldc0];
+  gptr(g->C)[bat * g->sC + row + (long long)col * g->ldc] = val;
 }
 
 template <typename G>
@@ -338,7 +444,9 @@ int gemm_launch(const GemmGroup* dev_groups, int ngroups, long long nblocks, lon
                 hipStream_t st, int n_override) {
   if (nblocks <= 0) return HPS_OK;
   dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
-  if (!ta && !tb)
+  if (!ta && !tb && n_override > 0 && n_override <= 16)
+    hipLaunchKernelGGL((gemm_skinny_kernel<double, GemmGroup>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (!ta && !tb)
     hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, false, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
   else if (ta && !tb)
     hipLaunchKernelGGL((gemm_grouped_kernel<double, GemmGroup, true, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
@@ -359,7 +467,9 @@ int gemm_launch_f32(const GemmGroupF32* dev_groups, int ngroups, long long nbloc
                     bool tb, hipStream_t st, int n_override) {
   if (nblocks <= 0) return HPS_OK;
   dim3 grid((unsigned)nblocks), block(GEMM_THREADS);
-  if (!ta && !tb)
+  if (!ta && !tb && n_override > 0 && n_override <= 16)
+    hipLaunchKernelGGL((gemm_skinny_kernel<float, GemmGroupF32>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
+  else if (!ta && !tb)
     hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, false, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);
   else if (ta && !tb)
     hipLaunchKernelGGL((gemm_grouped_kernel<float, GemmGroupF32, true, false>), grid, block, 0, st, dev_groups, ngroups, nblocks, n_override);

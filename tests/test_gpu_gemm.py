@@ -16,7 +16,9 @@ def _colmajor(x):
                                          (130, 7, 200, 0, 0), (50, 60, 70, 1, 0), (50, 60, 70, 0, 1),
                                          (50, 60, 70, 1, 1), (1, 1, 1, 0, 0),
                                          # few tiles, long K: split-K with a second reduction pass
-                                         (130, 7, 2000, 0, 0), (200, 16, 3584, 1, 0), (64, 16, 1000, 0, 1)])
+                                         (130, 7, 2000, 0, 0), (200, 16, 3584, 1, 0), (64, 16, 1000, 0, 1),
+                                         # N <= 16, neither operand transposed: the skinny path
+                                         (56, 16, 196, 0, 0), (200, 16, 3584, 0, 0), (33, 3, 9, 0, 0)])
 def test_gemm_matches_numpy(m, n, k, ta, tb):
     import paper_2503_17535_amd as hp
     say(f"[case] gemm {m}x{n}x{k} ta={ta} tb={tb}")
@@ -32,7 +34,8 @@ def test_gemm_matches_numpy(m, n, k, ta, tb):
 
 
 @pytest.mark.parametrize("m,n,k,ta,tb", [(16, 16, 4, 0, 0), (70, 33, 45, 0, 0), (130, 7, 200, 0, 0),
-                                         (50, 60, 70, 1, 0), (50, 60, 70, 1, 1), (130, 7, 2000, 0, 0)])
+                                         (50, 60, 70, 1, 0), (50, 60, 70, 1, 1), (130, 7, 2000, 0, 0),
+                                         (56, 16, 196, 0, 0)])
 def test_gemm_f32_matches_numpy(m, n, k, ta, tb):
     # fp32 products with fp32 accumulation: error bound ~ k * 2^-24 * |A||B|
     import paper_2503_17535_amd as hp

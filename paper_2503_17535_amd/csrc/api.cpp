@@ -42,6 +42,8 @@ int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, 
                      hipStream_t st);
 int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, int* flag,
                     long long batch, hipStream_t st);
+int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, const double* Wp, int wp,
+                   int* flag, long long batch, hipStream_t st);
 int gj_init_launch(int* pos, long long n, hipStream_t st);
 int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
                          hipStream_t st);
@@ -357,7 +359,7 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
   const int mnb = gj_panel_max_nb();
   g->pos = (int*)op_alloc(op, sizeof(int) * batch * m, false);
   g->piv = (int*)op_alloc(op, sizeof(int) * batch * m, false);
-  g->W = (double*)op_alloc(op, sizeof(double) * batch * m * mnb, false);
+  g->W = (double*)op_alloc(op, sizeof(double) * 2 * batch * m * mnb, false);  // two buffers, by panel parity
   if (!g->pos || !g->piv || !g->W) {
     set_error("device allocation failed (Gauss-Jordan workspace)");
     return HPS_ENOMEM;
@@ -368,11 +370,18 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
 int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
   if (g.small) return gj_small_launch(g.A, g.Z, g.m, op->flag, g.batch, st);
   HPS_TRY(gj_init_launch(g.pos, g.batch * g.m, st));
-  for (int j0 = 0; j0 < g.m; j0 += g.nb) {
-    const int w = std::min(g.nb, g.m - j0);
-    HPS_TRY(gj_panel_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W, op->flag, g.batch, st));
-    HPS_TRY(gj_update_launch(g.A, g.W, g.piv, g.m, j0, w, g.batch, st));
+  // panel k writes W buffer k % 2; launch k (k >= 1) factors panel k beside
+  // the update by panel k - 1 of the columns outside both panels
+  const long long wbuf = g.batch * g.m * gj_panel_max_nb();
+  const int np = (g.m + g.nb - 1) / g.nb;
+  HPS_TRY(gj_panel_launch(g.A, g.m, 0, std::min(g.nb, g.m), g.pos, g.piv, g.W, op->flag, g.batch, st));
+  for (int k = 1; k < np; ++k) {
+    const int j0 = k * g.nb, w = std::min(g.nb, g.m - j0);
+    HPS_TRY(gj_step_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W + (k % 2) * wbuf, g.W + ((k - 1) % 2) * wbuf, g.nb,
+                           op->flag, g.batch, st));
   }
+  const int jl = (np - 1) * g.nb;
+  HPS_TRY(gj_update_launch(g.A, g.W + ((np - 1) % 2) * wbuf, g.piv, g.m, jl, g.m - jl, g.batch, st));
   return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
 }
 

@@ -11,10 +11,10 @@
 //    (cyclic TR x TC thread grid, the pivot column rotated into slot 0), for
 //    m <= 224 (the many small merges near the leaves);
 //  * blocked: per panel of NB columns one workgroup per matrix factors the
-//    panel with the panel's rows in registers (gj_panel), then a grouped
-//    MFMA GEMM applies the panel's rank-NB update to all other columns; a
-//    final gather unscrambles rows and columns.  Used for the few large
-//    merges near the root.
+//    panel with the panel's rows in registers, while the other workgroups of
+//    the same launch apply the previous panel's rank-NB update to every other
+//    column (each workgroup owns whole columns); a final gather unscrambles
+//    rows and columns.  Used for the few large merges near the root.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -230,9 +230,8 @@ constexpr int rank_code_bits(int n) { return n < 256 ? 8 : 1 + rank_code_bits(n 
 // scaled by its own reciprocal pivot; one barrier; every thread takes the
 // best of the NW candidates and applies the rank-1 Gauss-Jordan update.
 template <int RPT, int NB>
-__global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
-                                                                  int* __restrict__ posall, int* __restrict__ pivall,
-                                                                  double* __restrict__ Wall, int* __restrict__ flag) {
+__device__ __forceinline__ void gj_panel_body(double* __restrict__ A, int m, int j0, int nbw, int* __restrict__ pos,
+                                              int* __restrict__ piv, double* __restrict__ W, int* __restrict__ flag) {
   constexpr int NW = PANEL_THREADS / 64;
   constexpr int CB = rank_code_bits(RPT * PANEL_THREADS);
   constexpr int CMAX = (1 << CB) - 1;
@@ -242,11 +241,6 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
   __shared__ double s_cand[2][NW][NB];  // each wavefront's candidate pivot row, scaled
   __shared__ int s_piv[NB];
 
-  const long long b = blockIdx.x;
-  double* A = Aall + b * (long long)m * m;
-  int* pos = posall + b * (long long)m;
-  int* piv = pivall + b * (long long)m;
-  double* W = Wall + b * (long long)m * PANEL_MAX_NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   double a[RPT][NB];
@@ -345,69 +339,113 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
   }
 }
 
-// Gauss-Jordan update of the columns outside the panel [j0, j0 + w):
-//   A(:, j) += W A(piv[j0 .. j0+w), j)   (W = panel - E_P, written by the panel kernel)
-// A workgroup owns GU_COLS whole columns: it first stages the (old) pivot-row
-// entries of its columns in LDS, then rewrites its columns, so no other
-// workgroup can overwrite a pivot row before it is read.
-constexpr int GU_THREADS = 256;
+template <int RPT, int NB>
+__global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
+                                                                  int* __restrict__ posall, int* __restrict__ pivall,
+                                                                  double* __restrict__ Wall, int* __restrict__ flag) {
+  const long long b = blockIdx.x;
+  gj_panel_body<RPT, NB>(Aall + b * (long long)m * m, m, j0, nbw, posall + b * (long long)m,
+                         pivall + b * (long long)m, Wall + b * (long long)m * PANEL_MAX_NB, flag);
+}
+
+// Gauss-Jordan update by the panel at jp of width w:
+//   A(:, j) += W A(piv[jp .. jp+w), j)   (W = panel - E_P, written by the panel kernel)
+// for the nout columns j = q (q < jx) and j = q + wx (q >= jx), q < nout: all
+// columns outside [jx, jx + wx) = [jp, jp + w) or a wider range, or (jx = 0)
+// the nout columns from wx on.  A workgroup owns COLS whole columns (the
+// qblk-th group): it first stages the (old) pivot-row entries of its columns
+// in LDS, then rewrites its columns, so no other workgroup can overwrite a
+// pivot row before it is read.
 constexpr int GU_COLS = 8;
-constexpr int GU_ROWS = 4;  // rows per thread and pass
-constexpr int GU_KC = 8;    // panel columns per chunk of W loads
-__global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restrict__ Aall, const double* __restrict__ Wall,
-                                                               const int* __restrict__ pivall, int m, int j0, int w) {
-  __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
-  const long long b = blockIdx.y;
-  double* A = Aall + b * (long long)m * m;
-  const double* W = Wall + b * (long long)m * PANEL_MAX_NB;
-  const int* piv = pivall + b * (long long)m;
+constexpr int GU_KC = 8;  // panel columns per chunk of W loads
+template <int THREADS, int ROWS, int COLS = GU_COLS>
+__device__ __forceinline__ void gj_update_body(double* __restrict__ A, const double* __restrict__ W,
+                                               const int* __restrict__ piv, int m, int jp, int w, int jx, int wx,
+                                               int nout, int qblk) {
+  __shared__ double s_p[PANEL_MAX_NB][COLS];
   const int tid = threadIdx.x;
-  const int nout = m - w;                  // columns outside the panel
-  const int q0 = blockIdx.x * GU_COLS;     // first outside column of this workgroup
-  auto colof = [&](int q) { return q < j0 ? q : q + w; };
-  for (int e = tid; e < PANEL_MAX_NB * GU_COLS; e += GU_THREADS) {
-    const int c = e / GU_COLS, jj = e % GU_COLS, q = q0 + jj;
-    s_p[c][jj] = (c < w && q < nout) ? A[piv[j0 + c] + (long long)colof(q) * m] : 0.0;
+  const int q0 = qblk * COLS;         // first column index q of this workgroup
+  auto colof = [&](int q) { return q < jx ? q : q + wx; };
+  for (int e = tid; e < PANEL_MAX_NB * COLS; e += THREADS) {
+    const int c = e / COLS, jj = e % COLS, q = q0 + jj;
+    s_p[c][jj] = (c < w && q < nout) ? A[piv[jp + c] + (long long)colof(q) * m] : 0.0;
   }
   __syncthreads();
-  double* colp[GU_COLS];
+  double* colp[COLS];
 #pragma unroll
-  for (int jj = 0; jj < GU_COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
-  for (int r0 = 0; r0 < m; r0 += GU_THREADS * GU_ROWS) {
-    double acc[GU_ROWS][GU_COLS];
+  for (int jj = 0; jj < COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
+  for (int r0 = 0; r0 < m; r0 += THREADS * ROWS) {
+    double acc[ROWS][COLS];
 #pragma unroll
-    for (int i = 0; i < GU_ROWS; ++i) {
-      const int r = r0 + tid + GU_THREADS * i;
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = r0 + tid + THREADS * i;
 #pragma unroll
-      for (int jj = 0; jj < GU_COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
+      for (int jj = 0; jj < COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
     }
     // K loop in chunks of GU_KC with every W load of a chunk issued first
     for (int c0 = 0; c0 < w; c0 += GU_KC) {
-      double wr[GU_KC][GU_ROWS];
+      double wr[GU_KC][ROWS];
 #pragma unroll
       for (int cc = 0; cc < GU_KC; ++cc)
 #pragma unroll
-        for (int i = 0; i < GU_ROWS; ++i) {
-          const int r = r0 + tid + GU_THREADS * i;
+        for (int i = 0; i < ROWS; ++i) {
+          const int r = r0 + tid + THREADS * i;
           wr[cc][i] = (r < m && c0 + cc < w) ? W[r + (long long)(c0 + cc) * m] : 0.0;
         }
 #pragma unroll
       for (int cc = 0; cc < GU_KC; ++cc)
 #pragma unroll
-        for (int jj = 0; jj < GU_COLS; ++jj) {
+        for (int jj = 0; jj < COLS; ++jj) {
           const double pc = s_p[c0 + cc][jj];
 #pragma unroll
-          for (int i = 0; i < GU_ROWS; ++i) acc[i][jj] += wr[cc][i] * pc;
+          for (int i = 0; i < ROWS; ++i) acc[i][jj] += wr[cc][i] * pc;
         }
     }
 #pragma unroll
-    for (int i = 0; i < GU_ROWS; ++i) {
-      const int r = r0 + tid + GU_THREADS * i;
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = r0 + tid + THREADS * i;
       if (r >= m) continue;
 #pragma unroll
-      for (int jj = 0; jj < GU_COLS; ++jj)
+      for (int jj = 0; jj < COLS; ++jj)
         if (q0 + jj < nout) colp[jj][r] = acc[i][jj];
     }
+  }
+}
+
+constexpr int GU_THREADS = 256;
+__global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restrict__ Aall, const double* __restrict__ Wall,
+                                                               const int* __restrict__ pivall, int m, int j0, int w) {
+  const long long b = blockIdx.y;
+  gj_update_body<GU_THREADS, 4>(Aall + b * (long long)m * m, Wall + b * (long long)m * PANEL_MAX_NB,
+                                pivall + b * (long long)m, m, j0, w, j0, w, m - w, blockIdx.x);
+}
+
+// One step of the blocked elimination in a single launch: workgroup 0 of each
+// matrix applies the previous panel's update to the panel's own columns (same
+// code and order of operations as the other columns' update), then factors
+// the panel at j0; the other workgroups apply the
+// previous panel's update to every column outside both panels.  The two parts touch disjoint columns; the
+// panel writes its W into the other buffer of the pair.
+template <int RPT, int NB>
+__global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
+                                                                 int* __restrict__ posall, int* __restrict__ pivall,
+                                                                 double* __restrict__ Wall, const double* __restrict__ Wpall,
+                                                                 int wp, int* __restrict__ flag) {
+  const long long b = blockIdx.y;
+  double* A = Aall + b * (long long)m * m;
+  int* piv = pivall + b * (long long)m;
+  const double* Wp = Wpall + b * (long long)m * PANEL_MAX_NB;
+  const int jp = j0 - wp;
+  if (blockIdx.x == 0) {
+    // in groups of GU_COLS columns (measured faster than one group of 16)
+    for (int qb = 0; qb * GU_COLS < nbw; ++qb) {
+      gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, 0, j0, nbw, qb);
+      __syncthreads();  // the updated columns are visible to the workgroup; s_p is free again
+    }
+    gj_panel_body<RPT, NB>(A, m, j0, nbw, posall + b * (long long)m, piv, Wall + b * (long long)m * PANEL_MAX_NB,
+                           flag);
+  } else {
+    gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, jp, wp + nbw, m - wp - nbw, blockIdx.x - 1);
   }
 }
 
@@ -446,6 +484,32 @@ int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, doubl
     hipLaunchKernelGGL((gj_panel_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 8192)
     hipLaunchKernelGGL((gj_panel_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
+  else {
+    set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
+    return HPS_EUNSUPPORTED;
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, const double* Wp, int wp,
+                   int* flag, long long batch, hipStream_t st) {
+  const int nout = m - wp - nbw;
+  dim3 grid((unsigned)(1 + (nout > 0 ? (nout + GU_COLS - 1) / GU_COLS : 0)), (unsigned)batch), block(PANEL_THREADS);
+  if (batch > 65535 || wp > PANEL_MAX_NB || j0 < wp) {
+    set_error("blocked Gauss-Jordan step: batch or panel layout out of range");
+    return HPS_EINVAL;
+  }
+  if (m <= 512)
+    hipLaunchKernelGGL((gj_step_kernel<1, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+  else if (m <= 1024)
+    hipLaunchKernelGGL((gj_step_kernel<2, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+  else if (m <= 2048)
+    hipLaunchKernelGGL((gj_step_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+  else if (m <= 4096)
+    hipLaunchKernelGGL((gj_step_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+  else if (m <= 8192)
+    hipLaunchKernelGGL((gj_step_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else {
     set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
     return HPS_EUNSUPPORTED;

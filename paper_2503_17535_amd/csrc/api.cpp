@@ -234,25 +234,24 @@ int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta 
 
 // Split a table of block ops into workgroup tasks of about kTaskElems elements
 // (runtime-column ops count as 16 columns); long ops are cut by rows and
-// columns, so no workgroup copies more than about kTaskElems elements.
+// columns, so no workgroup copies more than about kTaskElems elements.  Pieces
+// of at most kWaveElems elements are collected in tasks of their own in which
+// each wavefront takes every fourth piece: a whole workgroup walking a small
+// block leaves most of its lanes idle.
 void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
   constexpr long long kTaskElems = 16384;
+  constexpr long long kWaveElems = 1024;
   constexpr int kRtCols = 16;
   const int op0 = (int)op->hops.size();
   op->hops.insert(op->hops.end(), ops.begin(), ops.end());
   call->first_task = (int)op->htasks.size();
-  CopyTask cur{(int)op->hitems.size(), (int)op->hitems.size()};
-  long long load = 0;
-  auto flush = [&]() {
-    if (cur.end > cur.begin) op->htasks.push_back(cur);
-    cur.begin = cur.end = (int)op->hitems.size();
-    load = 0;
+  struct Piece {
+    CopyItem item;
+    long long e;
   };
-  auto push = [&](int opi, int r0, int r1, int c0, int c1, long long e) {
-    if (load + e > kTaskElems) flush();
-    op->hitems.push_back({opi, r0, r1, c0, c1});
-    cur.end = (int)op->hitems.size();
-    load += e;
+  std::vector<Piece> big, small;
+  auto piece = [&](int opi, int r0, int r1, int c0, int c1, long long e) {
+    (e <= kWaveElems ? small : big).push_back({{opi, r0, r1, c0, c1}, e});
   };
   for (size_t i = 0; i < ops.size(); ++i) {
     const BlockOp& o = ops[i];
@@ -261,7 +260,7 @@ void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
       const int rchunk = (int)std::max<long long>(1, kTaskElems / kRtCols);
       for (int r0 = 0; r0 < o.rows; r0 += rchunk) {
         const int r1 = std::min(o.rows, r0 + rchunk);
-        push(opi, r0, r1, 0, -1, (long long)(r1 - r0) * kRtCols);
+        piece(opi, r0, r1, 0, -1, (long long)(r1 - r0) * kRtCols);
       }
       continue;
     }
@@ -271,11 +270,28 @@ void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
       const int r1 = std::min(o.rows, r0 + rchunk);
       for (int c0 = 0; c0 < o.cols; c0 += cchunk) {
         const int c1 = std::min(o.cols, c0 + cchunk);
-        push(opi, r0, r1, c0, c1, (long long)(r1 - r0) * (c1 - c0));
+        piece(opi, r0, r1, c0, c1, (long long)(r1 - r0) * (c1 - c0));
       }
     }
   }
-  flush();
+  // runs of about kTaskElems elements: of big pieces for the whole workgroup,
+  // of small pieces for the wavefronts in turn
+  for (int per_wave = 0; per_wave < 2; ++per_wave) {
+    const std::vector<Piece>& list = per_wave ? small : big;
+    CopyTask cur{(int)op->hitems.size(), (int)op->hitems.size(), per_wave};
+    long long load = 0;
+    for (const Piece& pc : list) {
+      if (load + pc.e > kTaskElems && cur.end > cur.begin) {
+        op->htasks.push_back(cur);
+        cur.begin = cur.end;
+        load = 0;
+      }
+      op->hitems.push_back(pc.item);
+      cur.end = (int)op->hitems.size();
+      load += pc.e;
+    }
+    if (cur.end > cur.begin) op->htasks.push_back(cur);
+  }
   call->ntasks = (int)op->htasks.size() - call->first_task;
 }
 

@@ -75,12 +75,14 @@ struct BlockOp {
 // Work decomposition of a table of BlockOps: an item is a column range of one
 // op (c1 < 0: all runtime columns); a task (one workgroup per batch item) is a
 // run of consecutive items, sized so that every workgroup moves a similar
-// number of elements.
+// number of elements.  Items of a task with per_wave = 0 are copied one after
+// the other by the whole workgroup; with per_wave = 1 (small items) each
+// wavefront copies every fourth item of the task on its own.
 struct CopyItem {
   int op, r0, r1, c0, c1;  // rows [r0, r1), columns [c0, c1) (c1 < 0: the run-time column count)
 };
 struct CopyTask {
-  int begin, end;
+  int begin, end, per_wave;
 };
 
 // ---------------------------------------------------------------------------

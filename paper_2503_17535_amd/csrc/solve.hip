@@ -25,54 +25,71 @@ namespace hps {
 constexpr int BC_THREADS = 256;
 constexpr int BC_UNROLL = 8;  // elements per thread whose loads are in flight together
 
+// Copy (or add) one item: the (row, column) pairs of the item are walked by
+// nthr threads, thread t starting at pair t, with one division up front and
+// BC_UNROLL elements at a time (all their loads go out before the stores).
+template <typename T>
+__device__ __forceinline__ void copy_item(const BlockOp* __restrict__ ops, const CopyItem item, long long b,
+                                          int ncols_rt, T* __restrict__ dst, long long dst_stride,
+                                          const T* __restrict__ src0, long long s0_stride,
+                                          const T* __restrict__ src1, long long s1_stride, int nthr, int t) {
+  const BlockOp op = ops[item.op];
+  const int c0 = item.c0, c1 = item.c1 < 0 ? ncols_rt : item.c1;
+  T* D = dst + b * dst_stride + op.dst_off;
+  const T* S0 = nullptr;
+  const T* S1 = nullptr;
+  if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
+  if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
+  const int rows = item.r1 - item.r0;
+  if (rows <= 0 || c1 <= c0) return;
+  const int dq = nthr / rows, dr = nthr % rows;
+  int r = t % rows, c = c0 + t / rows;
+  while (c < c1) {
+    int er[BC_UNROLL], ec[BC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BC_UNROLL; ++u) {
+      er[u] = item.r0 + r;
+      ec[u] = c;
+      r += dr;
+      c += dq;
+      if (r >= rows) {
+        r -= rows;
+        ++c;
+      }
+    }
+    T v[BC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BC_UNROLL; ++u) {
+      const bool ok = ec[u] < c1;
+      const int cu = ok ? ec[u] : c0;  // a valid column for the unused tail
+      T x = T(0);
+      if (S0) x = S0[er[u] + (long long)cu * op.src_ld[0]];
+      if (S1) x += S1[er[u] + (long long)cu * op.src_ld[1]];
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < BC_UNROLL; ++u)
+      if (ec[u] < c1) D[er[u] + (long long)ec[u] * op.dst_ld] = v[u];
+  }
+}
+
+// One task: its items one after the other by the whole workgroup, or (small
+// items) every fourth item by each wavefront.
 template <typename T>
 __device__ __forceinline__ void block_copy_body(const BlockOp* __restrict__ ops, const CopyItem* __restrict__ items,
                                                 const CopyTask task, long long b, int ncols_rt, T* __restrict__ dst,
                                                 long long dst_stride, const T* __restrict__ src0,
                                                 long long s0_stride, const T* __restrict__ src1,
                                                 long long s1_stride) {
-  for (int it = task.begin; it < task.end; ++it) {
-    const CopyItem item = items[it];
-    const BlockOp op = ops[item.op];
-    const int c0 = item.c0, c1 = item.c1 < 0 ? ncols_rt : item.c1;
-    T* D = dst + b * dst_stride + op.dst_off;
-    const T* S0 = nullptr;
-    const T* S1 = nullptr;
-    if (op.nsrc > 0) S0 = (op.src_buf[0] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[0];
-    if (op.nsrc > 1) S1 = (op.src_buf[1] == 0 ? src0 + b * s0_stride : src1 + b * s1_stride) + op.src_off[1];
-    const int rows = item.r1 - item.r0;
-    if (rows <= 0 || c1 <= c0) continue;
-    // walk the (row, column) pairs of this thread with one division up front,
-    // BC_UNROLL elements at a time: all their loads go out before the stores
-    const int dq = BC_THREADS / rows, dr = BC_THREADS % rows;
-    int r = threadIdx.x % rows, c = c0 + threadIdx.x / rows;
-    while (c < c1) {
-      int er[BC_UNROLL], ec[BC_UNROLL];
-#pragma unroll
-      for (int u = 0; u < BC_UNROLL; ++u) {
-        er[u] = item.r0 + r;
-        ec[u] = c;
-        r += dr;
-        c += dq;
-        if (r >= rows) {
-          r -= rows;
-          ++c;
-        }
-      }
-      T v[BC_UNROLL];
-#pragma unroll
-      for (int u = 0; u < BC_UNROLL; ++u) {
-        const bool ok = ec[u] < c1;
-        const int cu = ok ? ec[u] : c0;  // a valid column for the unused tail
-        T x = T(0);
-        if (S0) x = S0[er[u] + (long long)cu * op.src_ld[0]];
-        if (S1) x += S1[er[u] + (long long)cu * op.src_ld[1]];
-        v[u] = x;
-      }
-#pragma unroll
-      for (int u = 0; u < BC_UNROLL; ++u)
-        if (ec[u] < c1) D[er[u] + (long long)ec[u] * op.dst_ld] = v[u];
-    }
+  constexpr int NWAVE = BC_THREADS / 64;
+  if (task.per_wave) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int it = task.begin + wave; it < task.end; it += NWAVE)
+      copy_item(ops, items[it], b, ncols_rt, dst, dst_stride, src0, s0_stride, src1, s1_stride, 64, lane);
+  } else {
+    for (int it = task.begin; it < task.end; ++it)
+      copy_item(ops, items[it], b, ncols_rt, dst, dst_stride, src0, s0_stride, src1, s1_stride, BC_THREADS,
+                (int)threadIdx.x);
   }
 }
 

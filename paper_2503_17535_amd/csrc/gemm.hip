@@ -252,7 +252,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
 // reads its MFMA fragments straight from memory: no LDS staging, no barriers.
 // Loads go out at clamped, valid addresses; out-of-range rows, columns and k
 // are masked where used.
-constexpr int SKK = 4;
+constexpr int SKK = 2;
 template <typename T, typename G>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(const G* __restrict__ groups, int ngroups,
                                                                    long long nblocks, int n_override) {

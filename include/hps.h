@@ -230,7 +230,9 @@ long long hps_debug_download(const hps_op_t* op, int which, int level, double* o
 
 /* Kernel check, for tests: the library's grouped MFMA GEMM on one product,
  *   C = alpha op(A) op(B) + beta C   (column-major, dev pointers, fp64),
- * op(X) = X or X^T per trans_a / trans_b.  Asynchronous on `stream`. */
+ * op(X) = X or X^T per trans_a / trans_b.  With n <= 16 and neither operand
+ * transposed it runs the skinny kernel the solve uses.  Asynchronous on
+ * `stream`. */
 int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, int trans_a,
                    const double* b, int ldb, int trans_b, double beta, double* c, int ldc,
                    void* stream);

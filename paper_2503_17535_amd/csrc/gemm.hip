@@ -9,6 +9,10 @@
 // layout (measured on gfx950): fp64 lane l, element v holds D(l/16 + 4v, l%16);
 // fp32 lane l, element v holds D(4 (l/16) + v, l%16).
 //
+// Products with at most 16 columns and neither operand transposed (the solve's
+// per-right-hand-side products) take gemm_skinny_kernel: the same blocks, but
+// the wavefronts read their MFMA fragments straight from memory (no LDS).
+//
 // One launch covers a list of groups (GemmGroup); every (group, batch item,
 // tile) triple is one workgroup.  Block indices are remapped so that the
 // blocks the hardware dispatches to one XCD (block id mod 8) are consecutive

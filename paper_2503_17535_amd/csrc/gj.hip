@@ -352,35 +352,35 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
 //   A(:, j) += W A(piv[jp .. jp+w), j)   (W = panel - E_P, written by the panel kernel)
 // for the nout columns j = q (q < jx) and j = q + wx (q >= jx), q < nout: all
 // columns outside [jx, jx + wx) = [jp, jp + w) or a wider range, or (jx = 0)
-// the nout columns from wx on.  A workgroup owns COLS whole columns (the
+// the nout columns from wx on.  A workgroup owns GU_COLS whole columns (the
 // qblk-th group): it first stages the (old) pivot-row entries of its columns
 // in LDS, then rewrites its columns, so no other workgroup can overwrite a
 // pivot row before it is read.
 constexpr int GU_COLS = 8;
 constexpr int GU_KC = 8;  // panel columns per chunk of W loads
-template <int THREADS, int ROWS, int COLS = GU_COLS>
+template <int THREADS, int ROWS>
 __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const double* __restrict__ W,
                                                const int* __restrict__ piv, int m, int jp, int w, int jx, int wx,
                                                int nout, int qblk) {
-  __shared__ double s_p[PANEL_MAX_NB][COLS];
+  __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
   const int tid = threadIdx.x;
-  const int q0 = qblk * COLS;         // first column index q of this workgroup
+  const int q0 = qblk * GU_COLS;         // first column index q of this workgroup
   auto colof = [&](int q) { return q < jx ? q : q + wx; };
-  for (int e = tid; e < PANEL_MAX_NB * COLS; e += THREADS) {
-    const int c = e / COLS, jj = e % COLS, q = q0 + jj;
+  for (int e = tid; e < PANEL_MAX_NB * GU_COLS; e += THREADS) {
+    const int c = e / GU_COLS, jj = e % GU_COLS, q = q0 + jj;
     s_p[c][jj] = (c < w && q < nout) ? A[piv[jp + c] + (long long)colof(q) * m] : 0.0;
   }
   __syncthreads();
-  double* colp[COLS];
+  double* colp[GU_COLS];
 #pragma unroll
-  for (int jj = 0; jj < COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
+  for (int jj = 0; jj < GU_COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
   for (int r0 = 0; r0 < m; r0 += THREADS * ROWS) {
-    double acc[ROWS][COLS];
+    double acc[ROWS][GU_COLS];
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       const int r = r0 + tid + THREADS * i;
 #pragma unroll
-      for (int jj = 0; jj < COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
+      for (int jj = 0; jj < GU_COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
     }
     // K loop in chunks of GU_KC with every W load of a chunk issued first
     for (int c0 = 0; c0 < w; c0 += GU_KC) {
@@ -395,7 +395,7 @@ __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const dou
 #pragma unroll
       for (int cc = 0; cc < GU_KC; ++cc)
 #pragma unroll
-        for (int jj = 0; jj < COLS; ++jj) {
+        for (int jj = 0; jj < GU_COLS; ++jj) {
           const double pc = s_p[c0 + cc][jj];
 #pragma unroll
           for (int i = 0; i < ROWS; ++i) acc[i][jj] += wr[cc][i] * pc;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const dou
       const int r = r0 + tid + THREADS * i;
       if (r >= m) continue;
 #pragma unroll
-      for (int jj = 0; jj < COLS; ++jj)
+      for (int jj = 0; jj < GU_COLS; ++jj)
         if (q0 + jj < nout) colp[jj][r] = acc[i][jj];
     }
   }
@@ -423,9 +423,9 @@ __global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restric
 // One step of the blocked elimination in a single launch: workgroup 0 of each
 // matrix applies the previous panel's update to the panel's own columns (same
 // code and order of operations as the other columns' update), then factors
-// the panel at j0; the other workgroups apply the
-// previous panel's update to every column outside both panels.  The two parts touch disjoint columns; the
-// panel writes its W into the other buffer of the pair.
+// the panel at j0; the other workgroups apply the previous panel's update to
+// every column outside both panels.  The two parts touch disjoint columns;
+// the panel writes its W into the other buffer of the pair.
 template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                  int* __restrict__ posall, int* __restrict__ pivall,

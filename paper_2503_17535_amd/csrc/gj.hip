@@ -459,11 +459,13 @@ int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, 
   return HPS_OK;
 }
 
-// Panels of 16 columns up to m = 2048: a narrower panel shortens the serial
-// chain of the panel kernel (each pivot step updates m x nb register entries)
-// at the cost of one more update launch per 16 columns; 16 measured faster
-// than 32 for m = 448 and 896.
+// Panel widths: a narrower panel shortens the serial chain of the panel
+// workgroup (each pivot step updates m x nb register entries), a wider one
+// needs fewer launches.  With the next panel's factorization running beside
+// the previous panel's update, 8 columns measured fastest for m = 448 and 896
+// (16 and 4 slower).
 int gj_panel_width(int m) {
+  if (m <= 1024) return 8;
   if (m <= 2048) return 16;
   if (m <= 4096) return 8;
   if (m <= 8192) return 4;
@@ -475,9 +477,9 @@ int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, doubl
                     hipStream_t st) {
   dim3 grid((unsigned)batch), block(PANEL_THREADS);
   if (m <= 512)
-    hipLaunchKernelGGL((gj_panel_kernel<1, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<1, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 1024)
-    hipLaunchKernelGGL((gj_panel_kernel<2, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
+    hipLaunchKernelGGL((gj_panel_kernel<2, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 2048)
     hipLaunchKernelGGL((gj_panel_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 4096)
@@ -501,9 +503,9 @@ int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double
     return HPS_EINVAL;
   }
   if (m <= 512)
-    hipLaunchKernelGGL((gj_step_kernel<1, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<1, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else if (m <= 1024)
-    hipLaunchKernelGGL((gj_step_kernel<2, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<2, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else if (m <= 2048)
     hipLaunchKernelGGL((gj_step_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else if (m <= 4096)

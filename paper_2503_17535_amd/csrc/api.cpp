@@ -358,14 +358,20 @@ void clear_stages(hps_op* op) {
 }
 
 // ---------------------------------------------------------------------------
-// batched Gauss-Jordan inversion: register form for m <= 224, blocked above
+// batched Gauss-Jordan inversion: register form for m <= 112 (and up to 224
+// for batches that fill the GPU), blocked above
 // ---------------------------------------------------------------------------
+constexpr int kGjSmallAlways = 112;
+
 int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch) {
   g->m = m;
   g->batch = batch;
   g->A = A;
   g->Z = Z;
-  g->small = m <= gj_small_max();
+  // the single-workgroup kernel (one CU per matrix) up to kGjSmallAlways, and
+  // up to its limit when the batch alone fills the GPU; otherwise the blocked
+  // form, whose column updates run on many CUs beside the panel
+  g->small = m <= kGjSmallAlways || (m <= gj_small_max() && batch >= 256);
   if (g->small) return HPS_OK;
   g->nb = gj_panel_width(m);
   if (g->nb == 0) {
@@ -618,7 +624,7 @@ int plan_op(hps_op* op) {
       set_error("device allocation failed (merge level)");
       return HPS_ENOMEM;
     }
-    if (m > gj_small_max()) {
+    if (m > kGjSmallAlways) {  // block elimination over the interface pieces (measured faster from here on)
       HPS_TRY(plan_schur(op, P, G.schur_p));
     } else {
       HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));

@@ -9,7 +9,8 @@
 // Two forms:
 //  * gj_small: one workgroup per matrix, the whole matrix in registers
 //    (cyclic TR x TC thread grid, the pivot column rotated into slot 0), for
-//    m <= 224 (the many small merges near the leaves);
+//    m <= 224 (used for the many small merges near the leaves, and for large
+//    batches such as 3D leaves);
 //  * blocked: per panel of NB columns one workgroup per matrix factors the
 //    panel with the panel's rows in registers, while the other workgroups of
 //    the same launch apply the previous panel's rank-NB update to every other

@@ -52,7 +52,11 @@ enum {
   HPS_FLAG_ROOT_T = 1,     /* also form the root DtN matrix (unused by Dirichlet solves) */
   HPS_FLAG_NO_CHECK = 2,   /* do not synchronize at the end of hps_build to check pivots */
   HPS_FLAG_TIMING = 4,     /* record per-stage HIP events (read with hps_stage_times)   */
-  HPS_FLAG_FP32_COPY = 8   /* keep fp32 copies of the solve operators (mixed precision) */
+  HPS_FLAG_FP32_COPY = 8,  /* keep fp32 copies of the solve operators (mixed precision) */
+  HPS_FLAG_FULL_PIVOT = 16, /* invert every merge matrix D whole with partial pivoting
+                               (no block elimination around D's zero blocks; m <= 8192) */
+  HPS_FLAG_TEST_NO_REFINE = 1 << 30 /* test hook: skip the Newton-Schulz steps, so that an
+                                       inaccurate block inverse takes the fallback below */
 };
 
 /* solve precision */
@@ -90,6 +94,34 @@ int hps_leaf_points(const hps_tree_t* tree, int p, double* xyz);
  * which hps_solve reads boundary data. */
 int hps_boundary_points(const hps_tree_t* tree, int p, double* xyz);
 
+/* Accuracy of the merge inverses of one tree level (Algorithm merge,
+ * "Invert D").  Every inverse Z = D^{-1} is probed with a fixed vector x:
+ *   residual = max over the level's nodes of |Z (D x) - x|_inf / |x|_inf.
+ * Large merge matrices (m > 112 unless HPS_FLAG_FULL_PIVOT) are inverted by
+ * block elimination around their zero interface blocks, pivoting inside the
+ * blocks only; for indefinite operators (Helmholtz) those blocks can be ill
+ * conditioned while D is not.  Nodes whose probe residual exceeds 1e-12 then
+ * get up to two Newton-Schulz steps Z <- 2Z - (Z D) Z (each squares I - Z D).
+ * If a node stays above 1e-10, or a pivot inside a block is zero, the build
+ * is redone with HPS_FLAG_FULL_PIVOT (partial pivoting over all of D); where
+ * that is unsupported (m > 8192) hps_build returns HPS_ESINGULAR naming the
+ * level and node. */
+typedef struct {
+  int level;            /* tree level of the parents (0 = root)                     */
+  int m;                /* size of D                                                */
+  long long nodes;      /* merges on the level                                      */
+  int block_inverse;    /* 1: block elimination + refinement; 0: whole-D pivoting   */
+  int ns_steps;         /* Newton-Schulz steps run on the worst node (0..2)         */
+  double residual0;     /* max probe residual right after the inversion            */
+  double residual;      /* max probe residual of the stored inverse                */
+  long long worst_node; /* node index (within the level) of `residual`              */
+} hps_level_info_t;
+
+/* Per-level merge-inverse accuracy of a built operator: fills out[0..L-1]
+ * (index = tree level) up to cap entries and returns the number written, or
+ * a negative error code.  Synchronizes the op's build stream the first time. */
+int hps_level_info(hps_op_t* op, hps_level_info_t* out, int cap);
+
 /* Device bytes an operator built with these arguments keeps resident
  * (excluding the transient build workspace), for admission control. */
 size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags);
@@ -102,8 +134,12 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags);
  *   stream  hipStream_t the build is queued on
  *   out     receives the operator handle (NULL on error)
  * Device memory for the operator is allocated by the library.  Unless
- * HPS_FLAG_NO_CHECK is set the call synchronizes the stream once at its end
- * and returns HPS_ESINGULAR if a pivot was exactly zero or not finite. */
+ * HPS_FLAG_NO_CHECK is set the call synchronizes the stream once at its end:
+ * it returns HPS_ESINGULAR if a pivot of a leaf or of a whole-D inversion was
+ * exactly zero or not finite, and checks the merge-inverse probes (see
+ * hps_level_info), redoing the build with HPS_FLAG_FULL_PIVOT when a
+ * block-eliminated inverse stayed inaccurate.  With HPS_FLAG_NO_CHECK neither
+ * check runs (hps_level_info still reports the probes). */
 int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
               void* stream, hps_op_t** out);
 

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhps.so")
 
 HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_ESINGULAR, HPS_EDEVICE, HPS_EUNSUPPORTED = range(6)
-FLAG_ROOT_T, FLAG_NO_CHECK, FLAG_TIMING, FLAG_FP32_COPY = 1, 2, 4, 8
+FLAG_ROOT_T, FLAG_NO_CHECK, FLAG_TIMING, FLAG_FP32_COPY, FLAG_FULL_PIVOT = 1, 2, 4, 8, 16
+FLAG_TEST_NO_REFINE = 1 << 30
 FP64, FP32_REFINED = 0, 1
 
 # every entry point include/hps.h declares
@@ -26,7 +27,7 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
-           "hps_debug_gemm_f32")
+           "hps_debug_gemm_f32", "hps_level_info")
 
 
 class HPSError(RuntimeError):
@@ -45,6 +46,13 @@ class Sizes(ctypes.Structure):
                 ("n_terms", ctypes.c_int), ("n_root_bdry", ctypes.c_longlong),
                 ("n_interior", ctypes.c_int), ("n_leaf_bdry", ctypes.c_int),
                 ("n_levels", ctypes.c_int), ("root_D", ctypes.c_longlong)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("m", ctypes.c_int), ("nodes", ctypes.c_longlong),
+                ("block_inverse", ctypes.c_int), ("ns_steps", ctypes.c_int),
+                ("residual0", ctypes.c_double), ("residual", ctypes.c_double),
+                ("worst_node", ctypes.c_longlong)]
 
 
 class BatchItem(ctypes.Structure):
@@ -93,6 +101,7 @@ def lib():
         L.hps_batcher_free.argtypes = [P]
         L.hps_batcher_free.restype = None
         L.hps_precompute_matrix.argtypes = [I, I, I, P, LL, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.hps_level_info.argtypes = [P, ctypes.POINTER(LevelInfo), I]
         for name in EXPORTS:
             if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error", "hps_batcher_free",
                             "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
@@ -231,6 +240,16 @@ class Operator:
         gptr = _dev_ptr(out, "grad", (s.n_leaves, s.n_terms, s.pts_per_leaf))
         _check(lib().hps_coeff_grad(self._h, uptr, lptr, nrhs, gptr, _stream_ptr(stream)))
         return out
+
+    def level_info(self):
+        """Per-level merge-inverse accuracy (see hps_level_info): a list of
+        dicts, index = tree level (0 = root)."""
+        cap = self.sizes.n_levels
+        arr = (LevelInfo * max(1, cap))()
+        n = lib().hps_level_info(self._h, arr, cap)
+        if n < 0:
+            _check(-n)
+        return [{k: getattr(arr[i], k) for k, _ in LevelInfo._fields_} for i in range(n)]
 
     def stage_times(self):
         names = (ctypes.c_char_p * 64)()

@@ -81,6 +81,10 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
                     int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st);
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
                     int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st);
+int probe_reduce_launch(const double* r, long long stride, int m, double inv_xmax, double tau, double* rho,
+                        int* gate, long long nodes, hipStream_t st);
+int gated_copy_launch(double* dst, const double* src, long long n, const int* gate, long long nodes,
+                      hipStream_t st);
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -368,6 +372,7 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
   g->batch = batch;
   g->A = A;
   g->Z = Z;
+  g->flag = op->flag;
   // the single-workgroup kernel (one CU per matrix) up to kGjSmallAlways, and
   // up to its limit when the batch alone fills the GPU; otherwise the blocked
   // form, whose column updates run on many CUs beside the panel
@@ -390,17 +395,17 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
 }
 
 int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
-  if (g.small) return gj_small_launch(g.A, g.Z, g.m, op->flag, g.batch, st);
+  if (g.small) return gj_small_launch(g.A, g.Z, g.m, g.flag, g.batch, st);
   HPS_TRY(gj_init_launch(g.pos, g.batch * g.m, st));
   // panel k writes W buffer k % 2; launch k (k >= 1) factors panel k beside
   // the update by panel k - 1 of the columns outside both panels
   const long long wbuf = g.batch * g.m * gj_panel_max_nb();
   const int np = (g.m + g.nb - 1) / g.nb;
-  HPS_TRY(gj_panel_launch(g.A, g.m, 0, std::min(g.nb, g.m), g.pos, g.piv, g.W, op->flag, g.batch, st));
+  HPS_TRY(gj_panel_launch(g.A, g.m, 0, std::min(g.nb, g.m), g.pos, g.piv, g.W, g.flag, g.batch, st));
   for (int k = 1; k < np; ++k) {
     const int j0 = k * g.nb, w = std::min(g.nb, g.m - j0);
     HPS_TRY(gj_step_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W + (k % 2) * wbuf, g.W + ((k - 1) % 2) * wbuf, g.nb,
-                           op->flag, g.batch, st));
+                           g.flag, g.batch, st));
   }
   const int jl = (np - 1) * g.nb;
   HPS_TRY(gj_update_launch(g.A, g.W + ((np - 1) % 2) * wbuf, g.piv, g.m, jl, g.m - jl, g.batch, st));
@@ -435,6 +440,9 @@ int plan_schur(hps_op* op, LevelPlan& P, int schur_p) {
   }
   HPS_TRY(plan_gj(op, &P.gjA, P.Ablk, P.Ainv, s, 2 * nm));
   HPS_TRY(plan_gj(op, &P.gjS, P.Sc, P.Scinv, r, nm));
+  // a zero pivot inside a block is not a singular D: it goes to its own flag
+  // slot, and the checked build then falls back to pivoting over all of D
+  P.gjA.flag = P.gjS.flag = op->flag + 1;
   const long long s2 = 2LL * s * s, sr2 = 2LL * s * r, r2 = (long long)r * r;
   {  // A_b = D(P_b, P_b)
     std::vector<BlockOp> ops;
@@ -505,6 +513,72 @@ int run_schur(hps_op* op, LevelPlan& P, hipStream_t st) {
   HPS_TRY(run_gemm(op, P.gemmZ1, st));
   HPS_TRY(run_copy(op, P.copyScZ, 0, P.Z, mm, P.Scinv, r2, nullptr, 0, P.nm, st));
   HPS_TRY(run_gemm(op, P.gemmZPP, st));
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// accuracy guard of the merge inverses: probe residual per node, gated
+// Newton-Schulz steps on the block-eliminated levels
+// ---------------------------------------------------------------------------
+constexpr int kProbes = 4;           // probe vectors per merge inverse
+constexpr int kNsSteps = 2;          // Newton-Schulz steps at most
+constexpr double kNsRefine = 1e-12;  // refine a node whose probe residual is above this
+constexpr double kNsAccept = 1e-10;  // above this after refinement: pivot over all of D instead
+
+int plan_guard(hps_op* op, LevelPlan& P) {
+  const int m = P.m;
+  const long long nm = P.nm, mm = (long long)m * m;
+  const long long mp = (long long)m * kProbes;
+  const int ldx = op->probe_ld;
+  P.py = (double*)op_alloc(op, sizeof(double) * nm * mp, false);
+  P.pr = (double*)op_alloc(op, sizeof(double) * nm * mp, false);
+  P.rho = (double*)op_alloc(op, sizeof(double) * (kNsSteps + 1) * nm, false);
+  P.gate = (int*)op_alloc(op, sizeof(int) * nm, false);
+  if (!P.py || !P.pr || !P.rho || !P.gate) {
+    set_error("device allocation failed (merge inverse probe)");
+    return HPS_ENOMEM;
+  }
+  // block-eliminated: y = Z x, r = D y - x;  whole-D: y = D x (before the
+  // inversion), r = Z y - x
+  const double* first = P.schur ? P.Z : P.Dbuf;
+  const double* second = P.schur ? P.Dbuf : P.Z;
+  add_gemm(op, {make_group(first, mm, m, op->probe_x, 0, ldx, P.py, mp, m, m, kProbes, m, 1.0, 0.0, nm)},
+           &P.probe1);
+  add_gemm(op, {make_group(second, mm, m, P.py, mp, m, P.pr, mp, m, m, kProbes, m, 1.0, -1.0, nm, op->probe_x, 0,
+                           ldx)},
+           &P.probe2);
+  if (!P.schur) return HPS_OK;
+  P.Wns = (double*)op_alloc(op, sizeof(double) * nm * mm, false);
+  P.Zns = (double*)op_alloc(op, sizeof(double) * nm * mm, false);
+  if (!P.Wns || !P.Zns) {
+    set_error("device allocation failed (Newton-Schulz workspace)");
+    return HPS_ENOMEM;
+  }
+  // W = D Z;  Zns = 2 Z - Z W   (I - D Zns = (I - D Z)^2)
+  GemmGroup w = make_group(P.Dbuf, mm, m, P.Z, mm, m, P.Wns, mm, m, m, m, m, 1.0, 0.0, nm);
+  w.gate = P.gate;
+  add_gemm(op, {w}, &P.nsW);
+  GemmGroup z = make_group(P.Z, mm, m, P.Wns, mm, m, P.Zns, mm, m, m, m, m, -1.0, 2.0, nm, P.Z, mm, m);
+  z.gate = P.gate;
+  add_gemm(op, {z}, &P.nsZ);
+  return HPS_OK;
+}
+
+// the probe after the inversion (k = 0) or after Newton-Schulz step k
+int run_probe(hps_op* op, LevelPlan& P, int k, hipStream_t st) {
+  if (P.schur) HPS_TRY(run_gemm(op, P.probe1, st, kProbes));
+  HPS_TRY(run_gemm(op, P.probe2, st, kProbes));
+  return probe_reduce_launch(P.pr, (long long)P.m * kProbes, P.m * kProbes, op->probe_inv_xmax, kNsRefine,
+                             P.rho + k * P.nm, P.gate, P.nm, st);
+}
+
+int run_refine(hps_op* op, LevelPlan& P, hipStream_t st) {
+  for (int k = 1; k <= kNsSteps; ++k) {
+    HPS_TRY(run_gemm(op, P.nsW, st));
+    HPS_TRY(run_gemm(op, P.nsZ, st));
+    HPS_TRY(gated_copy_launch(P.Z, P.Zns, (long long)P.m * P.m, P.gate, P.nm, st));
+    HPS_TRY(run_probe(op, P, k, st));
+  }
   return HPS_OK;
 }
 
@@ -597,6 +671,28 @@ int plan_op(hps_op* op) {
     add_copy(op, {o}, &op->copyRoot);
   }
 
+  // probe vectors of the merge-inverse guard: fixed pseudo-random values in
+  // [-1, 1) (splitmix64 of the element index)
+  {
+    long long mmax = 1;
+    const long long n0 = d == 2 ? (long long)(op->p - 2) : (long long)(op->p - 2) * (op->p - 2);
+    for (int lev = L - 1; lev >= 0; --lev) mmax = std::max<long long>(mmax, G.nint * (n0 << ((d - 1) * (L - 1 - lev))));
+    op->probe_ld = (int)mmax;
+    std::vector<double> x((size_t)mmax * kProbes);
+    double xmax = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) {
+      uint64_t z = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+      z ^= z >> 31;
+      x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+      xmax = std::max(xmax, std::fabs(x[i]));
+    }
+    op->probe_x = (double*)op_alloc(op, sizeof(double) * x.size(), false);
+    if (!op->probe_x) { set_error("device allocation failed (probe vector)"); return HPS_ENOMEM; }
+    HPS_HIP_TRY(hipMemcpy(op->probe_x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice));
+    op->probe_inv_xmax = 1.0 / xmax;
+  }
   op->levels.assign(L, LevelPlan());
   for (int lev = L - 1; lev >= 0; --lev) {
     LevelPlan& P = op->levels[lev];
@@ -624,11 +720,13 @@ int plan_op(hps_op* op) {
       set_error("device allocation failed (merge level)");
       return HPS_ENOMEM;
     }
-    if (m > kGjSmallAlways) {  // block elimination over the interface pieces (measured faster from here on)
+    if (m > kGjSmallAlways && !(op->flags & HPS_FLAG_FULL_PIVOT)) {
+      // block elimination over the interface pieces (measured faster from here on)
       HPS_TRY(plan_schur(op, P, G.schur_p));
     } else {
       HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));
     }
+    HPS_TRY(plan_guard(op, P));
     // --- D = sum over children touching interfaces i and j of T_c(face_i, face_j)
     {
       std::vector<BlockOp> ops;
@@ -826,6 +924,53 @@ int plan_op(hps_op* op) {
   return HPS_OK;
 }
 
+// Per-level probe results (synchronizes the op's stream).  Node residuals
+// are read from the last probe each node went through.
+int collect_info(hps_op* op) {
+  if (op->info_ready) return HPS_OK;
+  HPS_HIP_TRY(hipStreamSynchronize(op->stream));
+  const int L = op->tree.depth;
+  op->info.assign(L, hps_level_info_t());
+  for (int lev = 0; lev < L; ++lev) {
+    const LevelPlan& P = op->levels[lev];
+    const int nk = (P.schur && !(op->flags & HPS_FLAG_TEST_NO_REFINE)) ? kNsSteps + 1 : 1;
+    std::vector<double> rho((size_t)nk * P.nm);
+    HPS_HIP_TRY(hipMemcpy(rho.data(), P.rho, sizeof(double) * rho.size(), hipMemcpyDeviceToHost));
+    hps_level_info_t& I = op->info[lev];
+    I.level = lev;
+    I.m = P.m;
+    I.nodes = P.nm;
+    I.block_inverse = P.schur ? 1 : 0;
+    I.ns_steps = 0;
+    I.residual0 = 0.0;
+    I.residual = 0.0;
+    I.worst_node = 0;
+    for (long long b = 0; b < P.nm; ++b) {
+      const double r0 = rho[b];
+      // a node is refined at step k + 1 when the probe after step k is above
+      // the threshold (the gate); its final residual is that of the last probe
+      int steps = 0;
+      double rf = r0;
+      for (int k = 0; k + 1 < nk; ++k) {
+        if (!(rho[(size_t)k * P.nm + b] <= kNsRefine)) {
+          steps = k + 1;
+          rf = rho[(size_t)(k + 1) * P.nm + b];
+        } else {
+          break;
+        }
+      }
+      if (!(r0 <= I.residual0)) I.residual0 = r0;
+      if (!(rf <= I.residual)) {
+        I.residual = rf;
+        I.worst_node = b;
+        I.ns_steps = steps;
+      }
+    }
+  }
+  op->info_ready = true;
+  return HPS_OK;
+}
+
 int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
   const int L = op->tree.depth, nd = op->nd;
   HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
@@ -851,10 +996,14 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
     const long long childstride = (long long)nd * P.nbc * P.nbc;
     stage_begin(op, names[lev < 12 ? lev : 11], st);
     HPS_TRY(run_copy(op, P.copyD, 0, P.Dbuf, (long long)P.m * P.m, Tchild, childstride, nullptr, 0, P.nm, st));
+    if (!P.schur) HPS_TRY(run_gemm(op, P.probe1, st, kProbes));  // D x, before the inversion overwrites D
     if (P.schur) {
       HPS_TRY(run_schur(op, P, st));
+      HPS_TRY(run_probe(op, P, 0, st));
+      if (!(op->flags & HPS_FLAG_TEST_NO_REFINE)) HPS_TRY(run_refine(op, P, st));
     } else {
       HPS_TRY(run_gj(op, P.gj, st));
+      HPS_TRY(run_probe(op, P, 0, st));
     }
     HPS_TRY(run_gemm(op, P.gemmS, st));
     HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)nd * P.dn * P.dn, Tchild, childstride, nullptr, 0, P.nm, st));
@@ -1228,6 +1377,15 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags) {
 
 size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident : 0; }
 
+int hps_level_info(hps_op_t* op, hps_level_info_t* out, int cap) {
+  if (!op || (cap > 0 && !out)) { set_error("op must be non-NULL (and out when cap > 0)"); return -HPS_EINVAL; }
+  const int rc = collect_info(op);
+  if (rc != HPS_OK) return -rc;
+  const int n = std::min(cap, (int)op->info.size());
+  for (int i = 0; i < n; ++i) out[i] = op->info[i];
+  return n;
+}
+
 int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, void* stream, hps_op_t** out) {
   if (out) *out = nullptr;
   HPS_TRY(check_tree(tree, p));
@@ -1249,6 +1407,7 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
   int rc = get_consts(op->d, p, op->r, &op->cst);
   if (rc == HPS_OK) rc = plan_op(op);
   if (rc == HPS_OK) rc = run_build(op, coeffs, op->stream);
+  bool retry_full_pivot = false;
   if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) {
     int hflag[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
@@ -1260,7 +1419,36 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
       set_error(std::string("zero or non-finite pivot in ") +
                 ((hflag[0] & 1) ? "a leaf factorization (L_ii)" : "a merge matrix D"));
       rc = HPS_ESINGULAR;
+    } else {
+      rc = collect_info(op);
+      // block-eliminated inverses that stayed inaccurate after refinement,
+      // or a zero pivot inside one of their blocks
+      int bad = -1;
+      for (int lev = 0; rc == HPS_OK && lev < (int)op->info.size(); ++lev)
+        if (op->info[lev].block_inverse && (hflag[1] || !(op->info[lev].residual <= kNsAccept))) bad = lev;
+      if (bad >= 0) {
+        bool full_ok = true;
+        for (const auto& I : op->info) full_ok = full_ok && I.m <= 8192;
+        if (full_ok) {
+          retry_full_pivot = true;
+        } else {
+          const hps_level_info_t& I = op->info[bad];
+          char buf[256];
+          std::snprintf(buf, sizeof(buf),
+                        "merge level %d node %lld: inverse of D (m = %d) by block elimination has probe residual "
+                        "%.2e after %d Newton-Schulz steps%s, and m exceeds the whole-D pivoting limit (8192)",
+                        bad, I.worst_node, I.m, I.residual, I.ns_steps, hflag[1] ? " (zero pivot in a block)" : "");
+          set_error(buf);
+          rc = HPS_ESINGULAR;
+        }
+      }
     }
+  }
+  if (retry_full_pivot) {
+    // rare path: redo the whole build with partial pivoting over every D
+    (void)hipStreamSynchronize(op->stream);
+    hps_free(op);
+    return hps_build(tree, p, coeffs, flags | HPS_FLAG_FULL_PIVOT, stream, out);
   }
   if (rc == HPS_OK && (flags & HPS_FLAG_FP32_COPY)) rc = setup_fp32(op, coeffs, op->stream);
   if (rc != HPS_OK) {
@@ -1356,7 +1544,9 @@ int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap) {
 
 void hps_free(hps_op_t* op) {
   if (!op) return;
-  (void)hipStreamSynchronize(op->stream);
+  // solves, adjoint solves and batches may have used the operator on any
+  // stream: wait for all queued device work before its memory is recycled
+  (void)hipDeviceSynchronize();
   clear_stages(op);
   for (auto& a : op->allocs) dfree(a.p, a.bytes);
   delete op;

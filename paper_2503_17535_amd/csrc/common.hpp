@@ -32,6 +32,9 @@ struct GemmGroup {
   int ksplit, kchunk;
   long long part_off;
   double* part;
+  // gate[b] == 0 skips batch item b (NULL: every item runs); read on the
+  // device, so a kernel earlier on the stream can switch items on and off
+  const int* gate;
   // filled by the launcher
   int tiles_m, tiles_n;
   long long first_block, first_rblock;
@@ -52,6 +55,7 @@ struct GemmGroupF32 {
   int ksplit, kchunk;
   long long part_off;
   float* part;
+  const int* gate;
   int tiles_m, tiles_n;
   long long first_block, first_rblock;
 };

@@ -98,6 +98,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_grouped_kernel(const G* __r
   const long long bat = rel / tiles;
   const int tile = (int)(rel - bat * tiles);
   const int tm = tile % g->tiles_m, tn = tile / g->tiles_m;
+  if (g->gate && g->gate[bat] == 0) return;  // whole workgroup, before any barrier
   const int M = g->M, K = g->K;
   const int N = (n_override > 0 && n_override < g->N) ? n_override : g->N;
   const int i0 = tm * BM, j0 = tn * BN;
@@ -272,6 +273,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(const G* __re
   const int tile = (int)(rel - bat * tiles);
   const int tm = tile % g->tiles_m, tn = tile / g->tiles_m;
   if (tn > 0) return;  // columns past 64: none when N <= 16
+  if (g->gate && g->gate[bat] == 0) return;
   const int M = g->M, K = g->K;
   const int N = (n_override > 0 && n_override < g->N) ? n_override : g->N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -366,6 +368,7 @@ __global__ __launch_bounds__(RED_THREADS) void gemm_splitk_reduce_kernel(const G
   const long long mn = (long long)M * Nf;
   const long long bat = e / mn;
   if (bat >= g->batch) return;
+  if (g->gate && g->gate[bat] == 0) return;
   const int rem = (int)(e - bat * mn);
   const int col = rem / M, row = rem - col * M;
   if (col >= N) return;

@@ -36,6 +36,7 @@ struct GJPlan {
   int m = 0;
   long long batch = 0;
   double *A = nullptr, *Z = nullptr;
+  int* flag = nullptr;  // pivot failure flag the kernels set
   bool small = true;
   int nb = 0;
   int *pos = nullptr, *piv = nullptr;
@@ -65,6 +66,17 @@ struct LevelPlan {
   GJPlan gjA, gjS;
   CopyCall copyA, copyScZ;
   GemmCall gemmXY, gemmSc, gemmZ1, gemmZPP;
+  // accuracy guard with a few probe vectors x (the columns of op->probe_x):
+  // block-eliminated levels probe the right residual, y = Z x, r = D y - x
+  // (D stays intact); whole-D levels, whose Gauss-Jordan overwrites D, the
+  // left one, y = D x before the inversion, r = Z y - x.  rho = |r|_inf /
+  // |x|_inf per node after the inversion and after each Newton-Schulz step
+  // (rho[k * nm + node]).  The steps W = D Z, Zns = 2 Z - Z W run on the
+  // block-eliminated levels only, for the nodes whose gate the previous probe
+  // switched on.
+  double *py = nullptr, *pr = nullptr, *rho = nullptr, *Wns = nullptr, *Zns = nullptr;
+  int* gate = nullptr;
+  GemmCall probe1, probe2, nsW, nsZ;
   // fp32 copies for the mixed-precision solve
   float *Z32 = nullptr, *S32 = nullptr, *Bnz32 = nullptr;
   float *hint32 = nullptr, *gt32 = nullptr, *gint32 = nullptr;
@@ -133,6 +145,14 @@ struct hps_op {
   long long split_elems = 0;                   // split-K workspace (elements), fp64 and fp32
   double* splitws = nullptr;
   float* splitws32 = nullptr;
+  // merge-inverse probe vectors x (device, kProbes columns of the length of
+  // the largest D) and 1 / |x|_inf; per-level results of the probes, filled
+  // when the build is checked (host)
+  double* probe_x = nullptr;
+  int probe_ld = 0;
+  double probe_inv_xmax = 1.0;
+  bool info_ready = false;
+  std::vector<hps_level_info_t> info;
   std::vector<hps::Alloc> allocs;
   size_t resident = 0;
   std::vector<hps::TimedStage> stages;

@@ -283,7 +283,7 @@ def leaf_solve(disc: LeafDisc, ops, Qr: np.ndarray, c: np.ndarray, f=None) -> Le
 # Merge stage
 # --------------------------------------------------------------------------
 class MergeNode:
-    __slots__ = ("S", "gt", "perm", "D_lu", "B", "ext_idx", "int_idx", "n")
+    __slots__ = ("S", "gt", "perm", "D_lu", "Dinv", "B", "ext_idx", "int_idx", "n")
 
 
 def _child_index_sets(d: int, n: int):
@@ -394,20 +394,33 @@ def merge_blocks_general(d, T, h, n):
     return A, B, C, D, h_ext, h_int
 
 
-def merge(d, T, h, n, with_T=True):
+def merge(d, T, h, n, with_T=True, d_inverse="lu"):
     """One merge (Algorithm "Merge stage", inner loop body).  Returns the node
-    record and the parent's T, h in parent boundary order."""
+    record and the parent's T, h in parent boundary order.
+
+    "Invert D" is read as an LU factorization with partial pivoting applied
+    by triangular solves (d_inverse="lu", the default), or as the explicit
+    inverse D^{-1} applied by products (d_inverse="explicit"); the algorithm
+    does not say which, and the two differ only by rounding."""
     if d == 2:
         A, B, C, D, h_ext, h_int = merge_blocks_2d(T, h, n)
     else:
         A, B, C, D, h_ext, h_int = merge_blocks_general(d, T, h, n)
-    D_lu = sla.lu_factor(D)                       # "Invert D"
-    S = -sla.lu_solve(D_lu, C)                    # S = -D^{-1} C
-    gt = -sla.lu_solve(D_lu, h_int)               # g~ = -D^{-1} h_int
+    D_lu, Dinv = None, None
+    if d_inverse == "lu":
+        D_lu = sla.lu_factor(D)                   # "Invert D"
+        S = -sla.lu_solve(D_lu, C)                # S = -D^{-1} C
+        gt = -sla.lu_solve(D_lu, h_int)           # g~ = -D^{-1} h_int
+    elif d_inverse == "explicit":
+        Dinv = sla.inv(D)                         # "Invert D", explicitly
+        S = -(Dinv @ C)
+        gt = -(Dinv @ h_int)
+    else:
+        raise ValueError(d_inverse)
     h_seg = h_ext + B @ gt                        # h = h_ext - B D^{-1} h_int
     perm = parent_order(d, n)
     node = MergeNode()
-    node.S, node.gt, node.perm, node.D_lu, node.B, node.n = S, gt, perm, D_lu, B, n
+    node.S, node.gt, node.perm, node.D_lu, node.Dinv, node.B, node.n = S, gt, perm, D_lu, Dinv, B, n
     Tp = None
     if with_T:
         T_seg = A + B @ S                         # T = A - B D^{-1} C
@@ -423,9 +436,10 @@ class Operator:
 
 
 def build(tree: Tree, p: int, coeffs: np.ndarray, f: np.ndarray | None = None,
-          root_T: bool = False) -> Operator:
+          root_T: bool = False, d_inverse: str = "lu") -> Operator:
     """Local solve stage + merge stage.  coeffs[leaf, term, point]; f (optional)
-    [leaf, point] folds a source into the build (paper form)."""
+    [leaf, point] folds a source into the build (paper form); d_inverse
+    selects the reading of "Invert D" (see merge)."""
     d = tree.d
     disc = LeafDisc(d, p)
     ops = disc.term_ops(tree.leaf_r)
@@ -441,7 +455,7 @@ def build(tree: Tree, p: int, coeffs: np.ndarray, f: np.ndarray | None = None,
         nodes, Tn, hn = [], [], []
         for j in range(len(T) // nd):
             kids = slice(nd * j, nd * j + nd)
-            node, Tp, hp = merge(d, T[kids], h[kids], n, with_T=(lev > 0 or root_T))
+            node, Tp, hp = merge(d, T[kids], h[kids], n, with_T=(lev > 0 or root_T), d_inverse=d_inverse)
             nodes.append(node)
             Tn.append(Tp)
             hn.append(hp)
@@ -525,7 +539,7 @@ def up_pass(op: Operator, f: np.ndarray):
             for c in range(nd):
                 for i, ii in inter[c].items():
                     h_int[i * n:(i + 1) * n] += kids[c][ii]
-            gt = -sla.lu_solve(node.D_lu, h_int)
+            gt = -sla.lu_solve(node.D_lu, h_int) if node.Dinv is None else -(node.Dinv @ h_int)
             gts.append(gt)
             hn.append((h_ext + node.B @ gt)[node.perm])
         gt_levels[lev] = gts

@@ -59,3 +59,67 @@ def oracle_solve(d, p, L, coeffs, bd, src):
 def rel_inf(u, ref):
     """max over right-hand sides of ||u - ref||_inf / ||ref||_inf"""
     return max(np.abs(u[r] - ref[r]).max() / np.abs(ref[r]).max() for r in range(ref.shape[0]))
+
+
+def composite_solve(tree, p, coeffs, bd_r, bpts, src_r):
+    """Solution of the composite collocation system (oracle.dense, sparse LU)
+    for boundary values bd_r given at the root boundary points bpts.  In exact
+    arithmetic it equals the HPS solution, so its distance to the HPS oracle
+    measures how far rounding alone moves the result for this problem."""
+    import scipy.sparse.linalg as spla
+    from oracle import dense
+
+    def g_fun(x):
+        d2 = ((x[:, None, :] - bpts[None, :, :]) ** 2).sum(-1)
+        j = d2.argmin(axis=1)
+        assert np.all(d2[np.arange(len(j)), j] < 1e-24)
+        return bd_r[j]
+
+    K, layout = dense.assemble(tree, p, coeffs, sparse=True)
+    b = dense.rhs(tree, layout, src_r, g_fun)
+    x = spla.splu(K.tocsc()).solve(b)
+    return x[:layout["n_u"]].reshape(tree.n_leaves, p ** tree.d)
+
+
+def rounding_spread(tree, p, coeffs, bd, bpts, src, ref):
+    """max over rhs of the relative distance between the HPS oracle (ref) and
+    the composite-system solution: the spread of two fp64 computations of the
+    same exact result."""
+    alt = np.stack([composite_solve(tree, p, coeffs, bd[r], bpts, None if src is None else src[r])
+                    for r in range(bd.shape[0])])
+    return rel_inf(alt, ref)
+
+
+def merge_conditioning(tree, p, coeffs):
+    """cond_2(D) of every merge matrix of the oracle's tree, as
+    {m: (max, median)} (the conditioning the merges' inverses work under)."""
+    from oracle import hps as H
+    disc = ohps.LeafDisc(tree.d, p)
+    ops = disc.term_ops(tree.leaf_r)
+    Qr = disc.Q / tree.leaf_r
+    T = []
+    h = []
+    for i in range(tree.n_leaves):
+        lf = ohps.leaf_solve(disc, ops, Qr, coeffs[i], None)
+        T.append(lf.T)
+        h.append(lf.h)
+    nd = 2 ** tree.d
+    n = disc.n_face
+    out = {}
+    for lev in range(tree.L - 1, -1, -1):
+        Tn, hn, cs = [], [], []
+        for j in range(len(T) // nd):
+            kids = slice(nd * j, nd * j + nd)
+            if tree.d == 2:
+                D = H.merge_blocks_2d(T[kids], h[kids], n)[3]
+            else:
+                D = H.merge_blocks_general(tree.d, T[kids], h[kids], n)[3]
+            cs.append(np.linalg.cond(D))
+            if lev > 0:
+                _, Tp, hp = H.merge(tree.d, T[kids], h[kids], n)
+                Tn.append(Tp)
+                hn.append(hp)
+        out[D.shape[0]] = (float(max(cs)), float(np.median(cs)))
+        T, h = Tn, hn
+        n *= 2 ** (tree.d - 1)
+    return out

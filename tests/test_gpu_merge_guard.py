@@ -22,17 +22,22 @@ torch = pytest.importorskip("torch")
 TOL = 1e-10
 
 
-def _helmholtz(k, p, L, nrhs, flags=0):
-    import paper_2503_17535_amd as hp
+def _oracle(k, p, L, nrhs, d_inverse="lu"):
     import workloads as W
-    say(f"[case] Helmholtz k={k} p={p} L={L} nrhs={nrhs} flags={flags}")
     tree = ohps.Tree(2, L)
     disc = ohps.LeafDisc(2, p)
     pts = tree.leaf_points(disc)
     bpts = tree.root_boundary_points(disc)
     c, bd, src = W.helmholtz_inputs(pts, bpts, k, nrhs)
-    op_o = ohps.build(tree, p, c)
+    op_o = ohps.build(tree, p, c, d_inverse=d_inverse)
     ref = np.stack([ohps.solve(op_o, bd[r], src[r]) for r in range(nrhs)])
+    return tree, c, bd, src, ref
+
+
+def _helmholtz(k, p, L, nrhs, flags=0):
+    import paper_2503_17535_amd as hp
+    say(f"[case] Helmholtz k={k} p={p} L={L} nrhs={nrhs} flags={flags}")
+    tree, c, bd, src, ref = _oracle(k, p, L, nrhs)
     dev = torch.device("cuda:0")
     op = hp.build(hp.tree(2, L), p, torch.tensor(c, device=dev), flags=flags)
     u = op.solve(torch.tensor(bd, device=dev), torch.tensor(src, device=dev)).cpu().numpy()
@@ -61,10 +66,23 @@ def test_smoke_inputs_root_block_refined():
 @pytest.mark.parametrize("k", [9.93, 14.05])
 def test_near_subdomain_resonance(k):
     # k^2 next to Dirichlet eigenvalues of two-leaf sub-rectangles at the
-    # root (9.93) and at the lowest merge level (14.05, block residual 1e-5)
+    # root (9.93) and at the lowest merge level (14.05, block residual 1e-5).
+    # At 14.05 a lowest-level D itself has cond 2.4e5, and the two readings
+    # of "Invert D" in the oracle (LU solves, explicit inverse) differ by
+    # 1.8e-10: rounding alone moves the solution that far, so the bar is
+    # the larger of 1e-10 and twice that spread (the library inverts
+    # explicitly).
+    from gpu_util import merge_conditioning
     err, info = _helmholtz(k, 12, 3, 2)
+    tree, c, _, _, ref = _oracle(k, 12, 3, 2)
+    alt = _oracle(k, 12, 3, 2, d_inverse="explicit")[4]
+    spread = rel_inf(alt, ref)
+    conds = merge_conditioning(tree, 12, c)
+    tol = max(TOL, 2.0 * spread)
+    say(f"[case] k={k}: cond(D) per m (max, median) {conds}; oracle LU vs explicit {spread:.2e}; "
+        f"bar {tol:.2e}; GPU {err:.2e}")
     assert all(I["residual"] < 1e-10 for I in info)
-    assert err < TOL
+    assert err < tol
 
 
 def test_whole_d_pivoting_flag():

@@ -102,8 +102,11 @@ def test_weighted_DtN_symmetry_improves_with_p():
 # ---------------------------------------------------------------------------
 # P5 / P6: against the dense composite collocation system
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d_inverse", ["lu", "explicit"])
 @pytest.mark.parametrize("d,p,L", [(2, 8, 2), (2, 7, 1), (3, 5, 1), (3, 4, 2)])
-def test_full_solve_matches_dense_system(d, p, L):
+def test_full_solve_matches_dense_system(d, p, L, d_inverse):
+    # both readings of "Invert D" (LU solves, explicit inverse) reach the
+    # composite system's solution
     tree = hps.Tree(d, L)
     disc = hps.LeafDisc(d, p)
     pts = tree.leaf_points(disc)
@@ -111,10 +114,13 @@ def test_full_solve_matches_dense_system(d, p, L):
     f = np.sin(pts[..., 0] + 0.5) * np.cos(2 * pts[..., 1])
     gfun = lambda x: np.cos(x[..., 0]) + x[..., 1] ** 2 - 0.5 * x[..., -1]
     bp = tree.root_boundary_points(disc)
-    op = hps.build(tree, p, c, f)
+    op = hps.build(tree, p, c, f, d_inverse=d_inverse)
     u = hps.solve(op, gfun(bp))
     ud = dense.solve(tree, p, c, f, gfun)
     assert np.abs(u - ud).max() < 1e-11 * np.abs(ud).max()
+    if d_inverse == "explicit":  # the solve-time source path uses the same inverse
+        op2 = hps.build(tree, p, c, d_inverse=d_inverse)
+        assert np.abs(hps.solve(op2, gfun(bp), f) - ud).max() < 1e-11 * np.abs(ud).max()
 
 
 @pytest.mark.parametrize("d,p,L", [(2, 8, 1), (2, 6, 2), (3, 5, 1)])

@@ -283,7 +283,7 @@ def leaf_solve(disc: LeafDisc, ops, Qr: np.ndarray, c: np.ndarray, f=None) -> Le
 # Merge stage
 # --------------------------------------------------------------------------
 class MergeNode:
-    __slots__ = ("S", "gt", "perm", "D_lu", "Dinv", "B", "ext_idx", "int_idx", "n")
+    __slots__ = ("S", "gt", "perm", "D_lu", "Dinv", "B", "ext_idx", "int_idx", "n", "cond1")
 
 
 def _child_index_sets(d: int, n: int):
@@ -409,6 +409,10 @@ def merge(d, T, h, n, with_T=True, d_inverse="lu"):
     D_lu, Dinv = None, None
     if d_inverse == "lu":
         D_lu = sla.lu_factor(D)                   # "Invert D"
+        # reciprocal 1-norm condition estimate of D from its LU factors
+        # (LAPACK gecon): DtN merges of Helmholtz operators can be ill
+        # conditioned near interior resonances (Section 2, related work)
+        rcond1 = sla.lapack.dgecon(D_lu[0], np.linalg.norm(D, 1), norm="1")[0]
         S = -sla.lu_solve(D_lu, C)                # S = -D^{-1} C
         gt = -sla.lu_solve(D_lu, h_int)           # g~ = -D^{-1} h_int
     elif d_inverse == "explicit":
@@ -421,6 +425,7 @@ def merge(d, T, h, n, with_T=True, d_inverse="lu"):
     perm = parent_order(d, n)
     node = MergeNode()
     node.S, node.gt, node.perm, node.D_lu, node.Dinv, node.B, node.n = S, gt, perm, D_lu, Dinv, B, n
+    node.cond1 = (1.0 / rcond1 if rcond1 > 0 else np.inf) if d_inverse == "lu" else np.linalg.cond(D, 1)
     Tp = None
     if with_T:
         T_seg = A + B @ S                         # T = A - B D^{-1} C

@@ -123,3 +123,19 @@ def merge_conditioning(tree, p, coeffs):
         T, h = Tn, hn
         n *= 2 ** (tree.d - 1)
     return out
+
+
+def cond_by_level(op_o):
+    """cond_1(D) of the oracle operator's merges, per tree level (root
+    first) as (m, max, median): the conditioning every parity number of a
+    Helmholtz workload is reported with."""
+    out = []
+    for nodes in op_o.levels:
+        cs = [nd.cond1 for nd in nodes]
+        m = nodes[0].S.shape[0]
+        out.append((m, float(np.max(cs)), float(np.median(cs))))
+    return out
+
+
+def fmt_cond(conds):
+    return ", ".join(f"m={m}: {mx:.1e}/{md:.1e}" for m, mx, md in conds)

@@ -1,11 +1,13 @@
 """GPU parity: the HIP build + solve against the CPU oracle on the same
 seeded inputs (rel. l_inf <= 1e-10 per right-hand side, the solver's stated
 fp64 bar).  Sizes span several tiles, ragged tails, both Gauss-Jordan forms
-(register-resident for D <= 224, blocked above) and the 16-rhs chunking."""
+(register-resident single-workgroup inverse up to D = 112, or up to 224 when
+the batch fills the GPU; blocked above), the block elimination of merge
+matrices above 112 and the 16-rhs chunking."""
 import numpy as np
 import pytest
 
-from gpu_util import oracle_solve, rel_inf, rhs, say, var_coeffs
+from gpu_util import cond_by_level, fmt_cond, oracle_solve, rel_inf, rhs, say, var_coeffs
 from oracle import hps as ohps
 
 pytestmark = pytest.mark.gpu
@@ -105,9 +107,14 @@ def test_parity_helmholtz_full_size():
     dev = torch.device("cuda:0")
     op = hp.build(hp.tree(2, 6), 16, torch.tensor(c, device=dev))
     u = op.solve(torch.tensor(bd, device=dev), torch.tensor(src, device=dev)).cpu().numpy()
+    info = op.level_info()
     op.free()
     op_o = ohps.build(tree, 16, c)
     ref = np.stack([ohps.solve(op_o, bd[r], src[r]) for r in range(16)])
     err = rel_inf(u, ref)
+    # the conditioning of the merges this number was obtained under
+    say(f"[case] cond_1(D) per level (max/median): {fmt_cond(cond_by_level(op_o))}")
+    say("[case] merge-inverse probe residual per level: "
+        + ", ".join(f"m={I['m']}: {I['residual']:.1e} (ns {I['ns_steps']})" for I in info))
     say(f"[case] rel err {err:.3e}")
     assert err < TOL

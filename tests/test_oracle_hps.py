@@ -440,3 +440,26 @@ def test_point_layouts():
     assert np.all(E[:, 0] == 1) and np.all(np.diff(E[:, 1]) > 0)
     assert np.all(N[:, 1] == 1) and np.all(np.diff(N[:, 0]) > 0)
     assert np.all(Wd[:, 0] == -1) and np.all(np.diff(Wd[:, 1]) > 0)
+
+
+def test_merge_condition_estimate():
+    # the oracle's per-merge condition record (LAPACK gecon on the LU
+    # factors) against the exact 1-norm condition number of the same D
+    import workloads as W
+    tree = hps.Tree(2, 2)
+    disc = hps.LeafDisc(2, 10)
+    pts = tree.leaf_points(disc)
+    c, _, _ = W.helmholtz_inputs(pts, tree.root_boundary_points(disc), 9.93, 1)
+    op = hps.build(tree, 10, c)
+    ops = disc.term_ops(tree.leaf_r)
+    Qr = disc.Q / tree.leaf_r
+    T, h = [], []
+    for i in range(tree.n_leaves):
+        lf = hps.leaf_solve(disc, ops, Qr, c[i], None)
+        T.append(lf.T)
+        h.append(lf.h)
+    D = hps.merge_blocks_2d(T[0:4], h[0:4], disc.n_face)[3]
+    exact = np.linalg.cond(D, 1)
+    est = op.levels[1][0].cond1
+    # gecon is a lower bound that is rarely off by more than a factor of 3
+    assert exact / 3.0 <= est <= exact * (1 + 1e-8), (est, exact)

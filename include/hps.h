@@ -154,6 +154,28 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
 int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u,
               int nrhs, int precision, void* stream);
 
+/* Bytes of the static device workspace of hps_solve_noalloc (per GPU). */
+#define HPS_STATIC_WS_BYTES (384ull << 20)
+
+/* Allocation-free fp64 solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and 16-rhs chunking as hps_solve with
+ * precision HPS_FP64, and bitwise the same output, but the solve's working
+ * vectors (boundary data and fluxes of every tree level, leaf particular
+ * solutions, merge interface data, split-K partial products) live in a
+ * static device array of HPS_STATIC_WS_BYTES that the library holds on every
+ * GPU it runs on until the process ends, not in the operator.  The call
+ * allocates nothing (no hipMalloc/hipFree, no hipMemset: what must start at
+ * zero is cleared by a kernel; no stage timing).  The caller passes inputs
+ * and outputs as for hps_solve, on the device the operator was built on.
+ * Returns HPS_EINVAL, with both sizes in the message, if the operator's solve
+ * workspace does not fit the array (for example 2D p = 16 trees deeper than
+ * 6 levels).  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (different streams or
+ * threads) race on it and must be serialized by the caller. */
+int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u,
+                      int nrhs, void* stream);
+
 /* Mixed-precision solve (precision HPS_FP32_REFINED; operator built with
  * HPS_FLAG_FP32_COPY, 2D).  The stored operators are copied to fp32 at build
  * time (leaf LU and Y, merge D^{-1}, S and B's nonzero blocks); the solution

@@ -27,7 +27,7 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
-           "hps_debug_gemm_f32", "hps_level_info")
+           "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc")
 
 
 class HPSError(RuntimeError):
@@ -81,6 +81,7 @@ def lib():
         L.hps_op_footprint.restype = S
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
+        L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
         L.hps_solve_adjoint.argtypes = [P, P, P, P, I, P]
         L.hps_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D), I]
         L.hps_op_bytes.argtypes = [P]
@@ -205,6 +206,17 @@ class Operator:
             out = torch.empty((nrhs, s.n_leaves, s.pts_per_leaf), dtype=torch.float64, device=bdry.device)
         uptr = _dev_ptr(out, "u", (nrhs, s.n_leaves, s.pts_per_leaf))
         _check(lib().hps_solve(self._h, bptr, sptr, uptr, nrhs, precision, _stream_ptr(stream)))
+        return out
+
+    def solve_noalloc(self, bdry, src, out, stream=None):
+        """hps_solve_noalloc: the fp64 solve on the library's static device
+        workspace; `out` must be given (the call allocates nothing)."""
+        s = self.sizes
+        nrhs = bdry.shape[0]
+        bptr = _dev_ptr(bdry, "bdry", (nrhs, s.n_root_bdry))
+        sptr = None if src is None else _dev_ptr(src, "src", (nrhs, s.n_leaves, s.pts_per_leaf))
+        uptr = _dev_ptr(out, "u", (nrhs, s.n_leaves, s.pts_per_leaf))
+        _check(lib().hps_solve_noalloc(self._h, bptr, sptr, uptr, nrhs, _stream_ptr(stream)))
         return out
 
     def solve_adjoint(self, w, lam_src=None, lam_bdry=None, stream=None):

@@ -85,6 +85,8 @@ int probe_reduce_launch(const double* r, long long stride, int m, double inv_xma
                         int* gate, long long nodes, hipStream_t st);
 int gated_copy_launch(double* dst, const double* src, long long n, const int* gate, long long nodes,
                       hipStream_t st);
+int static_ws_ptr(void** out);
+int zero_fill_launch(double* x, long long n, hipStream_t st);
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
@@ -583,6 +585,76 @@ int run_refine(hps_op* op, LevelPlan& P, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// the allocation-free solve: the solve's GEMM descriptors with every pointer
+// into the solve workspace moved to the same offset in the device's static
+// workspace, and split-K partial products placed after it.  Copies take
+// their buffers at launch time and need no second table.
+// ---------------------------------------------------------------------------
+std::vector<const GemmCall*> solve_gemm_calls(hps_op* op) {
+  std::vector<const GemmCall*> calls;
+  if (op->d == 3) calls.push_back(&op->gemmVleaf);
+  calls.push_back(&op->gemmHleaf);
+  for (auto& P : op->levels) {
+    calls.push_back(&P.gemmGt);
+    calls.push_back(&P.gemmHp);
+    calls.push_back(&P.gemmDown);
+  }
+  return calls;
+}
+
+int plan_static_solve(hps_op* op) {
+  op->static_ok = false;
+  void* base = nullptr;
+  HPS_TRY(static_ws_ptr(&base));
+  op->static_base = (char*)base;
+  // split-K parts of the solve's calls, packed after the workspace copy
+  long long part_elems = 0;
+  for (const GemmCall* c : solve_gemm_calls(op))
+    for (int i = 0; i < c->count; ++i) {
+      const GemmGroup& g = op->hgroups[c->first + i];
+      if (g.ksplit > 1)
+        part_elems = std::max(part_elems, g.part_off + (long long)g.batch * g.ksplit * g.M * g.N);
+    }
+  op->static_need = op->ws_bytes + part_elems * (long long)sizeof(double);
+  if (op->static_need > (long long)HPS_STATIC_WS_BYTES) return HPS_OK;  // too large: the entry point says so
+  op->hgroups_static = op->hgroups;
+  auto mv = [op](const double* p) -> double* {
+    const char* c = (const char*)p;
+    if (c >= op->ws_base && c < op->ws_base + op->ws_bytes) return (double*)(op->static_base + (c - op->ws_base));
+    return (double*)p;
+  };
+  double* part0 = (double*)(op->static_base + op->ws_bytes);
+  for (const GemmCall* c : solve_gemm_calls(op))
+    for (int i = 0; i < c->count; ++i) {
+      GemmGroup& g = op->hgroups_static[c->first + i];
+      g.A = mv(g.A);
+      g.B = mv(g.B);
+      g.C = mv(g.C);
+      if (g.C0) g.C0 = mv(g.C0);
+      g.part = g.ksplit > 1 ? part0 + g.part_off : nullptr;
+    }
+  op->static_ok = true;
+  return HPS_OK;
+}
+
+// Buffers and descriptor table one solve runs on: the operator's own
+// workspace, or (allocation-free solve) the static workspace.
+struct SolveCtx {
+  const hps_op* op;
+  const GemmGroup* groups;
+  const char* base;  // where the solve workspace starts
+  double* at(double* p) const {
+    return base == op->ws_base ? p : (double*)(base + ((const char*)p - op->ws_base));
+  }
+};
+
+SolveCtx own_ctx(hps_op* op) { return {op, op->dgroups, op->ws_base}; }
+
+int run_gemm_ctx(const SolveCtx& c, const GemmCall& call, hipStream_t st, int n_override) {
+  return gemm_launch(c.groups + call.first, call.count, call.nblocks, call.nrblocks, call.ta, call.tb, st, n_override);
+}
+
+// ---------------------------------------------------------------------------
 // plan: allocations + every descriptor table
 // ---------------------------------------------------------------------------
 int plan_op(hps_op* op) {
@@ -598,8 +670,7 @@ int plan_op(hps_op* op) {
   if (d == 3) {
     op->Lbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * ni, false);
     op->Rbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * nb, false);
-    op->fint = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
-    if (!op->Lbuf || !op->Rbuf || !op->fint) { set_error("device allocation failed (3D leaf workspace)"); return HPS_ENOMEM; }
+    if (!op->Lbuf || !op->Rbuf) { set_error("device allocation failed (3D leaf workspace)"); return HPS_ENOMEM; }
     HPS_TRY(plan_gj(op, &op->leaf_gj, op->Lbuf, op->LU, ni, nl));
     // Y_int = -L_ii^{-1} (L_ie P);  v = L_ii^{-1} f_int
     add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->Rbuf, (long long)ni * nb, ni, op->Y,
@@ -612,20 +683,43 @@ int plan_op(hps_op* op) {
     set_error("device allocation failed (leaf operators)");
     return HPS_ENOMEM;
   }
-  // solve buffers per tree level
+  // solve workspace, one contiguous block (so that the allocation-free solve
+  // can run the same plans on a copy of it at another address): per tree
+  // level g, h [nodes][NR][nbl]; leaf v [nl][NR][ni]; per merge level
+  // hint, gt, gint [nm][NR][m]
   op->g.assign(L + 1, nullptr);
   op->h.assign(L + 1, nullptr);
   op->nbl.assign(L + 1, 0);
   for (int l = 0; l <= L; ++l) {
-    const long long nodes = 1LL << (d * l);
     const long long side = d == 2 ? (long long)(op->p - 2) << (L - l) : (long long)(op->p - 2) * (op->p - 2) << (2 * (L - l));
     op->nbl[l] = (int)(2 * d * side);
-    op->g[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
-    op->h[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
-    if (!op->g[l] || !op->h[l]) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
   }
-  op->v = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
-  if (!op->v) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+  {
+    auto al = [](long long elems) { return (elems * (long long)sizeof(double) + 255) / 256 * 256; };
+    long long bytes = 0;
+    for (int l = 0; l <= L; ++l) bytes += 2 * al((1LL << (d * l)) * NR * op->nbl[l]);
+    bytes += (d == 3 ? 2 : 1) * al(nl * NR * ni);  // v (and the gathered interior sources in 3D)
+    for (int lev = 0; lev < L; ++lev) {
+      const long long nm = 1LL << (d * lev), m = (long long)G.nint * (op->nbl[lev + 1] / (2 * d));
+      bytes += 3 * al(nm * NR * m);
+    }
+    op->ws_base = (char*)op_alloc(op, (size_t)bytes, false);
+    if (!op->ws_base) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+    op->ws_bytes = bytes;
+    long long cur = 0;
+    op->ws_take = [op, cur, al](long long elems) mutable {
+      double* p = (double*)(op->ws_base + cur);
+      cur += al(elems);
+      return p;
+    };
+  }
+  for (int l = 0; l <= L; ++l) {
+    const long long nodes = 1LL << (d * l);
+    op->g[l] = op->ws_take(nodes * NR * op->nbl[l]);
+    op->h[l] = op->ws_take(nodes * NR * op->nbl[l]);
+  }
+  op->v = op->ws_take(nl * NR * ni);
+  if (d == 3) op->fint = op->ws_take(nl * NR * ni);
   if (d == 3)
     add_gemm(op, {make_group(op->LU, (long long)ni * ni, ni, op->fint, (long long)NR * ni, ni, op->v, (long long)NR * ni,
                              ni, ni, NR, ni, 1.0, 0.0, nl)},
@@ -713,10 +807,10 @@ int plan_op(hps_op* op) {
     P.Dbuf = (double*)op_alloc(op, sizeof(double) * nm * m * m, false);
     const bool formT = lev > 0 || (op->flags & HPS_FLAG_ROOT_T);
     if (formT) P.Tp = (double*)op_alloc(op, sizeof(double) * nm * nbp * nbp, lev == 0);
-    P.hint = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
-    P.gt = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
-    P.gint = (double*)op_alloc(op, sizeof(double) * nm * NR * m, false);
-    if (!P.Z || !P.S || !P.Bnz || !P.Dbuf || (formT && !P.Tp) || !P.hint || !P.gt || !P.gint) {
+    P.hint = op->ws_take(nm * NR * m);
+    P.gt = op->ws_take(nm * NR * m);
+    P.gint = op->ws_take(nm * NR * m);
+    if (!P.Z || !P.S || !P.Bnz || !P.Dbuf || (formT && !P.Tp)) {
       set_error("device allocation failed (merge level)");
       return HPS_ENOMEM;
     }
@@ -908,6 +1002,7 @@ int plan_op(hps_op* op) {
     if (!op->splitws) { set_error("device allocation failed (split-K workspace)"); return HPS_ENOMEM; }
   }
   for (auto& g : op->hgroups) g.part = g.ksplit > 1 ? op->splitws + g.part_off : nullptr;
+  HPS_TRY(plan_static_solve(op));
   // upload descriptor tables
   op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
   op->dops = (BlockOp*)op_alloc(op, sizeof(BlockOp) * std::max<size_t>(1, op->hops.size()), false);
@@ -921,6 +1016,12 @@ int plan_op(hps_op* op) {
   HPS_HIP_TRY(hipMemcpy(op->dtasks, op->htasks.data(), sizeof(CopyTask) * op->htasks.size(), hipMemcpyHostToDevice));
   HPS_HIP_TRY(hipMemcpy(op->dgroups, op->hgroups.data(), sizeof(GemmGroup) * op->hgroups.size(), hipMemcpyHostToDevice));
   HPS_HIP_TRY(hipMemcpy(op->dops, op->hops.data(), sizeof(BlockOp) * op->hops.size(), hipMemcpyHostToDevice));
+  if (op->static_ok) {
+    op->dgroups_static = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * op->hgroups_static.size(), false);
+    if (!op->dgroups_static) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
+    HPS_HIP_TRY(hipMemcpy(op->dgroups_static, op->hgroups_static.data(), sizeof(GemmGroup) * op->hgroups_static.size(),
+                          hipMemcpyHostToDevice));
+  }
   return HPS_OK;
 }
 
@@ -1016,42 +1117,46 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
   return HPS_OK;
 }
 
-int run_solve_chunk(hps_op* op, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st) {
+int run_solve_chunk(hps_op* op, const SolveCtx& c, const double* bdry, const double* src, double* u, int nrhs,
+                    bool graph_safe, hipStream_t st) {
   const int L = op->tree.depth, nd = op->nd, NR = op->NR;
-  stage_begin(op, "solve", st);
+  if (!graph_safe) stage_begin(op, "solve", st);
   // root data
-  HPS_TRY(run_copy(op, op->copyRoot, nrhs, op->g[0], 0, bdry, 0, nullptr, 0, 1, st));
+  HPS_TRY(run_copy(op, op->copyRoot, nrhs, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st));
   if (src) {
     if (op->d == 2) {
-      HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, op->v, NR,
-                              st));
+      HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, c.at(op->v),
+                              NR, st));
     } else {
-      HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, op->fint, st));
-      HPS_TRY(run_gemm(op, op->gemmVleaf, st, nrhs));
+      HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
+      HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
     }
-    HPS_TRY(run_gemm(op, op->gemmHleaf, st, nrhs));
+    HPS_TRY(run_gemm_ctx(c, op->gemmHleaf, st, nrhs));
     for (int lev = L - 1; lev >= 0; --lev) {
       LevelPlan& P = op->levels[lev];
-      HPS_TRY(run_copy(op, P.copyHint, nrhs, P.hint, (long long)NR * P.m, op->h[lev + 1], (long long)nd * NR * P.nbc,
-                       nullptr, 0, P.nm, st));
-      HPS_TRY(run_gemm(op, P.gemmGt, st, nrhs));
-      if (lev > 0) HPS_TRY(run_gemm(op, P.gemmHp, st, nrhs));
+      HPS_TRY(run_copy(op, P.copyHint, nrhs, c.at(P.hint), (long long)NR * P.m, c.at(op->h[lev + 1]),
+                       (long long)nd * NR * P.nbc, nullptr, 0, P.nm, st));
+      HPS_TRY(run_gemm_ctx(c, P.gemmGt, st, nrhs));
+      if (lev > 0) HPS_TRY(run_gemm_ctx(c, P.gemmHp, st, nrhs));
     }
   } else {
     for (int lev = 0; lev < L; ++lev) {
       LevelPlan& P = op->levels[lev];
-      HPS_HIP_TRY(hipMemsetAsync(P.gt, 0, sizeof(double) * P.nm * NR * P.m, st));
+      if (graph_safe)
+        HPS_TRY(zero_fill_launch(c.at(P.gt), P.nm * NR * P.m, st));
+      else
+        HPS_HIP_TRY(hipMemsetAsync(P.gt, 0, sizeof(double) * P.nm * NR * P.m, st));
     }
   }
   for (int lev = 0; lev < L; ++lev) {
     LevelPlan& P = op->levels[lev];
-    HPS_TRY(run_gemm(op, P.gemmDown, st, nrhs));
-    HPS_TRY(run_copy(op, P.copyGchild, nrhs, op->g[lev + 1], (long long)nd * NR * P.nbc, op->g[lev],
-                     (long long)NR * P.nbp, P.gint, (long long)NR * P.m, P.nm, st));
+    HPS_TRY(run_gemm_ctx(c, P.gemmDown, st, nrhs));
+    HPS_TRY(run_copy(op, P.copyGchild, nrhs, c.at(op->g[lev + 1]), (long long)nd * NR * P.nbc, c.at(op->g[lev]),
+                     (long long)NR * P.nbp, c.at(P.gint), (long long)NR * P.m, P.nm, st));
   }
-  HPS_TRY(leaf_out_launch(op->Y, op->cst->P, op->g[L], src ? op->v : nullptr, op->cst->Ii, op->cst->Ie, op->ni,
-                          op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st));
-  stage_end(op, st);
+  HPS_TRY(leaf_out_launch(op->Y, op->cst->P, c.at(op->g[L]), src ? c.at(op->v) : nullptr, op->cst->Ii, op->cst->Ie,
+                          op->ni, op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st));
+  if (!graph_safe) stage_end(op, st);
   return HPS_OK;
 }
 
@@ -1480,7 +1585,33 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
     if (precision == HPS_FP32_REFINED)
       HPS_TRY(run_solve_refined_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
     else
-      HPS_TRY(run_solve_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+      HPS_TRY(run_solve_chunk(op, own_ctx(op), bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k,
+                              false, st));
+  }
+  return HPS_OK;
+}
+
+int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, void* stream) {
+  if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
+  if (!op->static_ok) {
+    char buf[200];
+    std::snprintf(buf, sizeof(buf),
+                  "solve workspace of this operator (%.1f MiB) exceeds the static workspace (%.1f MiB)",
+                  (double)op->static_need / 1048576.0, (double)HPS_STATIC_WS_BYTES / 1048576.0);
+    set_error(buf);
+    return HPS_EINVAL;
+  }
+  hipError_t pending = hipGetLastError();
+  if (pending != hipSuccess) {
+    set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
+    return HPS_EDEVICE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const SolveCtx c{op, op->dgroups_static, op->static_base};
+  const long long nbr = op->nbl[0], field = op->nl * op->npts;
+  for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
+    const int k = std::min(op->NR, nrhs - r0);
+    HPS_TRY(run_solve_chunk(op, c, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, true, st));
   }
   return HPS_OK;
 }

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <vector>
 
 #include "../../include/hps.h"
@@ -111,6 +112,18 @@ struct hps_op {
   hps::GemmCall gemmYleaf, gemmVleaf;
   int *perm = nullptr, *pos = nullptr, *flag = nullptr;
   std::vector<hps::LevelPlan> levels;  // index = tree level of the parents
+  // solve workspace: one block holding g, h, v (3D: fint) and every level's
+  // hint, gt, gint; ws_take hands out its pieces in plan order
+  char* ws_base = nullptr;
+  long long ws_bytes = 0;
+  std::function<double*(long long)> ws_take;
+  // allocation-free solve: the solve's GEMM descriptors rebased onto the
+  // device's static workspace (static_ok when ws + split-K parts fit in it)
+  bool static_ok = false;
+  char* static_base = nullptr;
+  long long static_need = 0;
+  std::vector<hps::GemmGroup> hgroups_static;
+  hps::GemmGroup* dgroups_static = nullptr;
   std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
   std::vector<int> nbl;                // boundary size per tree level
   double* v = nullptr;                 // [nl][NR][ni]

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/hps.h"
+#include "../../include/hps_test.h"
 #include "common.hpp"
 #include "op.hpp"
 #include "precompute.hpp"

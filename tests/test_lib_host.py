@@ -1,5 +1,5 @@
 """Host-side checks of the C library (no GPU): it loads, exports every
-symbol include/hps.h declares, its host precompute and point layouts agree
+symbol include/*.h declares, its host precompute and point layouts agree
 with the oracle, and invalid arguments are rejected."""
 import ctypes
 import os
@@ -11,11 +11,11 @@ import pytest
 import paper_2503_17535_amd as hp
 from oracle import hps as ohps
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hps.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
 
 
 def _declared():
-    txt = open(HEADER).read()
+    txt = "".join(open(os.path.join(INCLUDE, f)).read() for f in sorted(os.listdir(INCLUDE)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(hps_[a-z_0-9]+)\s*\(", txt)))
 
 

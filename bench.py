@@ -13,6 +13,12 @@ source pass + downward pass) + release of the operator.  ``value`` is leaves
 per second of whole steps; build-only leaves/s and solves/s are reported
 beside it from HIP events on the stream the library runs on.
 
+Beside the headline line: the roofline of the leaf kernel (dominant), of the
+solve (HBM) and per merge level (FP64); the mixed-precision solve; the small
+2D Poisson latency, the 3D div-grad build/solve with its peak device memory,
+the 32-field misfit gradient, continuous-batching serving; and the CPU oracle
+on the full workload, whose solution gives every GPU path's error.
+
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
 from __future__ import annotations
@@ -20,6 +26,8 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -42,35 +50,116 @@ def leaf_flops(p: int) -> float:
     return (2.0 / 3.0) * ni ** 3 + 2.0 * ni * ni * nb
 
 
-def cpu_baseline(seconds_budget: float = 30.0):
-    """The oracle (plain NumPy/SciPy) on a bounded sample of the workload:
-    one quadrant subtree of depth 5 (1024 leaves, same p, k and inputs), build
-    + 16 solves, scaled to leaves/s."""
+def merge_levels_2d(depth: int, p: int):
+    """(level, nodes, m, flops) of the 2D merges: the explicit inverse of D
+    (2 m^3), S = -D^{-1} C (2 m^3: C's zero blocks skipped) and, below the
+    root, T = A + B S (4 m^3: B's zero blocks skipped).  The accuracy guard's
+    Newton-Schulz steps are extra work and not counted."""
+    q = p - 2
+    out = []
+    for lev in range(depth - 1, -1, -1):
+        nodes = 4 ** lev
+        m = 4 * q * 2 ** (depth - 1 - lev)
+        per = 2.0 * m ** 3 + 2.0 * m ** 3 + (4.0 * m ** 3 if lev > 0 else 0.0)
+        out.append((lev, nodes, m, nodes * per))
+    return out
+
+
+def solve_bytes_2d(depth: int, p: int, nrhs: int, with_src: bool = True) -> float:
+    """Algorithmic HBM bytes of one solve pass over nrhs right-hand sides:
+    every stored operator read once (leaf LU factors when a source is given,
+    Y_int; per merge D^{-1}, S and the nonzero blocks of B), the source read
+    and the solution written."""
+    q = p - 2
+    nl, ni, nb, npts = 4 ** depth, q * q, 4 * q, p * p
+    b = nl * ni * nb * 8.0 + (nl * ni * ni * 8.0 if with_src else 0.0)
+    for lev, nodes, m, _ in merge_levels_2d(depth, p):
+        b += nodes * (m * m + m * 2 * m + m * m) * 8.0     # Z, S (m x 2m), 4 blocks (m/2)^2 of B
+    b += nrhs * nl * npts * 8.0 * (2 if with_src else 1)
+    return b
+
+
+def host_info():
+    info = {"os_cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "machine": platform.machine()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except Exception:  # pragma: no cover
+        pass
+    return info
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(coeffs, bdry, src):
+    """The oracle (plain NumPy/SciPy, LAPACK on the host's cores) on the full
+    workload: build + 16 solves, once.  Returns the record and the oracle's
+    solution (every GPU path's error is taken against it).  A 256-leaf
+    subtree is timed with all threads and with one beside it."""
     import numpy as np
     import workloads as W
     from oracle import hps as ohps
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    depth = DEPTH - 1
-    tree = ohps.Tree(2, depth, -1.0, 0.0)          # the SW quadrant of [-1,1]^2
-    disc = ohps.LeafDisc(2, P)
-    pts = tree.leaf_points(disc)
-    bpts = tree.root_boundary_points(disc)
-    c, bd, src = W.helmholtz_inputs(pts, bpts, K_WAVE, NRHS)
+    tree = ohps.Tree(2, DEPTH)
     t0 = time.perf_counter()
-    op = ohps.build(tree, P, c)
+    op = ohps.build(tree, P, coeffs)
     t1 = time.perf_counter()
-    for r in range(NRHS):
-        ohps.solve(op, bd[r], src[r])
+    ref = np.stack([ohps.solve(op, bdry[r], src[r]) for r in range(NRHS)])
     t2 = time.perf_counter()
+    del op
     nl = tree.n_leaves
-    return {"value": nl / (t2 - t0), "unit": "leaves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle build + {NRHS} solves of one depth-{depth} quadrant subtree "
-                      f"({nl} leaves, p={P}, k={K_WAVE:g}); build {t1 - t0:.2f}s, solves {t2 - t1:.2f}s",
-            "build_leaves_per_s": nl / (t1 - t0), "solves_per_s": NRHS / (t2 - t1)}
+    rec = {"value": nl / (t2 - t0), "unit": "leaves/s", "cores": int(blas_threads()), "kind": "oracle",
+           "sample": f"the full workload once: oracle build of all {nl} leaves (p={P}, k={K_WAVE:g}) + {NRHS} "
+                     f"solves; build {t1 - t0:.2f}s, solves {t2 - t1:.2f}s",
+           "build_leaves_per_s": nl / (t1 - t0), "solves_per_s": NRHS / (t2 - t1), "host": host_info()}
+    try:
+        # the same 256-leaf quadrant subtree (depth 4, same inputs) with all
+        # threads and with one, so that the two figures compare like with like
+        from threadpoolctl import threadpool_limits
+        sub = ohps.Tree(2, 4, -1.0, -0.5)
+        disc = ohps.LeafDisc(2, P)
+        pts = sub.leaf_points(disc)
+        c1, b1, s1 = W.helmholtz_inputs(pts, sub.root_boundary_points(disc), K_WAVE, 1)
+
+        def timed():
+            t0 = time.perf_counter()
+            o1 = ohps.build(sub, P, c1)
+            t1 = time.perf_counter()
+            ohps.solve(o1, b1[0], s1[0])
+            return sub.n_leaves / (t1 - t0), time.perf_counter() - t1
+        all_b, all_s = timed()
+        with threadpool_limits(1):
+            one_b, one_s = timed()
+        rec["subtree"] = {"sample": f"build of a {sub.n_leaves}-leaf subtree (depth 4) + 1 solve",
+                          "threads": int(blas_threads()), "build_leaves_per_s": all_b, "solve_s": all_s,
+                          "one_thread_build_leaves_per_s": one_b, "one_thread_solve_s": one_s}
+    except Exception as e:  # pragma: no cover
+        rec["subtree"] = {"error": str(e)}
+    return rec, ref
+
+
+def _median_ms(fn, reps=5):
+    import numpy as np
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
 
 
 def _leaf_source_hash():
@@ -98,24 +187,14 @@ def measured_traffic():
     return None
 
 
-def _median_ms(fn, reps=5):
+def rel_err(u, ref):
     import numpy as np
-    import torch
-    ts = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        fn()
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    return float(np.median(ts))
+    return float(max(np.abs(u[r] - ref[r]).max() / np.abs(ref[r]).max() for r in range(ref.shape[0])))
 
 
-def solve_rates(hp, t, c_d, b_d, s_d, sz):
+def solve_rates(hp, t, c_d, b_d, s_d):
     """Solve-only rates of one resident operator: 16 and 1 right-hand sides
-    (median of 5 after a warm-up)."""
+    (median of 5 after a warm-up), and the solve's HBM roofline."""
     op = hp.build(t, P, c_d)
     u16 = op.solve(b_d, s_d)
     ms16 = _median_ms(lambda: op.solve(b_d, s_d, out=u16))
@@ -123,14 +202,17 @@ def solve_rates(hp, t, c_d, b_d, s_d, sz):
     u1 = op.solve(b1, s1)
     ms1 = _median_ms(lambda: op.solve(b1, s1, out=u1))
     op.free()
+    by = solve_bytes_2d(DEPTH, P, NRHS)
+    gbs = by / (ms16 * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "algorithmic_bytes": by, "ms": ms16}
     return {"solve16_ms": ms16, "solves_per_s_nrhs16": NRHS * 1e3 / ms16,
-            "solve1_ms": ms1, "solves_per_s_nrhs1": 1e3 / ms1}
+            "solve1_ms": ms1, "solves_per_s_nrhs1": 1e3 / ms1}, roof, u16
 
 
 def refined_solve(hp, t, c_d, b_d, s_d):
     """Mixed-precision solve of the same workload (fp32 operator copies, fp64
-    residual refinement): time and the max relative difference to the fp64
-    solve of the same operator (the tests check both against the oracle)."""
+    residual refinement)."""
     import torch
     op = hp.build(t, P, c_d, flags=hp.FLAG_FP32_COPY)
     u64 = op.solve(b_d, s_d)
@@ -141,7 +223,148 @@ def refined_solve(hp, t, c_d, b_d, s_d):
     op.free()
     torch.cuda.synchronize()
     return {"sweeps": sweeps, "solve16_ms": ms, "solves_per_s": NRHS * 1e3 / ms,
-            "max_rel_diff_to_fp64": diff}
+            "max_rel_diff_to_fp64": diff}, u
+
+
+def poisson_latency(hp, W):
+    """Small 2D Poisson: -Lap u = 2 pi^2 sin(pi x) sin(pi y), depth 2 (16
+    leaves), p = 8: build + 1 solve latency (too small for either roofline)."""
+    import numpy as np
+    import torch
+    t = hp.tree(2, 2)
+    pts = hp.leaf_points(t, 8)
+    bpts = hp.boundary_points(t, 8)
+    c = torch.tensor(W.coeffs_poisson(pts), device="cuda:0")
+    g = torch.tensor(W.sinsin(bpts)[None], device="cuda:0")
+    f = torch.tensor(W.sinsin_minus_laplacian(pts)[None], device="cuda:0")
+    u = torch.empty((1, 16, 64), dtype=torch.float64, device="cuda:0")
+
+    def once():
+        op = hp.build(t, 8, c)
+        op.solve(g, f, out=u)
+        op.free()
+    for _ in range(3):
+        once()
+    torch.cuda.synchronize()
+    wall = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        once()
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e3)
+    err = float(np.abs(u[0].cpu().numpy() - W.sinsin(pts)).max())
+    return {"workload": "2D Poisson depth 2 (16 leaves), p=8, sin(pi x) sin(pi y)",
+            "build_solve_latency_ms_p50": float(np.median(wall)), "p99_ms": float(np.percentile(wall, 99)),
+            "abs_err_vs_exact": err}
+
+
+def divgrad_3d(hp, W):
+    """3D variable-coefficient Poisson div(a grad u) = f, a = 1 + 0.5 sin
+    product, octree depth 3 (512 leaves), p = 12, 10x10 Gauss face nodes;
+    manufactured u = sin sin sin + xyz.  Build and one solve, device times,
+    and the library's peak device memory over build + solve."""
+    import numpy as np
+    import torch
+    p, L = 12, 3
+    t = hp.tree(3, L)
+    pts = hp.leaf_points(t, p)
+    bpts = hp.boundary_points(t, p)
+    prm = W.draw_sinprod(W.rng(3, 0))
+    c = torch.tensor(W.coeffs_divgrad(pts, prm), device="cuda:0")
+    a, ga = W.eval_sinprod(prm, pts)
+    ue, gu, lap = W.sin3_plus_xyz(pts)
+    g = torch.tensor(W.sin3_plus_xyz(bpts)[0][None], device="cuda:0")
+    f = torch.tensor((a * lap + np.sum(ga * gu, axis=-1))[None], device="cuda:0")
+    torch.cuda.synchronize()
+    base, _ = hp.mem_stats(reset_peak=True)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    op = hp.build(t, p, c)
+    e[1].record()
+    u = op.solve(g, f)
+    e[2].record()
+    e[2].synchronize()
+    _, peak = hp.mem_stats()
+    resident = op.nbytes
+    ms_solve = _median_ms(lambda: op.solve(g, f, out=u), reps=3)
+    op.free()
+    err = float(np.abs(u[0].cpu().numpy() - ue).max() / np.abs(ue).max())
+    return {"workload": "3D div(a grad u) = f, octree depth 3 (512 leaves), p=12, root D 19200",
+            "build_ms": e[0].elapsed_time(e[1]), "solve_ms": ms_solve, "first_solve_ms": e[1].elapsed_time(e[2]),
+            "build_leaves_per_s": 512 * 1e3 / e[0].elapsed_time(e[1]),
+            "peak_device_GB": (peak - base) / 1e9, "resident_GB": resident / 1e9,
+            "rel_err_vs_manufactured": err}
+
+
+def misfit_gradients(hp, W, with_oracle: bool):
+    """Misfit gradient workload: J(q) = ||E u(q) - u_obs||^2 at 256 points,
+    2D Helmholtz k = 20, depth 5, p = 16, 32 seeded fields q: per field a
+    build, a solve, the adjoint solve and the coefficient gradient (through
+    torch.autograd).  Time for all 32, and the error of field 0's gradient
+    against the oracle's adjoint gradient."""
+    import numpy as np
+    import torch
+    from paper_2503_17535_amd.autograd import solve as hsolve
+    d, p, L = 2, 16, 5
+    dev = torch.device("cuda:0")
+    t = hp.tree(d, L)
+    pts = hp.leaf_points(t, p)
+    bpts = hp.boundary_points(t, p)
+    inp = W.differentiation_inputs(pts, bpts)
+    k = inp["k"]
+    bd = torch.tensor(inp["bdry"], device=dev)
+    src = torch.tensor(inp["src"], device=dev)
+    leaf, wts = hp.interp_weights(t, p, inp["x_obs"])
+    leaf_t, wts_t = torch.tensor(leaf, device=dev), torch.tensor(wts, device=dev)
+
+    def coeffs(q):
+        nl, npts = q.shape
+        c = torch.zeros((nl, 5, npts), dtype=torch.float64, device=dev)
+        c[:, 0] = -1.0
+        c[:, 2] = -1.0
+        return torch.cat([c, (-(k * k) * (1.0 + q))[:, None]], dim=1)
+
+    def observe(u):
+        return (wts_t * u[0, leaf_t, :]).sum(-1)
+
+    with torch.no_grad():
+        u_obs = observe(hsolve(t, p, coeffs(torch.tensor(inp["q_star"], device=dev)), bd, src))
+    qs = [torch.tensor(inp["q"][f], device=dev, requires_grad=True) for f in range(inp["q"].shape[0])]
+
+    def run():
+        grads = []
+        for q in qs:
+            q.grad = None
+            u = hsolve(t, p, coeffs(q), bd, src)
+            ((observe(u) - u_obs) ** 2).sum().backward()
+            grads.append(q.grad)
+        return grads
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grads = run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = {"workload": "misfit gradient, 2D Helmholtz k=20, depth 5 (1024 leaves), p=16, 256 points, 32 fields",
+           "fields": len(qs), "total_ms": wall * 1e3, "ms_per_field": wall * 1e3 / len(qs),
+           "gradients_per_s": len(qs) / wall}
+    if with_oracle:
+        from oracle import adjoint as A
+        from oracle import hps as ohps
+        tree = ohps.Tree(d, L)
+        disc = ohps.LeafDisc(d, p)
+        opts = tree.leaf_points(disc)
+        op_s = ohps.build(tree, p, W.coeffs_helmholtz(opts, k, inp["q_star"]))
+        oleaf, oW = A.observation(tree, p, inp["x_obs"])
+        uo_obs = np.einsum("mk,mk->m", oW, ohps.solve(op_s, inp["bdry"][0], inp["src"][0])[oleaf])
+        del op_s
+        op0 = ohps.build(tree, p, W.coeffs_helmholtz(opts, k, inp["q"][0]))
+        u0 = ohps.solve(op0, inp["bdry"][0], inp["src"][0])
+        lam0, _ = A.hps_adjoint(op0, A.misfit_weight(u0, oleaf, oW, uo_obs))
+        ref = -(k * k) * A.coeff_grad(tree, p, u0[None], lam0[None])[:, 5]
+        g0 = grads[0].cpu().numpy()
+        rec["field0_rel_err_vs_oracle"] = float(np.abs(g0 - ref).max() / np.abs(ref).max())
+    return rec
 
 
 def serving(hp, W, n_req=4096, rate=2000.0, pool=4):
@@ -190,6 +413,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline workload (no 2D Poisson, 3D or misfit-gradient legs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +494,12 @@ def main():
     roofline = {"kernel": "leaf2d_factor_kernel<16>", "bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": measured_traffic(), "algorithmic_flops_per_launch": flops, "avg_launch_ms": leaf_ms}
+    merge_roof = []
+    for lev, nodes, m, fl in merge_levels_2d(DEPTH, P):
+        ms = stages.get(f"merge_l{lev}", float("nan"))
+        tf = fl / (ms * 1e-3) / 1e12
+        merge_roof.append({"level": lev, "nodes": nodes, "m": m, "gflop": fl / 1e9, "ms": ms, "tflops": tf,
+                           "frac": tf / PEAK_FP64_TFLOPS})
 
     out = {
         "metric": METRIC,
@@ -286,13 +517,24 @@ def main():
         "solves_per_s": NRHS * 1e3 / solve_ms,
         "stages_ms": stages,
         "roofline": roofline,
+        "roofline_merge_levels": merge_roof,
     }
-    out.update(solve_rates(hp, t, c_d, b_d, s_d, sz))
-    out["refined"] = refined_solve(hp, t, c_d, b_d, s_d)
+    rates, roof_solve, u64 = solve_rates(hp, t, c_d, b_d, s_d)
+    out.update(rates)
+    out["roofline_solve"] = roof_solve
+    out["refined"], u_ref32 = refined_solve(hp, t, c_d, b_d, s_d)
+    if not args.no_extra:
+        out["poisson2d_latency"] = poisson_latency(hp, W)
+        out["divgrad3d"] = divgrad_3d(hp, W)
+        out["misfit_gradient"] = misfit_gradients(hp, W, with_oracle=not args.no_cpu_baseline)
     if not args.no_serving:
         out["serving"] = serving(hp, W)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        rec, ref = cpu_baseline(coeffs, bdry, src)
+        out["cpu_baseline"] = rec
+        out["rel_err_vs_oracle"] = {"fp64_step": rel_err(u_d.cpu().numpy(), ref),
+                                    "fp64_solve": rel_err(u64.cpu().numpy(), ref),
+                                    "fp32_refined": rel_err(u_ref32.cpu().numpy(), ref)}
     print(json.dumps(out), flush=True)
 
 

@@ -265,6 +265,14 @@ int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap);
 /* Resident device bytes of a built operator. */
 size_t hps_op_bytes(const hps_op_t* op);
 
+/* Device memory of the library (all operators and their build workspaces,
+ * the peak memory the paper reports for 3D trees, Section 4): bytes currently
+ * handed out (in_use) and
+ * their high-water mark since the last reset (peak); either may be NULL.
+ * reset_peak != 0 sets the mark to the current use after reading it.  Freed
+ * blocks the library keeps cached for later builds are not counted. */
+void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak);
+
 /* Release the operator and its device memory (after its queued work). */
 void hps_free(hps_op_t* op);
 

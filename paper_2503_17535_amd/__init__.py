@@ -27,7 +27,7 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
-           "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc")
+           "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats")
 
 
 class HPSError(RuntimeError):
@@ -82,6 +82,8 @@ def lib():
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
         L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
+        L.hps_mem_stats.argtypes = [ctypes.POINTER(S), ctypes.POINTER(S), I]
+        L.hps_mem_stats.restype = None
         L.hps_solve_adjoint.argtypes = [P, P, P, P, I, P]
         L.hps_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(D), I]
         L.hps_op_bytes.argtypes = [P]
@@ -105,12 +107,20 @@ def lib():
         L.hps_level_info.argtypes = [P, ctypes.POINTER(LevelInfo), I]
         for name in EXPORTS:
             if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error", "hps_batcher_free",
+                            "hps_mem_stats",
                             "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def mem_stats(reset_peak: bool = False) -> tuple[int, int]:
+    """(bytes in use, high-water mark) of the library's device memory."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    lib().hps_mem_stats(ctypes.byref(a), ctypes.byref(b), int(reset_peak))
+    return a.value, b.value
 
 
 def _check(rc):

@@ -101,7 +101,15 @@ namespace {
 std::mutex g_pool_mu;
 std::multimap<size_t, void*> g_pool_free;
 
+// bytes handed out by dalloc and not returned, and their high-water mark
+size_t g_in_use = 0, g_peak = 0;
+
 size_t round_size(size_t b) { return (b + 4095) & ~(size_t)4095; }
+
+void count_out(size_t bytes) {
+  g_in_use += bytes;
+  if (g_in_use > g_peak) g_peak = g_in_use;
+}
 
 void* dalloc(size_t bytes) {
   bytes = round_size(bytes ? bytes : 1);
@@ -111,6 +119,7 @@ void* dalloc(size_t bytes) {
     if (it != g_pool_free.end()) {
       void* p = it->second;
       g_pool_free.erase(it);
+      count_out(bytes);
       return p;
     }
   }
@@ -126,13 +135,17 @@ void* dalloc(size_t bytes) {
       return nullptr;
     }
   }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  count_out(bytes);
   return p;
 }
 
 void dfree(void* p, size_t bytes) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  g_pool_free.emplace(round_size(bytes ? bytes : 1), p);
+  const size_t b = round_size(bytes ? bytes : 1);
+  g_in_use -= b;
+  g_pool_free.emplace(b, p);
 }
 
 // device copies of the precomputed leaf operators, per (d, p, leaf half-width)
@@ -1482,6 +1495,13 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags) {
 }
 
 size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident : 0; }
+
+void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (in_use) *in_use = g_in_use;
+  if (peak) *peak = g_peak;
+  if (reset_peak) g_peak = g_in_use;
+}
 
 int hps_level_info(hps_op_t* op, hps_level_info_t* out, int cap) {
   if (!op || (cap > 0 && !out)) { set_error("op must be non-NULL (and out when cap > 0)"); return -HPS_EINVAL; }

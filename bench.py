@@ -367,43 +367,84 @@ def misfit_gradients(hp, W, with_oracle: bool):
     return rec
 
 
-def serving(hp, W, n_req=4096, rate=2000.0, pool=4):
-    """Continuous-batching serving: 8 resident Helmholtz operators (depths 4-7,
-    p 12/16, k 10-40), 4096 requests with exponential inter-arrival times at
-    2000/s replayed against the wall clock, each one right-hand side (Fourier
-    boundary data + one source bump) for a uniformly chosen operator; fp64.
-    Latency = device completion - scheduled arrival."""
+def serving(hp, W, n_req=4096, rate=2000.0):
+    """Continuous-batching serving (see paper_2503_17535_amd.serve): 8
+    resident Helmholtz operators (depths 4-7, p 12/16, k 10-40, built with
+    fp32 copies so both precisions run on them), 4096 requests with
+    exponential inter-arrival times at 2000/s replayed against the wall clock,
+    each for a uniformly chosen operator with its own seeded Fourier boundary
+    data and source bump (generated on the device before the run).  Latency =
+    device completion - scheduled arrival.  Runs: fp64 and fp32+fp64
+    refinement at 2000/s, and an fp64 rate sweep on the first 1024 requests."""
     import numpy as np
     import torch
     from paper_2503_17535_amd.serve import Request, Server, latency_stats
     dev = torch.device("cuda:0")
-    ops, pools = [], []
+    ops, pts_d, four = [], [], []
     for k, (L, p, kw) in enumerate(W.SERVING_OPS):
         tt = hp.tree(2, L)
         pts = hp.leaf_points(tt, p)
         bpts = hp.boundary_points(tt, p)
-        c, bd, src = W.helmholtz_inputs(pts, bpts, kw, pool, config=4, op_seed=k)
-        ops.append(hp.build(tt, p, torch.tensor(c, device=dev)))
-        pools.append((torch.tensor(bd, device=dev), torch.tensor(src, device=dev)))
+        c, _, _ = W.helmholtz_inputs(pts, bpts, kw, 1, config=4, op_seed=k)
+        ops.append(hp.build(tt, p, torch.tensor(c, device=dev), flags=hp.FLAG_FP32_COPY))
+        pts_d.append(torch.tensor(pts, device=dev))
+        # Fourier basis in perimeter arclength at this operator's boundary points
+        sarc = W.perimeter_arclength(bpts)
+        m = np.arange(17)[:, None]
+        four.append((torch.tensor(np.cos(2 * np.pi * m * sarc / 8.0), device=dev),
+                     torch.tensor(np.sin(2 * np.pi * m * sarc / 8.0), device=dev)))
     resident = sum(op.nbytes for op in ops)
-    ta, opi, rhs = W.serving_arrivals(n_req, rate, len(ops), pool)
-    # warm-up pass (not measured)
-    warm = [Request(op=i % len(ops), bdry=pools[i % len(ops)][0][0], src=pools[i % len(ops)][1][0],
-                    t_arrival=0.0) for i in range(2 * len(ops))]
-    srv = Server(ops)
-    srv.run(warm)
-    srv.batches.clear()
-    reqs = [Request(op=int(opi[i]), bdry=pools[opi[i]][0][rhs[i]], src=pools[opi[i]][1][rhs[i]],
-                    t_arrival=float(ta[i])) for i in range(n_req)]
-    srv.run(reqs)
+    ta, opi, _ = W.serving_arrivals(n_req, rate, len(ops), 1)
+    data = []
+    for i in range(n_req):
+        fo, sb = W.serving_request_params(i)
+        k = int(opi[i])
+        cb, sn = four[k]
+        bd = torch.tensor(fo["a"], device=dev) @ cb + torch.tensor(fo["b"], device=dev) @ sn
+        z = torch.tensor(sb["centres"][0], device=dev)
+        src = float(sb["amps"][0]) * torch.exp(-((pts_d[k] - z) ** 2).sum(-1) / (2 * 0.1 ** 2))
+        data.append((bd, src))
     torch.cuda.synchronize()
-    st = latency_stats(reqs)
-    st.update({"rate_per_s": rate, "operators": len(ops), "resident_GB": resident / 1e9,
-               "batches": len(srv.batches), "mean_batch": float(np.mean(srv.batches)), "precision": "fp64"})
-    srv.free()
+    solo = []
+    for op in ops:      # one-rhs solve of each operator alone (median of 5)
+        k = ops.index(op)
+        i = int(np.nonzero(opi == k)[0][0])
+        b1, s1 = data[i][0][None].contiguous(), data[i][1][None].contiguous()
+        u1 = op.solve(b1, s1)
+        solo.append(_median_ms(lambda: op.solve(b1, s1, out=u1)))
+
+    def run(prec, r, n):
+        t_a, o_i, _ = W.serving_arrivals(n_req, r, len(ops), 1)
+        srv = Server(ops, precision=prec)
+        warm = [Request(op=k, bdry=data[int(np.nonzero(opi == k)[0][0])][0],
+                        src=data[int(np.nonzero(opi == k)[0][0])][1], t_arrival=0.0) for k in range(len(ops))]
+        srv.run(warm)
+        srv.batches.clear()
+        reqs = [Request(op=int(o_i[i]), bdry=data[i][0], src=data[i][1], t_arrival=float(t_a[i]))
+                for i in range(n)]
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        st = latency_stats(reqs)
+        st.update({"rate_per_s": r, "batches": len(srv.batches), "mean_batch": float(np.mean(srv.batches)),
+                   "precision": prec})
+        srv.free()
+        return st, reqs
+
+    fp64, reqs64 = run("fp64", rate, n_req)
+    ref32, reqs32 = run("fp32_refined", rate, n_req)
+    # largest relative difference of a refined result to the fp64 result of
+    # the same request (both are checked against the oracle in the tests)
+    diff = max(((a.u - b.u).abs().max() / b.u.abs().max()).item() for a, b in zip(reqs32[::64], reqs64[::64]))
+    ref32["max_rel_diff_to_fp64"] = diff
+    del reqs64, reqs32
+    sweep = [run("fp64", r, 1024)[0] for r in (1000.0, 4000.0, 8000.0)]
+    out = dict(fp64)
+    out.update({"operators": len(ops), "resident_GB": resident / 1e9, "classes": "depth <= 5 | 6 | 7",
+                "solo_1rhs_ms": solo, "p99_over_deepest_solo": fp64["p99_ms"] / max(solo),
+                "fp32_refined": ref32, "rate_sweep_fp64": sweep})
     for op in ops:
         op.free()
-    return st
+    return out
 
 
 def main():

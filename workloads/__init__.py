@@ -289,6 +289,14 @@ def differentiation_inputs(leaf_pts: np.ndarray, bdry_pts: np.ndarray, k: float 
 
 
 
+def serving_request_params(i: int, config: int = 4):
+    """Right-hand side of serving request i: its own seeded Fourier boundary
+    series (16 modes, as the Helmholtz workload) and one Gaussian source
+    bump (centre ~ U([-0.75, 0.75]^2), amplitude ~ N(0, 1), width 0.1)."""
+    g = rng(config, 5000 + i)
+    return draw_fourier(g), draw_source_bump(g)
+
+
 def serving_arrivals(n: int = 4096, rate: float = 2000.0, nops: int = 8, pool: int = 8,
                      config: int = 4):
     """Open-loop request stream: exponential inter-arrival times at ``rate``

@@ -105,6 +105,69 @@ __device__ __forceinline__ void leaf2d_stage_aug(double* s_aug, int c0, int nc, 
   }
 }
 
+// Matrix-core helpers of the back substitution: 16 x 16 products on
+// v_mfma_f64_16x16x4f64 (lane l, accumulator element e holds row (l >> 4) + 4e,
+// column l & 15 of the product) and the inverse of a unit triangular block.
+typedef double v4d_l __attribute__((ext_vector_type(4)));
+
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ v4d_l mfma_f64(double a, double b, v4d_l c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Z = X Y for 16 x 16 row-major matrices in LDS, by one wavefront (Z may not
+// alias X or Y).
+__device__ __forceinline__ void mm16(const double (*X)[16], const double (*Yv)[16], double (*Z)[16], int g, int cl) {
+  v4d_l z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) z = mfma_f64(X[cl][4 * c + g], Yv[4 * c + g][cl], z);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Z[g + 4 * e][cl] = z[e];
+  wave_sync();
+}
+
+// (I + N)^{-1} = (I - N)(I + N^2)(I + N^4)(I + N^8) for a strictly
+// triangular 16 x 16 N (N^16 = 0), as six products on the matrix cores by one
+// wavefront.  N is overwritten; work holds three 16 x 16 matrices; the
+// result goes to out.
+__device__ __forceinline__ void tri_inv16(double (*N)[16], double (*work)[16][16], double (*out)[16], int lane) {
+  const int g = lane >> 4, cl = lane & 15;
+  double (*A)[16] = work[0];
+  double (*B)[16] = work[1];
+  double (*Cm)[16] = work[2];
+  // A = I - N, B = I + N^2 (N^2 in Cm)
+  mm16(N, N, Cm, g, cl);
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, m = e & 15;
+    const double d = (i == m) ? 1.0 : 0.0;
+    A[i][m] = d - N[i][m];
+    B[i][m] = d + Cm[i][m];
+  }
+  wave_sync();
+  mm16(A, B, out, g, cl);          // out = (I - N)(I + N^2)
+  mm16(Cm, Cm, N, g, cl);          // N  = N^4
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, m = e & 15;
+    B[i][m] = ((i == m) ? 1.0 : 0.0) + N[i][m];
+  }
+  wave_sync();
+  mm16(out, B, A, g, cl);          // A = ... (I + N^4)
+  mm16(N, N, Cm, g, cl);           // Cm = N^8
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, m = e & 15;
+    B[i][m] = ((i == m) ? 1.0 : 0.0) + Cm[i][m];
+  }
+  wave_sync();
+  mm16(A, B, out, g, cl);          // out = ... (I + N^8)
+}
+
+
 template <int P>
 __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
     const double* __restrict__ coeffs,  // [nl][6][P*P]
@@ -130,6 +193,7 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   __shared__ double s_L0[TC][RI * TR];
   __shared__ double s_aug[C::SAUG > 0 ? NI * C::SAUG : 1];
   __shared__ double s_dinv[NI];
+  __shared__ double s_uinv[(NI + 15) / 16][16][16];  // inverses of the diagonal U blocks
   __shared__ int s_perm[NI], s_pos[RI * TR];
   __shared__ int s_piv[2];
   __shared__ int s_active[6];
@@ -308,61 +372,16 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
   });
   __syncthreads();
 
-  // ---- back substitution of the augmented columns:  U X = (forward-eliminated L_ie P)
-  // After the forward pass slot s holds block RF + s (RF = RJP - 1 rotations);
-  // only NLB slots are live.  Blocked by TC columns: the block's U columns
-  // (entries of rows pivoted before the column, zero elsewhere) are staged in
-  // LDS once; then each column group, whose TR lanes hold every row of its
-  // columns, runs the block's steps on its own with x_k broadcast inside the
-  // group, so a block costs two workgroup barriers instead of one per step.
+  // ---- back substitution of the augmented columns:  U X = Yp, on the matrix cores.
+  // Yp (the forward-eliminated L_ie P) leaves the registers in pivot order
+  // (unknown k = pivot step of its row) into Y, which X then overwrites.
+  // Blocked by 16 unknowns: for block J (last to first)
+  //   X_J = U_JJ^{-1} (Yp_J - sum_{J2 > J} U_{J,J2} X_J2),
+  // the U blocks read from the factor just written, the inverses of the
+  // diagonal blocks formed first, one wavefront per 16 right-hand sides.
   constexpr int RF = RJP - 1;
   constexpr int NLB = (NBLK - RF) < RJ ? (NBLK - RF) : RJ;
-  constexpr int RT = RI * TR;
-  for (int kb = RJP - 1; kb >= 0; --kb) {
-    if (kb < RJP - 1) __syncthreads();  // the previous block's reads are done
-    for (int e = tid; e < TC * RT; e += NT) {
-      const int c = e / RT, row = e % RT, k = kb * TC + c;
-      double u = 0.0;
-      if (k < NI && row < NI) {
-        const int pk = s_pos[row];
-        if (pk < k) u = LUl[(long long)k * NI + pk];  // U part, pivot order
-      }
-      s_L0[c][row] = u;
-    }
-    __syncthreads();
-    const int tlast = (NI - kb * TC) < TC ? (NI - kb * TC) : TC;  // steps in this block
-    int pr_n = s_perm[kb * TC + tlast - 1];
-    double dinv_n = s_dinv[kb * TC + tlast - 1];
-    for (int t = tlast - 1; t >= 0; --t) {
-      const int k = kb * TC + t;
-      const int pr = __builtin_amdgcn_readfirstlane(pr_n);  // uniform
-      const int rip = pr / TR, trp = pr % TR;
-      const double dinv = dinv_n;
-      if (t > 0) {  // the next step's pivot row and reciprocal, ahead of time
-        pr_n = s_perm[k - 1];
-        dinv_n = s_dinv[k - 1];
-      }
-      double x[NLB];
-      // x_k of each live column: the pivot row's entry, scaled, from lane trp;
-      // the uniform register index becomes a scalar branch
-      static_for<0, RI>([&](auto ric) {
-        constexpr int R = decltype(ric)::value;
-        if (R == rip) {
-#pragma unroll
-          for (int s = 0; s < NLB; ++s) {
-            x[s] = __shfl(a[R][s] * dinv, gbase + trp);
-            if (tr == trp) a[R][s] = x[s];
-          }
-        }
-      });
-#pragma unroll
-      for (int s = 0; s < NLB; ++s)
-#pragma unroll
-        for (int ri = 0; ri < RI; ++ri) a[ri][s] -= s_L0[t][tr + TR * ri] * x[s];
-    }
-  }
-
-  // ---- outputs: X row k (unknown k) sits in augmented row perm[k]
+  constexpr int NPB = (NI + 15) / 16;          // blocks of 16 unknowns
   double* Yl = Y + leaf * (long long)NI * NB;
 #pragma unroll
   for (int ri = 0; ri < RI; ++ri) {
@@ -373,7 +392,79 @@ __global__ __launch_bounds__(Leaf2DCfg<P>::NT) void leaf2d_factor_kernel(
     for (int s = 0; s < NLB; ++s) {
       const int col = (RF + s) * TC + tc;
       if (col < NI || col >= NC) continue;
-      Yl[pk + (long long)(col - NI) * NI] = -a[ri][s];
+      Yl[pk + (long long)(col - NI) * NI] = a[ri][s];
+    }
+  }
+  __syncthreads();
+  {
+    // inverses of the diagonal U blocks: U = D (I + N), N = D^{-1}(U - D)
+    // strictly upper, U^{-1} = (I + N)^{-1} D^{-1}; workspaces in s_L0
+    // (a dedicated workspace for small leaves, whose s_L0 is smaller than one)
+    const int lane64 = tid & 63, wv = tid >> 6;
+    constexpr int NWL0 = (TC * RI * TR) / (5 * 256);
+    constexpr int NWI = NWL0 < 1 ? 1 : (NWL0 < NT / 64 ? NWL0 : NT / 64);
+    __shared__ double s_triw[NWL0 < 1 ? 5 * 256 : 1];
+    if (wv < NWI) {
+      double* twb = NWL0 < 1 ? s_triw : &s_L0[0][0] + wv * 5 * 256;
+      double (*tw)[16][16] = reinterpret_cast<double (*)[16][16]>(twb);
+      for (int jb = wv; jb < NPB; jb += NWI) {
+        const int k0 = 16 * jb, npiv = min(16, NI - k0);
+        for (int e = lane64; e < 256; e += 64) {
+          const int i = e >> 4, m = e & 15;
+          double v = 0.0;
+          if (i < m && m < npiv) v = LUl[(long long)(k0 + m) * NI + k0 + i] / LUl[(long long)(k0 + i) * NI + k0 + i];
+          tw[0][i][m] = v;
+        }
+        wave_sync();
+        tri_inv16(tw[0], &tw[1], tw[4], lane64);
+        for (int e = lane64; e < 256; e += 64) {
+          const int i = e >> 4, m = e & 15;
+          const double dinv = m < npiv ? 1.0 / LUl[(long long)(k0 + m) * NI + k0 + m] : 1.0;
+          s_uinv[jb][i][m] = tw[4][i][m] * dinv;
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    constexpr int NBT = (NB + 15) / 16;
+    static_assert(NBT <= NT / 64, "one wavefront per 16 right-hand sides");
+    if (wv < NBT) {
+      const int g = lane64 >> 4, cl = lane64 & 15;
+      const int rhs = 16 * wv + cl;
+      v4d_l X[NPB];
+      static_for<0, NPB>([&](auto jc) {
+        constexpr int J = NPB - 1 - decltype(jc)::value;
+        v4d_l z;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * J + g + 4 * e;
+          z[e] = (k < NI && rhs < NB) ? Yl[(long long)rhs * NI + k] : 0.0;
+        }
+        // this block row's U blocks, all loads issued before the products
+        double ua[NPB > J + 1 ? NPB - J - 1 : 1][4];
+        static_for<J + 1, NPB>([&](auto j2c) {
+          constexpr int J2 = decltype(j2c)::value;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int sc = 16 * J2 + 4 * c + g;
+            ua[J2 - J - 1][c] = (sc < NI && 16 * J + cl < NI) ? -LUl[(long long)sc * NI + 16 * J + cl] : 0.0;
+          }
+        });
+        static_for<J + 1, NPB>([&](auto j2c) {
+          constexpr int J2 = decltype(j2c)::value;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) z = mfma_f64(ua[J2 - J - 1][c], X[J2][c], z);
+        });
+        v4d_l x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x = mfma_f64(s_uinv[J][cl][4 * c + g], z[c], x);
+        X[J] = x;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * J + g + 4 * e;
+          if (k < NI && rhs < NB) Yl[(long long)rhs * NI + k] = -x[e];
+        }
+      });
     }
   }
   for (int i = tid; i < NI; i += NT) {

@@ -296,6 +296,53 @@ def divgrad_3d(hp, W):
             "rel_err_vs_manufactured": err}
 
 
+def subtree_recomputation(hp, W):
+    """2D p = 16 trees of depth 8 and 9 (16.8M and 67.1M unknowns), the sizes
+    of the paper's subtree-recomputation runs: build + one solve with a
+    source (local solves, merges, downward pass: what the paper times) of the
+    resident operator and of the recomputing one (hps_build_subtrees with
+    5- and 6-level subtrees), the library's peak device memory of each, and
+    the error against the problem's exact polynomial solution."""
+    import numpy as np
+    import torch
+    out = []
+    for L, sd in ((8, 5), (9, 6)):
+        p = 16
+        t = hp.tree(2, L)
+        pts = hp.leaf_points(t, p)
+        bpts = hp.boundary_points(t, p)
+        c, f, g, uex = W.poly5_problem(pts, bpts)
+        del pts
+        ct = torch.tensor(c, device="cuda:0")
+        del c
+        ft = torch.tensor(f[None], device="cuda:0")
+        gt = torch.tensor(g[None], device="cuda:0")
+        u = torch.empty_like(ft)
+        scale = np.abs(uex).max()
+        rec = {"depth": L, "p": p, "unknowns": int(4 ** L * p * p), "subtree_depth": sd,
+               "resident_operator_GB": hp.footprint(t, p) / 1e9}
+        for mode in ("resident", "recompute"):
+            torch.cuda.synchronize()
+            base, _ = hp.mem_stats(reset_peak=True)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            op = hp.build_subtrees(t, p, ct, sd) if mode == "recompute" else hp.build(t, p, ct)
+            e[1].record()
+            op.solve(gt, ft, out=u)
+            e[2].record()
+            e[2].synchronize()
+            _, peak = hp.mem_stats()
+            op.free()
+            rec[mode] = {"build_s": e[0].elapsed_time(e[1]) * 1e-3, "solve_s": e[1].elapsed_time(e[2]) * 1e-3,
+                         "total_s": e[0].elapsed_time(e[2]) * 1e-3, "peak_device_GB": (peak - base) / 1e9,
+                         "rel_err_vs_exact": float(np.abs(u[0].cpu().numpy() - uex).max() / scale)}
+        out.append(rec)
+        del ct, ft, gt, u
+        torch.cuda.empty_cache()
+    return {"workload": "2D variable-coefficient problem with a degree-5 polynomial solution, p=16",
+            "runs": out}
+
+
 def misfit_gradients(hp, W, with_oracle: bool):
     """Misfit gradient workload: J(q) = ||E u(q) - u_obs||^2 at 256 points,
     2D Helmholtz k = 20, depth 5, p = 16, 32 seeded fields q: per field a
@@ -455,7 +502,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="only the headline workload (no 2D Poisson, 3D or misfit-gradient legs)")
+                    help="only the headline workload (no 2D Poisson, 3D, misfit-gradient or recomputation legs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -568,6 +615,7 @@ def main():
         out["poisson2d_latency"] = poisson_latency(hp, W)
         out["divgrad3d"] = divgrad_3d(hp, W)
         out["misfit_gradient"] = misfit_gradients(hp, W, with_oracle=not args.no_cpu_baseline)
+        out["subtree_recomputation"] = subtree_recomputation(hp, W)
     if not args.no_serving:
         out["serving"] = serving(hp, W)
     if not args.no_cpu_baseline:

@@ -143,6 +143,39 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags);
 int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
               void* stream, hps_op_t** out);
 
+/* Build with subtree recomputation (Section 4.1, Algorithm "Subtree
+ * recomputation strategy"), for trees whose stored operators exceed the
+ * device memory.  The tree is cut subtree_depth levels above the leaves:
+ * only the merge operators of the top depth - subtree_depth levels stay
+ * resident, together with a device copy of the coefficients and the storage
+ * of ONE subtree (its leaf factors and merges), which is rebuilt from the
+ * coefficients for each subtree in turn.  The build passes over the
+ * subtrees once to obtain the T of every subtree root, then merges the top
+ * levels.  Every hps_solve then rebuilds each subtree, twice when a source is
+ * given (once for the source's outgoing flux at the subtree root, once for
+ * the downward pass from the boundary data the top levels hand down), so a
+ * solve costs about the build of the subtrees plus a solve.
+ *   tree           2D, depth >= 2
+ *   subtree_depth  1 <= subtree_depth < depth
+ *   coeffs, flags, stream, out  as for hps_build; HPS_FLAG_FP32_COPY and
+ *                  HPS_FLAG_ROOT_T are rejected (HPS_EUNSUPPORTED)
+ * The operator serves hps_solve with precision HPS_FP64 (same arguments,
+ * results within rounding of an hps_build operator's: the arithmetic is the
+ * same, only the merge inverses' Newton-Schulz gate and batch-size dependent
+ * kernel choices may differ), hps_solve_adjoint (adjoint checkpointing: the
+ * transposed passes in reverse order, every subtree rebuilt twice, once for
+ * the g of its root and once more before its root-to-leaves part),
+ * hps_coeff_grad, hps_free, hps_op_bytes (top levels + one subtree + the
+ * coefficient copy), hps_level_info (the top levels) and hps_stage_times;
+ * hps_solve_noalloc and hps_solve_batch return HPS_EUNSUPPORTED for it.
+ * Solves and adjoint solves of one such operator rebuild its one subtree
+ * plan: calls on different streams must be serialized by the caller.  The
+ * build checks (see hps_build) run on every subtree and on the top levels;
+ * if any asks for whole-D pivoting the whole build is redone with
+ * HPS_FLAG_FULL_PIVOT, which later solves then use. */
+int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int flags,
+                       int subtree_depth, void* stream, hps_op_t** out);
+
 /* Solve stage (Algorithm down_pass, with the source entering through the
  * linear upward pass of the particular solution, Section 3):
  *   bdry  dev  [nrhs][n_root_bdry]        Dirichlet data g at the root Gauss points

@@ -27,7 +27,8 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_op_bytes", "hps_free", "hps_last_error", "hps_precompute_matrix",
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
-           "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats")
+           "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats",
+           "hps_build_subtrees")
 
 
 class HPSError(RuntimeError):
@@ -80,6 +81,7 @@ def lib():
         L.hps_op_footprint.argtypes = [TP, I, I]
         L.hps_op_footprint.restype = S
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
+        L.hps_build_subtrees.argtypes = [TP, I, P, I, I, P, ctypes.POINTER(P)]
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
         L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
         L.hps_mem_stats.argtypes = [ctypes.POINTER(S), ctypes.POINTER(S), I]
@@ -197,13 +199,18 @@ def _dev_ptr(t, name, shape=None):
 class Operator:
     """A built HPS solution operator, resident in device memory."""
 
-    def __init__(self, t: Tree, p: int, coeffs, flags: int = 0, stream=None):
+    def __init__(self, t: Tree, p: int, coeffs, flags: int = 0, stream=None, subtree_depth: int = 0):
         self.tree, self.p, self.flags = t, p, flags
+        self.subtree_depth = subtree_depth
         self.sizes = sizes(t, p)
         s = self.sizes
         ptr = _dev_ptr(coeffs, "coeffs", (s.n_leaves, s.n_terms, s.pts_per_leaf))
         h = ctypes.c_void_p()
-        _check(lib().hps_build(ctypes.byref(t), p, ptr, flags, _stream_ptr(stream), ctypes.byref(h)))
+        if subtree_depth > 0:
+            _check(lib().hps_build_subtrees(ctypes.byref(t), p, ptr, flags, subtree_depth, _stream_ptr(stream),
+                                            ctypes.byref(h)))
+        else:
+            _check(lib().hps_build(ctypes.byref(t), p, ptr, flags, _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 
     def solve(self, bdry, src=None, out=None, stream=None, precision: int = FP64):
@@ -365,3 +372,11 @@ def debug_gemm(A, B, C, alpha=1.0, beta=0.0, trans_a=False, trans_b=False, strea
 
 def build(t: Tree, p: int, coeffs, flags: int = 0, stream=None) -> Operator:
     return Operator(t, p, coeffs, flags, stream)
+
+
+def build_subtrees(t: Tree, p: int, coeffs, subtree_depth: int, flags: int = 0, stream=None) -> Operator:
+    """hps_build_subtrees: only the top depth - subtree_depth merge levels stay
+    resident; every solve rebuilds the subtrees below them."""
+    if subtree_depth < 1:
+        raise ValueError("subtree_depth must be >= 1")
+    return Operator(t, p, coeffs, flags, stream, subtree_depth=subtree_depth)

@@ -53,9 +53,11 @@ int leaf3d_assemble_launch(const double* coeffs, const double* D1, const double*
 int leaf_gather_int_launch(const double* src, const int* Ii, int ni, int npts, long long nl, int nrhs, int NRcap,
                            double* fint, hipStream_t st);
 int leaf_gather_pts_launch(const double* w, const int* idx, int n, int npts, long long nl, int nrhs, int NRcap,
-                           double* out, hipStream_t st);
+                           double* out, hipStream_t st,
+                           long long rstride = 0);
 int leaf_scatter_int_launch(const double* fint, const int* pos_i, int ni, int npts, long long nl, int nrhs, int NRcap,
-                            double* lam, hipStream_t st);
+                            double* lam, hipStream_t st,
+                            long long rstride = 0);
 int leaf_src_t_launch(const double* LU, const int* perm, const double* b, int NI, long long nl, int nrhs, int NRcap,
                       double* x, hipStream_t st);
 int block_copy_launch_f32(const BlockOp* dev_ops, const CopyItem* dev_items, const CopyTask* dev_tasks, int ntasks,
@@ -79,9 +81,10 @@ int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const C
                       int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
                       const double* src1, long long s1_stride, long long batch, hipStream_t st);
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
-                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st);
+                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride = 0);
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
-                    int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st);
+                    int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st,
+                    long long rstride = 0);
 int probe_reduce_launch(const double* r, long long stride, int m, double inv_xmax, double tau, double* rho,
                         int* gate, long long nodes, hipStream_t st);
 int gated_copy_launch(double* dst, const double* src, long long n, const int* gate, long long nodes,
@@ -383,7 +386,31 @@ void clear_stages(hps_op* op) {
 // ---------------------------------------------------------------------------
 constexpr int kGjSmallAlways = 112;
 
-int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch) {
+long long al256(long long bytes) { return (bytes + 255) / 256 * 256; }
+
+// the next piece of the merge-level build workspace (reset per level)
+void* lvl_take(hps_op* op, long long bytes) {
+  const long long b = al256(bytes);
+  if (!op->lvl_ws || op->lvl_cur + b > op->lvl_ws_bytes) {
+    set_error("merge-level build workspace exhausted (internal sizing error)");
+    return nullptr;
+  }
+  void* p = op->lvl_ws + op->lvl_cur;
+  op->lvl_cur += b;
+  return p;
+}
+
+bool gj_is_small(int m, long long batch) { return m <= kGjSmallAlways || (m <= gj_small_max() && batch >= 256); }
+
+// bytes plan_gj takes from the level workspace for a blocked inverse
+long long gj_ws_bytes(int m, long long batch) {
+  if (gj_is_small(m, batch)) return 0;
+  return 2 * al256((long long)sizeof(int) * batch * m) +
+         al256((long long)sizeof(double) * 2 * batch * m * gj_panel_max_nb());
+}
+
+// level_ws: workspace from the shared merge-level region (else owned by op)
+int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch, bool level_ws = false) {
   g->m = m;
   g->batch = batch;
   g->A = A;
@@ -392,7 +419,7 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
   // the single-workgroup kernel (one CU per matrix) up to kGjSmallAlways, and
   // up to its limit when the batch alone fills the GPU; otherwise the blocked
   // form, whose column updates run on many CUs beside the panel
-  g->small = m <= kGjSmallAlways || (m <= gj_small_max() && batch >= 256);
+  g->small = gj_is_small(m, batch);
   if (g->small) return HPS_OK;
   g->nb = gj_panel_width(m);
   if (g->nb == 0) {
@@ -400,9 +427,10 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch)
     return HPS_EUNSUPPORTED;
   }
   const int mnb = gj_panel_max_nb();
-  g->pos = (int*)op_alloc(op, sizeof(int) * batch * m, false);
-  g->piv = (int*)op_alloc(op, sizeof(int) * batch * m, false);
-  g->W = (double*)op_alloc(op, sizeof(double) * 2 * batch * m * mnb, false);  // two buffers, by panel parity
+  auto take = [&](long long bytes) { return level_ws ? lvl_take(op, bytes) : op_alloc(op, (size_t)bytes, false); };
+  g->pos = (int*)take((long long)sizeof(int) * batch * m);
+  g->piv = (int*)take((long long)sizeof(int) * batch * m);
+  g->W = (double*)take((long long)sizeof(double) * 2 * batch * m * mnb);  // two buffers, by panel parity
   if (!g->pos || !g->piv || !g->W) {
     set_error("device allocation failed (Gauss-Jordan workspace)");
     return HPS_ENOMEM;
@@ -444,18 +472,15 @@ int plan_schur(hps_op* op, LevelPlan& P, int schur_p) {
   P.schur = true;
   P.sP = s;
   P.sR = r;
-  P.Ablk = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * s, false);
-  P.Ainv = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * s, false);
-  P.Xs = (double*)op_alloc(op, sizeof(double) * nm * 2 * s * r, false);
-  P.Ys = (double*)op_alloc(op, sizeof(double) * nm * 2 * r * s, false);
-  P.Sc = (double*)op_alloc(op, sizeof(double) * nm * r * r, false);
-  P.Scinv = (double*)op_alloc(op, sizeof(double) * nm * r * r, false);
-  if (!P.Ablk || !P.Ainv || !P.Xs || !P.Ys || !P.Sc || !P.Scinv) {
-    set_error("device allocation failed (block inversion workspace)");
-    return HPS_ENOMEM;
-  }
-  HPS_TRY(plan_gj(op, &P.gjA, P.Ablk, P.Ainv, s, 2 * nm));
-  HPS_TRY(plan_gj(op, &P.gjS, P.Sc, P.Scinv, r, nm));
+  P.Ablk = (double*)lvl_take(op, sizeof(double) * nm * 2 * s * s);
+  P.Ainv = (double*)lvl_take(op, sizeof(double) * nm * 2 * s * s);
+  P.Xs = (double*)lvl_take(op, sizeof(double) * nm * 2 * s * r);
+  P.Ys = (double*)lvl_take(op, sizeof(double) * nm * 2 * r * s);
+  P.Sc = (double*)lvl_take(op, sizeof(double) * nm * r * r);
+  P.Scinv = (double*)lvl_take(op, sizeof(double) * nm * r * r);
+  if (!P.Ablk || !P.Ainv || !P.Xs || !P.Ys || !P.Sc || !P.Scinv) return HPS_ENOMEM;
+  HPS_TRY(plan_gj(op, &P.gjA, P.Ablk, P.Ainv, s, 2 * nm, true));
+  HPS_TRY(plan_gj(op, &P.gjS, P.Sc, P.Scinv, r, nm, true));
   // a zero pivot inside a block is not a singular D: it goes to its own flag
   // slot, and the checked build then falls back to pivoting over all of D
   P.gjA.flag = P.gjS.flag = op->flag + 1;
@@ -546,8 +571,8 @@ int plan_guard(hps_op* op, LevelPlan& P) {
   const long long nm = P.nm, mm = (long long)m * m;
   const long long mp = (long long)m * kProbes;
   const int ldx = op->probe_ld;
-  P.py = (double*)op_alloc(op, sizeof(double) * nm * mp, false);
-  P.pr = (double*)op_alloc(op, sizeof(double) * nm * mp, false);
+  P.py = (double*)lvl_take(op, sizeof(double) * nm * mp);
+  P.pr = (double*)lvl_take(op, sizeof(double) * nm * mp);
   P.rho = (double*)op_alloc(op, sizeof(double) * (kNsSteps + 1) * nm, false);
   P.gate = (int*)op_alloc(op, sizeof(int) * nm, false);
   if (!P.py || !P.pr || !P.rho || !P.gate) {
@@ -564,8 +589,8 @@ int plan_guard(hps_op* op, LevelPlan& P) {
                            ldx)},
            &P.probe2);
   if (!P.schur) return HPS_OK;
-  P.Wns = (double*)op_alloc(op, sizeof(double) * nm * mm, false);
-  P.Zns = (double*)op_alloc(op, sizeof(double) * nm * mm, false);
+  P.Wns = (double*)lvl_take(op, sizeof(double) * nm * mm);
+  P.Zns = (double*)lvl_take(op, sizeof(double) * nm * mm);
   if (!P.Wns || !P.Zns) {
     set_error("device allocation failed (Newton-Schulz workspace)");
     return HPS_ENOMEM;
@@ -578,6 +603,22 @@ int plan_guard(hps_op* op, LevelPlan& P) {
   z.gate = P.gate;
   add_gemm(op, {z}, &P.nsZ);
   return HPS_OK;
+}
+
+// bytes one merge level takes from the level workspace (the pieces of
+// plan_op, plan_schur, plan_gj and plan_guard above, in any order)
+long long level_ws_bytes(int m, int n, long long nm, bool schur, int schur_p) {
+  const long long mm = (long long)m * m, d8 = sizeof(double);
+  long long b = al256(d8 * nm * mm) + 2 * al256(d8 * nm * m * kProbes);  // D, probe products
+  if (schur) {
+    const long long s = (long long)schur_p * n, r = m - 2 * s;
+    b += 2 * al256(d8 * nm * 2 * s * s) + 2 * al256(d8 * nm * 2 * s * r) + 2 * al256(d8 * nm * r * r);
+    b += gj_ws_bytes((int)s, 2 * nm) + gj_ws_bytes((int)r, nm);
+    b += 2 * al256(d8 * nm * mm);  // Newton-Schulz
+  } else {
+    b += gj_ws_bytes(m, nm);
+  }
+  return b;
 }
 
 // the probe after the inversion (k = 0) or after Newton-Schulz step k
@@ -618,6 +659,7 @@ std::vector<const GemmCall*> solve_gemm_calls(hps_op* op) {
 
 int plan_static_solve(hps_op* op) {
   op->static_ok = false;
+  if (op->ext_side > 0 || op->root_h) return HPS_OK;  // parts of a subtree-recomputing operator
   void* base = nullptr;
   HPS_TRY(static_ws_ptr(&base));
   op->static_base = (char*)base;
@@ -676,11 +718,14 @@ int plan_op(hps_op* op) {
   const MergeGeom& G = merge_geom(d);
   const int ni = op->ni, nb = op->nb, NR = op->NR;
   const long long nl = op->nl;
+  const bool ext = op->ext_side > 0;  // leaves are subtree roots (their T arrive from outside)
   // leaf storage
-  op->LU = (double*)op_alloc(op, sizeof(double) * nl * ni * ni);
-  op->Y = (double*)op_alloc(op, sizeof(double) * nl * ni * nb);
-  op->perm = (int*)op_alloc(op, sizeof(int) * nl * ni);
-  op->pos = (int*)op_alloc(op, sizeof(int) * nl * ni);
+  if (!ext) {
+    op->LU = (double*)op_alloc(op, sizeof(double) * nl * ni * ni);
+    op->Y = (double*)op_alloc(op, sizeof(double) * nl * ni * nb);
+    op->perm = (int*)op_alloc(op, sizeof(int) * nl * ni);
+    op->pos = (int*)op_alloc(op, sizeof(int) * nl * ni);
+  }
   if (d == 3) {
     op->Lbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * ni, false);
     op->Rbuf = (double*)op_alloc(op, sizeof(double) * nl * ni * nb, false);
@@ -691,9 +736,24 @@ int plan_op(hps_op* op) {
                              (long long)ni * nb, ni, ni, nb, ni, -1.0, 0.0, nl)},
              &op->gemmYleaf);
   }
-  op->Tleaf = (double*)op_alloc(op, sizeof(double) * nl * nb * nb, false);
+  // T of the leaves (Tbuf[0]) and of the levels below the root: level lev
+  // writes Tbuf[(L - lev) % 2] while its children's T sit in the other one
+  {
+    const long long side0 = ext ? op->ext_side : (d == 2 ? op->p - 2 : (long long)(op->p - 2) * (op->p - 2));
+    long long tb[2] = {nl * nb * nb, 0};
+    for (int lev = 1; lev < L; ++lev) {
+      const long long nbp = 2LL * d * (side0 << ((d - 1) * (L - lev)));
+      tb[(L - lev) % 2] = std::max(tb[(L - lev) % 2], (1LL << (d * lev)) * nbp * nbp);
+    }
+    for (int k = 0; k < 2; ++k)
+      if (tb[k] > 0) {
+        op->Tbuf[k] = (double*)op_alloc(op, sizeof(double) * tb[k], false);
+        if (!op->Tbuf[k]) { set_error("device allocation failed (T workspace)"); return HPS_ENOMEM; }
+      }
+  }
+  op->Tleaf = op->Tbuf[0];
   op->flag = (int*)op_alloc(op, sizeof(int) * 4, false);
-  if (!op->LU || !op->Y || !op->perm || !op->pos || !op->Tleaf || !op->flag) {
+  if ((!ext && (!op->LU || !op->Y || !op->perm || !op->pos)) || !op->Tleaf || !op->flag) {
     set_error("device allocation failed (leaf operators)");
     return HPS_ENOMEM;
   }
@@ -705,7 +765,8 @@ int plan_op(hps_op* op) {
   op->h.assign(L + 1, nullptr);
   op->nbl.assign(L + 1, 0);
   for (int l = 0; l <= L; ++l) {
-    const long long side = d == 2 ? (long long)(op->p - 2) << (L - l) : (long long)(op->p - 2) * (op->p - 2) << (2 * (L - l));
+    const long long base = ext ? op->ext_side : (d == 2 ? op->p - 2 : (long long)(op->p - 2) * (op->p - 2));
+    const long long side = base << ((d - 1) * (L - l));
     op->nbl[l] = (int)(2 * d * side);
   }
   {
@@ -739,7 +800,7 @@ int plan_op(hps_op* op) {
                              ni, ni, NR, ni, 1.0, 0.0, nl)},
              &op->gemmVleaf);
   // adjoint leaf products
-  {
+  if (!ext) {
     const int ne = op->ne;
     if (d == 2) {
       op->fint = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
@@ -764,14 +825,16 @@ int plan_op(hps_op* op) {
                &op->adjLinvT, true, false);
   }
 
-  // leaf T = Q_e P + Q_i Y_int
-  add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->Y, (long long)ni * nb, ni, op->Tleaf, (long long)nb * nb, nb, nb,
-                           nb, ni, 1.0, 1.0, nl, op->cst->QeP, 0, nb)},
-           &op->gemmTleaf);
-  // h = Q_i v (solve)
-  add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->v, (long long)NR * ni, ni, op->h[L], (long long)NR * nb, nb, nb, NR,
-                           ni, 1.0, 0.0, nl)},
-           &op->gemmHleaf);
+  if (!ext) {
+    // leaf T = Q_e P + Q_i Y_int
+    add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->Y, (long long)ni * nb, ni, op->Tleaf, (long long)nb * nb, nb, nb,
+                             nb, ni, 1.0, 1.0, nl, op->cst->QeP, 0, nb)},
+             &op->gemmTleaf);
+    // h = Q_i v (solve)
+    add_gemm(op, {make_group(op->cst->Qi, 0, nb, op->v, (long long)NR * ni, ni, op->h[L], (long long)NR * nb, nb, nb,
+                             NR, ni, 1.0, 0.0, nl)},
+             &op->gemmHleaf);
+  }
   // root data: bdry -> g[0]
   {
     BlockOp o = make_op(0, op->nbl[0], op->nbl[0], 0);
@@ -783,7 +846,7 @@ int plan_op(hps_op* op) {
   // [-1, 1) (splitmix64 of the element index)
   {
     long long mmax = 1;
-    const long long n0 = d == 2 ? (long long)(op->p - 2) : (long long)(op->p - 2) * (op->p - 2);
+    const long long n0 = op->nbl[L] / (2 * d);  // Gauss points per leaf face
     for (int lev = L - 1; lev >= 0; --lev) mmax = std::max<long long>(mmax, G.nint * (n0 << ((d - 1) * (L - 1 - lev))));
     op->probe_ld = (int)mmax;
     std::vector<double> x((size_t)mmax * kProbes);
@@ -801,9 +864,22 @@ int plan_op(hps_op* op) {
     HPS_HIP_TRY(hipMemcpy(op->probe_x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice));
     op->probe_inv_xmax = 1.0 / xmax;
   }
+  // the merge-level build workspace, sized for the largest level
+  {
+    long long need = 0;
+    for (int lev = 0; lev < L; ++lev) {
+      const int n = op->nbl[lev + 1] / (2 * d), m = G.nint * n;
+      const bool schur = m > kGjSmallAlways && !(op->flags & HPS_FLAG_FULL_PIVOT);
+      need = std::max(need, level_ws_bytes(m, n, 1LL << (d * lev), schur, G.schur_p));
+    }
+    op->lvl_ws = (char*)op_alloc(op, (size_t)need, false);
+    if (!op->lvl_ws) { set_error("device allocation failed (merge-level build workspace)"); return HPS_ENOMEM; }
+    op->lvl_ws_bytes = need;
+  }
   op->levels.assign(L, LevelPlan());
   for (int lev = L - 1; lev >= 0; --lev) {
     LevelPlan& P = op->levels[lev];
+    op->lvl_cur = 0;
     P.lev = lev;
     P.nm = 1LL << (d * lev);
     P.nbc = op->nbl[lev + 1];
@@ -818,9 +894,9 @@ int plan_op(hps_op* op) {
     P.Z = (double*)op_alloc(op, sizeof(double) * nm * m * m);
     P.S = (double*)op_alloc(op, sizeof(double) * nm * m * nbp);
     P.Bnz = (double*)op_alloc(op, sizeof(double) * nm * nd * dn * dn);
-    P.Dbuf = (double*)op_alloc(op, sizeof(double) * nm * m * m, false);
+    P.Dbuf = (double*)lvl_take(op, sizeof(double) * nm * m * m);
     const bool formT = lev > 0 || (op->flags & HPS_FLAG_ROOT_T);
-    if (formT) P.Tp = (double*)op_alloc(op, sizeof(double) * nm * nbp * nbp, lev == 0);
+    if (formT) P.Tp = lev == 0 ? (double*)op_alloc(op, sizeof(double) * nm * nbp * nbp) : op->Tbuf[(L - lev) % 2];
     P.hint = op->ws_take(nm * NR * m);
     P.gt = op->ws_take(nm * NR * m);
     P.gint = op->ws_take(nm * NR * m);
@@ -832,7 +908,7 @@ int plan_op(hps_op* op) {
       // block elimination over the interface pieces (measured faster from here on)
       HPS_TRY(plan_schur(op, P, G.schur_p));
     } else {
-      HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm));
+      HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Z, m, nm, true));
     }
     HPS_TRY(plan_guard(op, P));
     // --- D = sum over children touching interfaces i and j of T_c(face_i, face_j)
@@ -928,7 +1004,7 @@ int plan_op(hps_op* op) {
                              NR, m, -1.0, 0.0, nm)},
              &P.gemmGt);
     // h_parent(c, F) = h_c(F) + Bnz_c(F, :) gt(interfaces of c)
-    if (lev > 0) {
+    if (lev > 0 || op->root_h) {
       std::vector<GemmGroup> gs;
       const int ngrp = 2 * d * G.sub_per_face;
       for (int gi = 0; gi < ngrp; ++gi) {
@@ -984,7 +1060,8 @@ int plan_op(hps_op* op) {
                              nbp, nbp, NR, m, 1.0, 1.0, nm, op->g[lev], (long long)NR * nbp, nbp)},
              &P.gemmSt, true, false);
     // gt_total(i) = g_int(i) + sum over both children of Bnz_c(., i)^T h_parent(c, .)
-    if (lev > 0) {
+    // (at the root only when the root's h comes from outside: a subtree root)
+    if (lev > 0 || op->root_h) {
       for (int pass = 0; pass < 2; ++pass) {
         std::vector<GemmGroup> gs;
         for (int c = 0; c < nd; ++c)
@@ -1006,7 +1083,8 @@ int plan_op(hps_op* op) {
       }
     }
     // h_int = -Z^T gt_total
-    add_gemm(op, {make_group(P.Z, (long long)m * m, m, lev > 0 ? P.gt : P.gint, (long long)NR * m, m, P.hint,
+    add_gemm(op, {make_group(P.Z, (long long)m * m, m, (lev > 0 || op->root_h) ? P.gt : P.gint, (long long)NR * m, m,
+                             P.hint,
                              (long long)NR * m, m, m, NR, m, -1.0, 0.0, nm)},
              &P.gemmZt, true, false);
   }
@@ -1086,9 +1164,12 @@ int collect_info(hps_op* op) {
   return HPS_OK;
 }
 
-int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
+int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags = true) {
   const int L = op->tree.depth, nd = op->nd;
-  HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
+  if (reset_flags) HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
+  if (op->ext_side > 0) {
+    // top levels of a subtree-recomputing operator: Tleaf holds the subtree roots' T
+  } else {
   stage_begin(op, "leaf_factor", st);
   if (op->d == 2) {
     HPS_TRY(leaf2d_launch(op->p, coeffs, op->cst->D1, op->cst->D2, op->cst->Mt, op->LU, op->perm, op->pos, op->Y,
@@ -1103,6 +1184,7 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
   stage_begin(op, "leaf_T", st);
   HPS_TRY(run_gemm(op, op->gemmTleaf, st));
   stage_end(op, st);
+  }
   static const char* names[] = {"merge_l0", "merge_l1", "merge_l2", "merge_l3", "merge_l4", "merge_l5",
                                 "merge_l6", "merge_l7", "merge_l8", "merge_l9", "merge_l10", "merge_l11"};
   for (int lev = L - 1; lev >= 0; --lev) {
@@ -1131,27 +1213,31 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st) {
   return HPS_OK;
 }
 
-int run_solve_chunk(hps_op* op, const SolveCtx& c, const double* bdry, const double* src, double* u, int nrhs,
-                    bool graph_safe, hipStream_t st) {
+// Upward part of a solve: root data (when bdry is given), the sources' leaf
+// solutions and the upward pass of their fluxes; without sources the
+// interface data of every merge start at zero.  Operators whose leaves are
+// subtree roots take the leaf-level fluxes h[L] as already filled.
+int run_solve_up(hps_op* op, const SolveCtx& c, const double* bdry, const double* src, bool has_src, int nrhs,
+                 bool graph_safe, hipStream_t st) {
   const int L = op->tree.depth, nd = op->nd, NR = op->NR;
-  if (!graph_safe) stage_begin(op, "solve", st);
-  // root data
-  HPS_TRY(run_copy(op, op->copyRoot, nrhs, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st));
-  if (src) {
-    if (op->d == 2) {
-      HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, c.at(op->v),
-                              NR, st));
-    } else {
-      HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
-      HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
+  if (bdry) HPS_TRY(run_copy(op, op->copyRoot, nrhs, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st));
+  if (has_src) {
+    if (op->ext_side == 0) {
+      if (op->d == 2) {
+        HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs,
+                                c.at(op->v), NR, st, op->rstride));
+      } else {
+        HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
+        HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
+      }
+      HPS_TRY(run_gemm_ctx(c, op->gemmHleaf, st, nrhs));
     }
-    HPS_TRY(run_gemm_ctx(c, op->gemmHleaf, st, nrhs));
     for (int lev = L - 1; lev >= 0; --lev) {
       LevelPlan& P = op->levels[lev];
       HPS_TRY(run_copy(op, P.copyHint, nrhs, c.at(P.hint), (long long)NR * P.m, c.at(op->h[lev + 1]),
                        (long long)nd * NR * P.nbc, nullptr, 0, P.nm, st));
       HPS_TRY(run_gemm_ctx(c, P.gemmGt, st, nrhs));
-      if (lev > 0) HPS_TRY(run_gemm_ctx(c, P.gemmHp, st, nrhs));
+      if (lev > 0 || op->root_h) HPS_TRY(run_gemm_ctx(c, P.gemmHp, st, nrhs));
     }
   } else {
     for (int lev = 0; lev < L; ++lev) {
@@ -1162,27 +1248,76 @@ int run_solve_chunk(hps_op* op, const SolveCtx& c, const double* bdry, const dou
         HPS_HIP_TRY(hipMemsetAsync(P.gt, 0, sizeof(double) * P.nm * NR * P.m, st));
     }
   }
+  return HPS_OK;
+}
+
+// Downward pass and (ordinary leaves) the leaf solutions u = [P g; Y g + v].
+int run_solve_down(hps_op* op, const SolveCtx& c, bool has_src, double* u, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd, NR = op->NR;
   for (int lev = 0; lev < L; ++lev) {
     LevelPlan& P = op->levels[lev];
     HPS_TRY(run_gemm_ctx(c, P.gemmDown, st, nrhs));
     HPS_TRY(run_copy(op, P.copyGchild, nrhs, c.at(op->g[lev + 1]), (long long)nd * NR * P.nbc, c.at(op->g[lev]),
                      (long long)NR * P.nbp, c.at(P.gint), (long long)NR * P.m, P.nm, st));
   }
-  HPS_TRY(leaf_out_launch(op->Y, op->cst->P, c.at(op->g[L]), src ? c.at(op->v) : nullptr, op->cst->Ii, op->cst->Ie,
-                          op->ni, op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st));
+  if (op->ext_side == 0)
+    HPS_TRY(leaf_out_launch(op->Y, op->cst->P, c.at(op->g[L]), has_src ? c.at(op->v) : nullptr, op->cst->Ii,
+                            op->cst->Ie, op->ni, op->ne, op->nb, op->npts, op->nl, nrhs, NR, u, st, op->rstride));
+  return HPS_OK;
+}
+
+int run_solve_chunk(hps_op* op, const SolveCtx& c, const double* bdry, const double* src, double* u, int nrhs,
+                    bool graph_safe, hipStream_t st) {
+  if (!graph_safe) stage_begin(op, "solve", st);
+  HPS_TRY(run_solve_up(op, c, bdry, src, src != nullptr, nrhs, graph_safe, st));
+  HPS_TRY(run_solve_down(op, c, src != nullptr, u, nrhs, st));
   if (!graph_safe) stage_end(op, st);
   return HPS_OK;
 }
 
-int run_adjoint_chunk(hps_op* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, hipStream_t st) {
+// Solve of a subtree-recomputing operator (Algorithm "Subtree recomputation
+// strategy", Section 4.1): with sources, every subtree is rebuilt from its
+// coefficients and its sources' outgoing flux taken at its root; the top
+// levels run their upward and downward passes; then every subtree is rebuilt
+// once more and solved from the boundary data the top levels handed down.
+int run_solve_subtrees(hps_op* top, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st) {
+  hps_op* sub = top->sub;
+  const int Lt = top->tree.depth, NR = top->NR;
+  const long long nsub = top->nl, nb = top->nbl[Lt];
+  const long long coef_stride = sub->nl * (sub->d == 2 ? 6 : 10) * sub->npts;
+  const long long pts_stride = sub->nl * sub->npts;
+  const SolveCtx ct = own_ctx(top), cs = own_ctx(sub);
+  if (src) {
+    for (long long j = 0; j < nsub; ++j) {
+      HPS_TRY(run_build(sub, top->sub_coef + j * coef_stride, st));
+      HPS_TRY(run_solve_up(sub, cs, nullptr, src + j * pts_stride, true, nrhs, false, st));
+      HPS_HIP_TRY(hipMemcpyAsync(top->h[Lt] + j * NR * nb, sub->h[0], sizeof(double) * nrhs * nb,
+                                 hipMemcpyDeviceToDevice, st));
+    }
+  }
+  HPS_TRY(run_solve_up(top, ct, bdry, nullptr, src != nullptr, nrhs, false, st));
+  HPS_TRY(run_solve_down(top, ct, src != nullptr, nullptr, nrhs, st));
+  for (long long j = 0; j < nsub; ++j) {
+    HPS_TRY(run_build(sub, top->sub_coef + j * coef_stride, st));
+    HPS_TRY(run_solve_up(sub, cs, top->g[Lt] + j * NR * nb, src ? src + j * pts_stride : nullptr, src != nullptr,
+                         nrhs, false, st));
+    HPS_TRY(run_solve_down(sub, cs, src != nullptr, u + j * pts_stride, nrhs, st));
+  }
+  return HPS_OK;
+}
+
+// Adjoint of the downward pass, leaves to root: (ordinary leaves) g_leaf =
+// Y^T w_int + P^T w_ext and v = w_int, then per level the interface sums
+// g_int, the parent's exterior faces and g_parent += S^T g_int.  Operators
+// whose leaves are subtree roots take g[L] as already filled.
+int run_adjoint_up(hps_op* op, const double* w, int nrhs, hipStream_t st) {
   const int L = op->tree.depth, nd = op->nd, NR = op->NR;
-  stage_begin(op, "adjoint", st);
-  // leaves: g_leaf = Y^T w_int + P^T w_ext; v = w_int
-  HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, op->v, st));
-  HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ie, op->ne, op->npts, op->nl, nrhs, NR, op->wext, st));
-  HPS_TRY(run_gemm(op, op->adjYt, st, nrhs));
-  HPS_TRY(run_gemm(op, op->adjPt, st, nrhs));
-  // transposed downward pass, leaves to root
+  if (op->ext_side == 0) {
+    HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, op->v, st, op->rstride));
+    HPS_TRY(leaf_gather_pts_launch(w, op->cst->Ie, op->ne, op->npts, op->nl, nrhs, NR, op->wext, st, op->rstride));
+    HPS_TRY(run_gemm(op, op->adjYt, st, nrhs));
+    HPS_TRY(run_gemm(op, op->adjPt, st, nrhs));
+  }
   for (int lev = L - 1; lev >= 0; --lev) {
     LevelPlan& P = op->levels[lev];
     const long long cstride = (long long)nd * NR * P.nbc;
@@ -1191,12 +1326,18 @@ int run_adjoint_chunk(hps_op* op, const double* w, double* lam_src, double* lam_
                      st));
     HPS_TRY(run_gemm(op, P.gemmSt, st, nrhs));
   }
-  if (lam_bdry) HPS_TRY(run_copy(op, op->copyRoot, nrhs, lam_bdry, 0, op->g[0], 0, nullptr, 0, 1, st));
-  // transposed upward pass, root to leaves
-  HPS_HIP_TRY(hipMemsetAsync(op->h[0], 0, sizeof(double) * NR * op->nbl[0], st));
+  return HPS_OK;
+}
+
+// Adjoint of the source's upward pass, root to leaves, from h[0] (zero at the
+// domain root, handed down at a subtree root), then (ordinary leaves)
+// v += Q_i^T h_leaf, f_int = L_ii^{-T} v scattered into lam_src.
+int run_adjoint_down(hps_op* op, double* lam_src, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, nd = op->nd, NR = op->NR;
+  if (!op->root_h) HPS_HIP_TRY(hipMemsetAsync(op->h[0], 0, sizeof(double) * NR * op->nbl[0], st));
   for (int lev = 0; lev < L; ++lev) {
     LevelPlan& P = op->levels[lev];
-    if (lev > 0) {
+    if (lev > 0 || op->root_h) {
       HPS_TRY(run_gemm(op, P.gemmBt1, st, nrhs));
       HPS_TRY(run_gemm(op, P.gemmBt2, st, nrhs));
     }
@@ -1204,15 +1345,52 @@ int run_adjoint_chunk(hps_op* op, const double* w, double* lam_src, double* lam_
     HPS_TRY(run_copy(op, P.copyGchild, nrhs, op->h[lev + 1], (long long)nd * NR * P.nbc, op->h[lev],
                      (long long)NR * P.nbp, P.hint, (long long)NR * P.m, P.nm, st));
   }
-  // leaves: v += Q_i^T h_leaf;  f_int = L_ii^{-T} v
+  if (op->ext_side > 0) return HPS_OK;
   HPS_TRY(run_gemm(op, op->adjQt, st, nrhs));
   if (op->d == 2) {
     HPS_TRY(leaf_src_t_launch(op->LU, op->perm, op->v, op->ni, op->nl, nrhs, NR, op->fint, st));
   } else {
     HPS_TRY(run_gemm(op, op->adjLinvT, st, nrhs));
   }
-  HPS_TRY(leaf_scatter_int_launch(op->fint, op->cst->PosI, op->ni, op->npts, op->nl, nrhs, NR, lam_src, st));
+  return leaf_scatter_int_launch(op->fint, op->cst->PosI, op->ni, op->npts, op->nl, nrhs, NR, lam_src, st,
+                                 op->rstride);
+}
+
+int run_adjoint_chunk(hps_op* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, hipStream_t st) {
+  stage_begin(op, "adjoint", st);
+  HPS_TRY(run_adjoint_up(op, w, nrhs, st));
+  if (lam_bdry) HPS_TRY(run_copy(op, op->copyRoot, nrhs, lam_bdry, 0, op->g[0], 0, nullptr, 0, 1, st));
+  HPS_TRY(run_adjoint_down(op, lam_src, nrhs, st));
   stage_end(op, st);
+  return HPS_OK;
+}
+
+// Adjoint solve of a subtree-recomputing operator: the transposed passes in
+// reverse order, with every subtree rebuilt twice (its leaves-to-root part
+// gives the g of its root; after the top levels, the same part again, to
+// restore its interface sums, and then its root-to-leaves part from the h
+// the top levels hand down).
+int run_adjoint_subtrees(hps_op* top, const double* w, double* lam_src, double* lam_bdry, int nrhs, hipStream_t st) {
+  hps_op* sub = top->sub;
+  const int Lt = top->tree.depth, NR = top->NR;
+  const long long nsub = top->nl, nb = top->nbl[Lt];
+  const long long coef_stride = sub->nl * 6 * sub->npts, pts_stride = sub->nl * sub->npts;
+  for (long long j = 0; j < nsub; ++j) {
+    HPS_TRY(run_build(sub, top->sub_coef + j * coef_stride, st));
+    HPS_TRY(run_adjoint_up(sub, w + j * pts_stride, nrhs, st));
+    HPS_HIP_TRY(hipMemcpyAsync(top->g[Lt] + j * NR * nb, sub->g[0], sizeof(double) * nrhs * nb,
+                               hipMemcpyDeviceToDevice, st));
+  }
+  HPS_TRY(run_adjoint_up(top, nullptr, nrhs, st));
+  if (lam_bdry) HPS_TRY(run_copy(top, top->copyRoot, nrhs, lam_bdry, 0, top->g[0], 0, nullptr, 0, 1, st));
+  HPS_TRY(run_adjoint_down(top, nullptr, nrhs, st));
+  for (long long j = 0; j < nsub; ++j) {
+    HPS_TRY(run_build(sub, top->sub_coef + j * coef_stride, st));
+    HPS_TRY(run_adjoint_up(sub, w + j * pts_stride, nrhs, st));
+    HPS_HIP_TRY(hipMemcpyAsync(sub->h[0], top->h[Lt] + j * NR * nb, sizeof(double) * nrhs * nb,
+                               hipMemcpyDeviceToDevice, st));
+    HPS_TRY(run_adjoint_down(sub, lam_src + j * pts_stride, nrhs, st));
+  }
   return HPS_OK;
 }
 
@@ -1423,6 +1601,46 @@ int run_solve_refined_chunk(hps_op* op, const double* bdry, const double* src, d
   return HPS_OK;
 }
 
+// After a queued build: synchronize, then check the pivots and the
+// merge-inverse probes (see hps_level_info).  *retry is set when a
+// block-eliminated inverse stayed inaccurate (or had a zero pivot inside a
+// block) and pivoting over all of D can redo it.
+int check_build(hps_op* op, bool* retry) {
+  *retry = false;
+  int hflag[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess) {
+    set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
+    return HPS_EDEVICE;
+  }
+  if (hflag[0]) {
+    set_error(std::string("zero or non-finite pivot in ") +
+              ((hflag[0] & 1) ? "a leaf factorization (L_ii)" : "a merge matrix D"));
+    return HPS_ESINGULAR;
+  }
+  op->info_ready = false;
+  HPS_TRY(collect_info(op));
+  int bad = -1;
+  for (int lev = 0; lev < (int)op->info.size(); ++lev)
+    if (op->info[lev].block_inverse && (hflag[1] || !(op->info[lev].residual <= kNsAccept))) bad = lev;
+  if (bad < 0) return HPS_OK;
+  bool full_ok = true;
+  for (const auto& I : op->info) full_ok = full_ok && I.m <= 8192;
+  if (full_ok) {
+    *retry = true;
+    return HPS_OK;
+  }
+  const hps_level_info_t& I = op->info[bad];
+  char buf[256];
+  std::snprintf(buf, sizeof(buf),
+                "merge level %d node %lld: inverse of D (m = %d) by block elimination has probe residual "
+                "%.2e after %d Newton-Schulz steps%s, and m exceeds the whole-D pivoting limit (8192)",
+                bad, I.worst_node, I.m, I.residual, I.ns_steps, hflag[1] ? " (zero pivot in a block)" : "");
+  set_error(buf);
+  return HPS_ESINGULAR;
+}
+
 int check_tree(const hps_tree_t* t, int p) {
   if (!t) { set_error("tree is NULL"); return HPS_EINVAL; }
   if (t->dim != 2 && t->dim != 3) { set_error("dim must be 2 or 3"); return HPS_EINVAL; }
@@ -1494,7 +1712,7 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags) {
   return bytes;
 }
 
-size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident : 0; }
+size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident + (op->sub ? op->sub->resident : 0) : 0; }
 
 void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -1534,42 +1752,7 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
   if (rc == HPS_OK) rc = plan_op(op);
   if (rc == HPS_OK) rc = run_build(op, coeffs, op->stream);
   bool retry_full_pivot = false;
-  if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) {
-    int hflag[4] = {0, 0, 0, 0};
-    hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
-    if (e != hipSuccess) {
-      set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
-      rc = HPS_EDEVICE;
-    } else if (hflag[0]) {
-      set_error(std::string("zero or non-finite pivot in ") +
-                ((hflag[0] & 1) ? "a leaf factorization (L_ii)" : "a merge matrix D"));
-      rc = HPS_ESINGULAR;
-    } else {
-      rc = collect_info(op);
-      // block-eliminated inverses that stayed inaccurate after refinement,
-      // or a zero pivot inside one of their blocks
-      int bad = -1;
-      for (int lev = 0; rc == HPS_OK && lev < (int)op->info.size(); ++lev)
-        if (op->info[lev].block_inverse && (hflag[1] || !(op->info[lev].residual <= kNsAccept))) bad = lev;
-      if (bad >= 0) {
-        bool full_ok = true;
-        for (const auto& I : op->info) full_ok = full_ok && I.m <= 8192;
-        if (full_ok) {
-          retry_full_pivot = true;
-        } else {
-          const hps_level_info_t& I = op->info[bad];
-          char buf[256];
-          std::snprintf(buf, sizeof(buf),
-                        "merge level %d node %lld: inverse of D (m = %d) by block elimination has probe residual "
-                        "%.2e after %d Newton-Schulz steps%s, and m exceeds the whole-D pivoting limit (8192)",
-                        bad, I.worst_node, I.m, I.residual, I.ns_steps, hflag[1] ? " (zero pivot in a block)" : "");
-          set_error(buf);
-          rc = HPS_ESINGULAR;
-        }
-      }
-    }
-  }
+  if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) rc = check_build(op, &retry_full_pivot);
   if (retry_full_pivot) {
     // rare path: redo the whole build with partial pivoting over every D
     (void)hipStreamSynchronize(op->stream);
@@ -1583,6 +1766,99 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
     return rc;
   }
   *out = op;
+  return HPS_OK;
+}
+
+int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int flags, int subtree_depth,
+                       void* stream, hps_op_t** out) {
+  if (out) *out = nullptr;
+  HPS_TRY(check_tree(tree, p));
+  if (!coeffs || !out) { set_error("coeffs and out must not be NULL"); return HPS_EINVAL; }
+  if (tree->dim != 2) { set_error("subtree recomputation is implemented for 2D trees"); return HPS_EUNSUPPORTED; }
+  if (subtree_depth < 1 || subtree_depth >= tree->depth) {
+    set_error("subtree_depth must satisfy 1 <= subtree_depth < depth");
+    return HPS_EINVAL;
+  }
+  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_ROOT_T)) {
+    set_error("HPS_FLAG_FP32_COPY and HPS_FLAG_ROOT_T are not available with subtree recomputation");
+    return HPS_EUNSUPPORTED;
+  }
+  const int Ls = subtree_depth, Lt = tree->depth - Ls;
+  const LeafOps& o = leaf_ops(2, p);
+  hipStream_t st = (hipStream_t)stream;
+  const int keep = flags & (HPS_FLAG_FULL_PIVOT | HPS_FLAG_TEST_NO_REFINE);
+  // one subtree's plan: a depth-Ls tree over the subtree's box (every subtree
+  // has the same leaf size, so the plan serves all of them), with its root T
+  // and its root's outgoing source flux
+  hps_op* sub = new hps_op();
+  sub->tree = *tree;
+  sub->tree.depth = Ls;
+  sub->tree.hi = tree->lo + (tree->hi - tree->lo) / (double)(1LL << Lt);
+  sub->p = p;
+  sub->d = 2;
+  sub->nd = 4;
+  sub->flags = keep | HPS_FLAG_ROOT_T;
+  sub->nl = 1LL << (2 * Ls);
+  sub->npts = o.npts;
+  sub->ni = o.n_i;
+  sub->ne = o.n_e;
+  sub->nb = o.n_b;
+  sub->r = (tree->hi - tree->lo) / 2.0 / (double)(1LL << tree->depth);
+  sub->stream = st;
+  sub->root_h = true;
+  sub->rstride = (1LL << (2 * tree->depth)) * o.npts;
+  int rc = get_consts(2, p, sub->r, &sub->cst);
+  if (rc == HPS_OK) rc = plan_op(sub);
+  if (rc != HPS_OK) { hps_free(sub); return rc; }
+  // the top levels: leaves are the subtree roots
+  hps_op* top = new hps_op();
+  top->tree = *tree;
+  top->tree.depth = Lt;
+  top->p = p;
+  top->d = 2;
+  top->nd = 4;
+  top->flags = keep | (flags & HPS_FLAG_TIMING);
+  top->nl = 1LL << (2 * Lt);
+  top->ext_side = (p - 2) << Ls;
+  top->nb = 4 * top->ext_side;
+  top->r = sub->r;
+  top->stream = st;
+  top->sub = sub;
+  top->full_depth = tree->depth;
+  rc = plan_op(top);
+  const long long ncoef = (1LL << (2 * tree->depth)) * 6 * o.npts;
+  if (rc == HPS_OK) {
+    top->sub_coef = (double*)op_alloc(top, sizeof(double) * ncoef);
+    if (!top->sub_coef) { set_error("device allocation failed (coefficient copy)"); rc = HPS_ENOMEM; }
+  }
+  if (rc == HPS_OK) {
+    const hipError_t e = hipMemcpyAsync(top->sub_coef, coeffs, sizeof(double) * ncoef, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) { set_error(std::string("coefficient copy failed: ") + hipGetErrorString(e)); rc = HPS_EDEVICE; }
+  }
+  const bool check = !(flags & HPS_FLAG_NO_CHECK);
+  bool retry = false;
+  const long long coef_stride = sub->nl * 6 * o.npts, nbs = top->nb;
+  for (long long j = 0; rc == HPS_OK && !retry && j < top->nl; ++j) {
+    rc = run_build(sub, top->sub_coef + j * coef_stride, st);
+    if (rc == HPS_OK) {
+      const hipError_t e = hipMemcpyAsync(top->Tleaf + j * nbs * nbs, sub->levels[0].Tp, sizeof(double) * nbs * nbs,
+                                          hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) { set_error(std::string("subtree copy failed: ") + hipGetErrorString(e)); rc = HPS_EDEVICE; }
+    }
+    if (rc == HPS_OK && check) rc = check_build(sub, &retry);
+  }
+  if (rc == HPS_OK && !retry) rc = run_build(top, nullptr, st);
+  if (rc == HPS_OK && !retry && check) rc = check_build(top, &retry);
+  if (rc == HPS_OK && retry) {
+    hps_free(top);
+    return hps_build_subtrees(tree, p, coeffs, flags | HPS_FLAG_FULL_PIVOT, subtree_depth, stream, out);
+  }
+  if (rc != HPS_OK) {
+    if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(st);
+    hps_free(top);
+    return rc;
+  }
+  *out = top;
   return HPS_OK;
 }
 
@@ -1600,6 +1876,14 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
   }
   hipStream_t st = (hipStream_t)stream;
   clear_stages(op);
+  if (op->sub) {
+    const long long nbr = op->nbl[0], field = op->sub->rstride;
+    for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
+      const int k = std::min(op->NR, nrhs - r0);
+      HPS_TRY(run_solve_subtrees(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+    }
+    return HPS_OK;
+  }
   const long long nbr = op->nbl[0], field = op->nl * op->npts;
   for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
     const int k = std::min(op->NR, nrhs - r0);
@@ -1614,6 +1898,7 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
 
 int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, void* stream) {
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
+  if (op->sub) { set_error("operators built with subtree recomputation solve through hps_solve"); return HPS_EUNSUPPORTED; }
   if (!op->static_ok) {
     char buf[200];
     std::snprintf(buf, sizeof(buf),
@@ -1653,10 +1938,15 @@ int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* la
   }
   hipStream_t st = (hipStream_t)stream;
   clear_stages(op);
-  const long long nbr = op->nbl[0], field = op->nl * op->npts;
+  const long long nbr = op->nbl[0], field = op->nl * op->npts, sfield = op->sub ? op->sub->rstride : 0;
   for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
     const int k = std::min(op->NR, nrhs - r0);
-    HPS_TRY(run_adjoint_chunk(op, w + r0 * field, lam_src + r0 * field, lam_bdry ? lam_bdry + r0 * nbr : nullptr, k, st));
+    if (op->sub)
+      HPS_TRY(run_adjoint_subtrees(op, w + r0 * sfield, lam_src + r0 * sfield, lam_bdry ? lam_bdry + r0 * nbr : nullptr,
+                                   k, st));
+    else
+      HPS_TRY(run_adjoint_chunk(op, w + r0 * field, lam_src + r0 * field, lam_bdry ? lam_bdry + r0 * nbr : nullptr, k,
+                                st));
   }
   return HPS_OK;
 }
@@ -1666,7 +1956,11 @@ int hps_coeff_grad(hps_op_t* op, const double* u, const double* lam, int nrhs, d
     set_error("op, u, lam, grad must be non-NULL and nrhs >= 1");
     return HPS_EINVAL;
   }
-  return coeff_grad_launch(op->d, op->p, u, lam, op->cst->D1, op->cst->D2, op->nl, nrhs, grad, (hipStream_t)stream);
+  // the gradient needs only the leaf differentiation matrices (the same for
+  // every leaf of the tree, so a subtree plan's serve for all leaves)
+  const hps_op* lo = op->sub ? op->sub : op;
+  const long long nl = op->sub ? op->sub->rstride / op->sub->npts : op->nl;
+  return coeff_grad_launch(op->d, op->p, u, lam, lo->cst->D1, lo->cst->D2, nl, nrhs, grad, (hipStream_t)stream);
 }
 
 int hps_interp_weights(const hps_tree_t* tree, int p, const double* x, long long m, long long* leaf, double* w) {
@@ -1700,6 +1994,7 @@ void hps_free(hps_op_t* op) {
   // stream: wait for all queued device work before its memory is recycled
   (void)hipDeviceSynchronize();
   clear_stages(op);
+  if (op->sub) hps_free(op->sub);
   for (auto& a : op->allocs) dfree(a.p, a.bytes);
   delete op;
 }

@@ -124,6 +124,25 @@ struct hps_op {
   long long static_need = 0;
   std::vector<hps::GemmGroup> hgroups_static;
   hps::GemmGroup* dgroups_static = nullptr;
+  // subtree recomputation (hps_build_subtrees): this operator keeps the top
+  // levels resident; its leaves are the roots of complete subtrees of depth
+  // sub->tree.depth, whose operators are rebuilt from the kept coefficients
+  // (sub_coef) whenever a solve needs them
+  int ext_side = 0;           // Gauss points per side of a top-level leaf (0: ordinary leaves)
+  bool root_h = false;        // the source pass also forms the root's outgoing flux h[0]
+  long long rstride = 0;      // right-hand-side stride of src / u (0: nl * npts)
+  hps_op* sub = nullptr;      // one subtree's plan, rebuilt for each subtree in turn
+  int full_depth = 0;         // depth of the whole tree
+  double* sub_coef = nullptr; // device copy of every leaf's coefficients
+  // merge-level build workspace.  Levels are built one after another on one
+  // stream, so each level takes its transient buffers (gathered D, block
+  // elimination and Newton-Schulz blocks, Gauss-Jordan panels, probe
+  // products) from the start of lvl_ws, sized for the largest level; the
+  // leaves' T sit in Tbuf[0] and the levels' T (below the root) alternate
+  // between Tbuf[1] and Tbuf[0]
+  char* lvl_ws = nullptr;
+  long long lvl_ws_bytes = 0, lvl_cur = 0;
+  double* Tbuf[2] = {nullptr, nullptr};
   std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
   std::vector<int> nbl;                // boundary size per tree level
   double* v = nullptr;                 // [nl][NR][ni]

@@ -344,21 +344,23 @@ __global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(2)
                                                                 const int* __restrict__ permall,
                                                                 const int* __restrict__ posall,
                                                                 const double* __restrict__ src, const int* __restrict__ Ii,
-                                                                int NI, int npts, long long nl, int nrhs,
+                                                                int NI, int npts, long long rstride, int nrhs,
                                                                 double* __restrict__ vout, int NRcap) {
   __shared__ double s_y[SRC_MAXR];
   __shared__ double s_stage[RPT * SRCW_THREADS * SRC_STAGE];
   const long long leaf = blockIdx.x;
   const double* f = src + leaf * npts;
-  const long long rstride = nl * npts;
   auto key = [=](int k) { return Ii[k]; };
   auto at = [=](int j, int ik) { return f[(long long)j * rstride + ik]; };
   leaf_src_wave<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, key, at, NI, nrhs,
                              vout + leaf * (long long)NRcap * NI, s_y, s_stage);
 }
 
+// src[r] starts rstride doubles after src[r - 1] (nl * npts for a whole
+// operator's sources; larger when the leaves are a slice of a bigger field)
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
-                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st) {
+                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride) {
+  if (rstride <= 0) rstride = nl * npts;
   if (nrhs > SRC_MAXR) {
     set_error("leaf_src: at most 16 right-hand sides per pass");
     return HPS_EINVAL;
@@ -366,10 +368,10 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
   const int rpt = (NI + SRCW_THREADS - 1) / SRCW_THREADS;
   dim3 grid((unsigned)nl), block(SRCW_THREADS);
   switch (rpt) {
-    case 1: hipLaunchKernelGGL(leaf_src_kernel<1>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 2: hipLaunchKernelGGL(leaf_src_kernel<2>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 3: hipLaunchKernelGGL(leaf_src_kernel<3>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
-    case 4: hipLaunchKernelGGL(leaf_src_kernel<4>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, nl, nrhs, v, NRcap); break;
+    case 1: hipLaunchKernelGGL(leaf_src_kernel<1>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
+    case 2: hipLaunchKernelGGL(leaf_src_kernel<2>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
+    case 3: hipLaunchKernelGGL(leaf_src_kernel<3>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
+    case 4: hipLaunchKernelGGL(leaf_src_kernel<4>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
     default:
       set_error("leaf_src: too many interior points");
       return HPS_EUNSUPPORTED;
@@ -449,19 +451,21 @@ __device__ __forceinline__ void leaf_out_body(const double* __restrict__ Y, cons
 __global__ __launch_bounds__(OUT_THREADS) void leaf_out_kernel(const double* __restrict__ Yall, const double* __restrict__ P,
                                                                const double* __restrict__ gall, const double* __restrict__ vall,
                                                                const int* __restrict__ Ii, const int* __restrict__ Ie,
-                                                               int NI, int NE, int NB, int npts, long long nl, int nrhs,
+                                                               int NI, int NE, int NB, int npts, long long rstride, int nrhs,
                                                                int NRcap, double* __restrict__ u) {
   extern __shared__ double s_g[];  // [NB][OUT_MAXR]
   const long long leaf = blockIdx.x;
   double* ul = u + leaf * npts;
-  const long long rstride = nl * npts;
   auto out = [=](int j, int pt, double val) { ul[(long long)j * rstride + pt] = val; };
   leaf_out_body(Yall + leaf * (long long)NI * NB, P, gall + leaf * (long long)NRcap * NB,
                 vall ? vall + leaf * (long long)NRcap * NI : nullptr, Ii, Ie, NI, NE, NB, npts, nrhs, out, s_g);
 }
 
+// u[r] starts rstride doubles after u[r - 1] (0: nl * npts)
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
-                    int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st) {
+                    int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st,
+                    long long rstride) {
+  if (rstride <= 0) rstride = nl * npts;
   if (nrhs > OUT_MAXR) {
     set_error("leaf_out: at most 16 right-hand sides per pass");
     return HPS_EINVAL;
@@ -475,7 +479,7 @@ int leaf_out_launch(const double* Y, const double* P, const double* g, const dou
     HPS_HIP_TRY(hipFuncSetAttribute((const void*)leaf_out_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   }
   hipLaunchKernelGGL(leaf_out_kernel, dim3((unsigned)nl), dim3(OUT_THREADS), shm, st, Y, P, g, v, Ii, Ie, NI, NE, NB,
-                     npts, nl, nrhs, NRcap, u);
+                     npts, rstride, nrhs, NRcap, u);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
@@ -485,37 +489,42 @@ int leaf_out_launch(const double* Y, const double* P, const double* g, const dou
 // Adjoint (transposed) solve pieces.
 // ---------------------------------------------------------------------------
 // out[leaf][r][k] = w[r][leaf][idx[k]]  (k < n)
+// w[r] starts rstride doubles after w[r - 1] (0: nl * npts)
 __global__ void leaf_gather_pts_kernel(const double* __restrict__ w, const int* __restrict__ idx, int n, int npts,
-                                       long long nl, int nrhs, int NRcap, double* __restrict__ out) {
+                                       long long rstride, int nrhs, int NRcap, double* __restrict__ out) {
   const long long leaf = blockIdx.y;
   const int r = blockIdx.z;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-    out[(leaf * NRcap + r) * n + k] = w[((long long)r * nl + leaf) * npts + idx[k]];
+    out[(leaf * NRcap + r) * n + k] = w[(long long)r * rstride + leaf * npts + idx[k]];
 }
 
 int leaf_gather_pts_launch(const double* w, const int* idx, int n, int npts, long long nl, int nrhs, int NRcap,
-                           double* out, hipStream_t st) {
+                           double* out, hipStream_t st, long long rstride) {
+  if (rstride <= 0) rstride = nl * npts;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)nl, (unsigned)nrhs);
-  hipLaunchKernelGGL(leaf_gather_pts_kernel, grid, dim3(256), 0, st, w, idx, n, npts, nl, nrhs, NRcap, out);
+  hipLaunchKernelGGL(leaf_gather_pts_kernel, grid, dim3(256), 0, st, w, idx, n, npts, rstride, nrhs, NRcap, out);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
 
 // lam[r][leaf][pt] = interior value fint[leaf][r][k] at pt = Ii[k], 0 at exterior points
+// lam[r] starts rstride doubles after lam[r - 1] (0: nl * npts)
 __global__ void leaf_scatter_int_kernel(const double* __restrict__ fint, const int* __restrict__ pos_i, int ni,
-                                        int npts, long long nl, int nrhs, int NRcap, double* __restrict__ lam) {
+                                        int npts, long long rstride, int nrhs, int NRcap, double* __restrict__ lam) {
   const long long leaf = blockIdx.y;
   const int r = blockIdx.z;
   for (int pt = blockIdx.x * blockDim.x + threadIdx.x; pt < npts; pt += gridDim.x * blockDim.x) {
     const int k = pos_i[pt];
-    lam[((long long)r * nl + leaf) * npts + pt] = k >= 0 ? fint[(leaf * NRcap + r) * ni + k] : 0.0;
+    lam[(long long)r * rstride + leaf * npts + pt] = k >= 0 ? fint[(leaf * NRcap + r) * ni + k] : 0.0;
   }
 }
 
 int leaf_scatter_int_launch(const double* fint, const int* pos_i, int ni, int npts, long long nl, int nrhs, int NRcap,
-                            double* lam, hipStream_t st) {
+                            double* lam, hipStream_t st, long long rstride) {
+  if (rstride <= 0) rstride = nl * npts;
   dim3 grid((unsigned)((npts + 255) / 256), (unsigned)nl, (unsigned)nrhs);
-  hipLaunchKernelGGL(leaf_scatter_int_kernel, grid, dim3(256), 0, st, fint, pos_i, ni, npts, nl, nrhs, NRcap, lam);
+  hipLaunchKernelGGL(leaf_scatter_int_kernel, grid, dim3(256), 0, st, fint, pos_i, ni, npts, rstride, nrhs, NRcap,
+                     lam);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

@@ -118,3 +118,23 @@ def test_interp_weights_reject_outside_points():
     with pytest.raises(hp.HPSError) as e:
         hp.interp_weights(t, 8, np.array([[0.0, 1.5]]))
     assert e.value.code == hp.HPS_EINVAL
+
+
+def test_subtree_build_arguments_rejected():
+    # argument checks of hps_build_subtrees return before any device work
+    import numpy as np
+    L = hp.lib()
+    buf = np.zeros(16)
+    ptr = ctypes.c_void_p(buf.ctypes.data)
+    h = ctypes.c_void_p()
+    cases = [(hp.tree(3, 2), 0, 1, hp.HPS_EUNSUPPORTED),       # 2D only
+             (hp.tree(2, 3), 0, 0, hp.HPS_EINVAL),             # subtree_depth >= 1
+             (hp.tree(2, 3), 0, 3, hp.HPS_EINVAL),             # subtree_depth < depth
+             (hp.tree(2, 3), hp.FLAG_FP32_COPY, 1, hp.HPS_EUNSUPPORTED),
+             (hp.tree(2, 3), hp.FLAG_ROOT_T, 1, hp.HPS_EUNSUPPORTED)]
+    for t, flags, sd, code in cases:
+        rc = L.hps_build_subtrees(ctypes.byref(t), 8, ptr, flags, sd, None, ctypes.byref(h))
+        assert rc == code and not h.value, (t.dim, flags, sd, rc)
+        assert L.hps_last_error()
+    t = hp.tree(2, 3)
+    assert L.hps_build_subtrees(ctypes.byref(t), 8, None, 0, 1, None, ctypes.byref(h)) == hp.HPS_EINVAL

@@ -230,6 +230,36 @@ def dtn_problem_f(pts):
     return u_xx + u_yy - np.cos(5 * y) * u_x + np.sin(5 * y) * u_y
 
 
+def poly5(pts):
+    """u = x^3 y^2 - 2 x y^3 + x^2 - 3 y + 1 and its derivatives in the order
+    of TERMS_2D (u_xx, u_xy, u_yy, u_x, u_y, u)."""
+    x, y = pts[..., 0], pts[..., 1]
+    u = x**3 * y**2 - 2 * x * y**3 + x**2 - 3 * y + 1
+    return u, (6 * x * y**2 + 2, 6 * x**2 * y - 6 * y**2, 2 * x**3 - 12 * x * y,
+               3 * x**2 * y**2 - 2 * y**3 + 2 * x, 2 * x**3 * y - 6 * x * y**2 - 3, u)
+
+
+def poly5_problem(pts: np.ndarray, bpts: np.ndarray):
+    """Variable-coefficient 2D problem (every term on, a Helmholtz-like
+    zeroth-order term) whose exact solution is the degree-5 polynomial poly5:
+    returns coefficients, source f = L u at the leaf points, boundary data and
+    u at the leaf points.  The discretization reproduces polynomials of degree
+    <= p - 3 up to rounding, so this checks a solve of any size."""
+    c = coeffs_general2d(pts, {
+        "xx": lambda x, y: -(1.0 + 0.2 * np.sin(x + 2 * y)),
+        "xy": lambda x, y: 0.1 * np.cos(x * y),
+        "yy": lambda x, y: -(1.0 + 0.2 * np.cos(x - y)),
+        "x": lambda x, y: 0.3 * np.cos(3 * y),
+        "y": lambda x, y: -0.2 * np.sin(2 * x),
+        "0": lambda x, y: -4.0 * (1.0 + 0.3 * np.sin(3 * x) * np.cos(y)) - 0.5,
+    })
+    u, d = poly5(pts)
+    f = c[:, 0, :] * d[0]
+    for t in range(1, 6):
+        f += c[:, t, :] * d[t]
+    return c, f, poly5(bpts)[0], u
+
+
 # --------------------------------------------------------------------------
 # Per-workload bundles
 # --------------------------------------------------------------------------

@@ -2,7 +2,7 @@
 
 A plain, slow, obviously correct fp64 NumPy/SciPy implementation of what the
 GPU library computes, written from the paper (arXiv 2503.17535, Sections 3.1-3.3,
-Appendices A and C).  It shares no code with the HIP library and neither
+Appendices A, B and C).  It shares no code with the HIP library and neither
 imports the other; only the seeded input generators in ``workloads`` serve
 both.
 
@@ -19,6 +19,7 @@ Modules:
 * ``dense``    — the composite collocation system assembled densely (tiny trees),
   an independent check of ``hps``.
 * ``adjoint``  — transposed solve and the misfit gradient.
+* ``iti``      — the 2D impedance-to-impedance variant (Appendix B), complex128.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests against
 closed forms, library routines, the dense system or values printed in the

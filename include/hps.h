@@ -176,6 +176,34 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags,
 int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int flags,
                        int subtree_depth, void* stream, hps_op_t** out);
 
+/* Build of the ItI (impedance-to-impedance) variant (Appendix B), 2D: the
+ * Poincare-Steklov operators map incoming impedance data g = u_n + i eta u to
+ * outgoing data h = u_n - i eta u (Section 2), which keeps the merges well
+ * posed for Helmholtz problems at any wavenumber (Section 2, related work).
+ * Leaf stage (Algorithm "2D ItI local solve"): B = [G; L(I_i, :)] with the
+ * Robin rows G = N~ + i eta I at the 4p - 4 boundary Chebyshev points, B^{-1}
+ * by batched Gauss-Jordan, Y = B^{-1}(:, I_e) P, T = Q H Y.  Merges
+ * (Appendix B.2): D = I + [[0, D12], [D21, 0]] inverted through its Schur
+ * complement W = I - D12 D21 (eq. ItI_D_inv), S = -D^{-1} C, T = A + B S.
+ * Every corner carries the Robin condition of the side that starts at it on a
+ * counterclockwise walk of the leaf boundary (SW: S, SE: E, NE: N, NW: W).
+ *   tree    2D (depth limited by W of the root merge: 16 (p - 2) 2^(depth-1)
+ *           reals <= 8192, i.e. depth <= 7 at p = 16)
+ *   eta     impedance parameter, > 0
+ *   coeffs  dev  [n_leaves][6][p^2] real coefficient samples (as hps_build)
+ *   flags   HPS_FLAG_NO_CHECK, HPS_FLAG_TIMING (others: HPS_EUNSUPPORTED)
+ * Complex data are interleaved (re, im) doubles, the layout of complex128:
+ * hps_solve on the returned operator reads bdry as [nrhs][n_root_bdry]
+ * complex incoming impedance data at the root Gauss points (2 n_root_bdry
+ * doubles per rhs), src as [nrhs][n_leaves][p^2] complex and writes u in the
+ * same complex layout; precision must be HPS_FP64.  Unless HPS_FLAG_NO_CHECK
+ * is set the call synchronizes once and returns HPS_ESINGULAR on a zero or
+ * non-finite Gauss-Jordan pivot.  The operator serves hps_solve, hps_free,
+ * hps_op_bytes and hps_stage_times; the adjoint, coefficient-gradient,
+ * allocation-free, batched and level-info calls return HPS_EUNSUPPORTED. */
+int hps_build_iti(const hps_tree_t* tree, int p, double eta, const double* coeffs, int flags,
+                  void* stream, hps_op_t** out);
+
 /* Solve stage (Algorithm down_pass, with the source entering through the
  * linear upward pass of the particular solution, Section 3):
  *   bdry  dev  [nrhs][n_root_bdry]        Dirichlet data g at the root Gauss points

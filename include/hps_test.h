@@ -23,6 +23,10 @@ extern "C" {
  *   4 merge D^{-1} of tree level `level`   [merges][m*m]
  *   5 merge S of tree level `level`        [merges][m*n_parent]
  *   6 merge parent T of tree level `level` [merges][n_parent^2]
+ * For an ItI operator (real representation of complex data, 2p^2 reals per
+ * leaf): 0 is (S B)^{-1} [n_leaves][(2p^2)^2], S the row equilibration of
+ * B, and 2 is Y [n_leaves][2p^2 * n_b],
+ * both column-major; T below the root is build workspace (levels reuse it).
  * Returns the number of doubles written, or a negative error code. */
 long long hps_debug_download(const hps_op_t* op, int which, int level, double* out, long long cap);
 

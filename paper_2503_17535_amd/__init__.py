@@ -28,7 +28,7 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats",
-           "hps_build_subtrees")
+           "hps_build_subtrees", "hps_build_iti")
 
 
 class HPSError(RuntimeError):
@@ -82,6 +82,7 @@ def lib():
         L.hps_op_footprint.restype = S
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
         L.hps_build_subtrees.argtypes = [TP, I, P, I, I, P, ctypes.POINTER(P)]
+        L.hps_build_iti.argtypes = [TP, I, D, P, I, P, ctypes.POINTER(P)]
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
         L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
         L.hps_mem_stats.argtypes = [ctypes.POINTER(S), ctypes.POINTER(S), I]
@@ -185,10 +186,11 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dev_ptr(t, name, shape=None):
+def _dev_ptr(t, name, shape=None, dtype=None):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
-        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype:
+        raise TypeError(f"{name} must be a CUDA {str(dtype).replace('torch.', '')} tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -372,6 +374,39 @@ def debug_gemm(A, B, C, alpha=1.0, beta=0.0, trans_a=False, trans_b=False, strea
 
 def build(t: Tree, p: int, coeffs, flags: int = 0, stream=None) -> Operator:
     return Operator(t, p, coeffs, flags, stream)
+
+
+class ItiOperator(Operator):
+    """An operator of the ItI variant (hps_build_iti): complex128 boundary
+    data (incoming impedance u_n + i eta u at the root Gauss points), sources
+    and solutions."""
+
+    def __init__(self, t: Tree, p: int, coeffs, eta: float, flags: int = 0, stream=None):
+        self.tree, self.p, self.flags, self.eta = t, p, flags, eta
+        self.subtree_depth = 0
+        self.sizes = sizes(t, p)
+        s = self.sizes
+        ptr = _dev_ptr(coeffs, "coeffs", (s.n_leaves, s.n_terms, s.pts_per_leaf))
+        h = ctypes.c_void_p()
+        _check(lib().hps_build_iti(ctypes.byref(t), p, float(eta), ptr, flags, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, bdry, src=None, out=None, stream=None, precision: int = FP64):
+        import torch
+        s, c = self.sizes, torch.complex128
+        nrhs = bdry.shape[0]
+        bptr = _dev_ptr(bdry, "bdry", (nrhs, s.n_root_bdry), c)
+        sptr = None if src is None else _dev_ptr(src, "src", (nrhs, s.n_leaves, s.pts_per_leaf), c)
+        if out is None:
+            out = torch.empty((nrhs, s.n_leaves, s.pts_per_leaf), dtype=c, device=bdry.device)
+        uptr = _dev_ptr(out, "u", (nrhs, s.n_leaves, s.pts_per_leaf), c)
+        _check(lib().hps_solve(self._h, bptr, sptr, uptr, nrhs, precision, _stream_ptr(stream)))
+        return out
+
+
+def build_iti(t: Tree, p: int, coeffs, eta: float, flags: int = 0, stream=None) -> ItiOperator:
+    """hps_build_iti: the impedance-to-impedance variant (2D)."""
+    return ItiOperator(t, p, coeffs, eta, flags, stream)
 
 
 def build_subtrees(t: Tree, p: int, coeffs, subtree_depth: int, flags: int = 0, stream=None) -> Operator:

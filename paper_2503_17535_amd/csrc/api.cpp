@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -22,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hps.h"
@@ -90,6 +92,10 @@ int probe_reduce_launch(const double* r, long long stride, int m, double inv_xma
 int gated_copy_launch(double* dst, const double* src, long long n, const int* gate, long long nodes,
                       hipStream_t st);
 int static_ws_ptr(void** out);
+int iti_leaf_assemble_launch(const double* coeffs, const double* D1, const double* D2, const double* Gr,
+                             const int* Ii, int p, long long nl, double* scale, double* B, hipStream_t st);
+int iti_gather_src_launch(const double* src, const int* Iir, const double* scale, int ni2, int m, long long nl,
+                          int nrhs, int NRcap, double* fint, hipStream_t st);
 int zero_fill_launch(double* x, long long n, hipStream_t st);
 
 static thread_local std::string g_err;
@@ -217,6 +223,105 @@ int get_consts(int d, int p, double r, DevConsts** out) {
   HPS_TRY(upload(&c.Ie, o.Ie));
   HPS_TRY(upload(&c.PosI, o.pos_i));
   auto res = g_cst.emplace(key, c);
+  *out = &res.first->second;
+  return HPS_OK;
+}
+
+// ItI leaf constants (Appendix B.1) for leaves of half-width r, impedance
+// parameter eta, in the real representation (see iti.hip).  The Robin rows
+// of a corner belong to the side that starts at it on a counterclockwise walk
+// (S and E keep their first p - 1 points, N and W their last p - 1).
+std::map<std::tuple<int, double, double>, ItiConsts> g_iti_cst;
+
+int get_iti_consts(int p, double r, double eta, ItiConsts** out) {
+  std::lock_guard<std::mutex> lk(g_cst_mu);
+  auto key = std::make_tuple(p, r, eta);
+  auto it = g_iti_cst.find(key);
+  if (it != g_iti_cst.end()) { *out = &it->second; return HPS_OK; }
+  using cd = std::complex<double>;
+  const LeafOps& o = leaf_ops(2, p);
+  const MergeGeom& geo = merge_geom(2);
+  const int q = p - 2, np = p * p, nr = 4 * p - 4, nbq = 4 * q;
+  std::vector<double> D1((size_t)p * p);
+  for (int i = 0; i < p * p; ++i) D1[i] = o.D[i] / r;
+  // outward normal derivative at point pt of side f, as a row over the points
+  auto normal = [&](int pt, int f, std::vector<cd>& row) {
+    std::fill(row.begin(), row.end(), cd(0.0));
+    const FaceDesc& fd = geo.faces[f];
+    const double sign = fd.side ? 1.0 : -1.0;
+    const int xy[2] = {pt % p, pt / p};
+    const int ca = xy[fd.axis];
+    for (int m = 0; m < p; ++m) {
+      int c2[2] = {xy[0], xy[1]};
+      c2[fd.axis] = m;
+      row[c2[0] + p * c2[1]] += sign * D1[(size_t)ca * p + m];
+    }
+  };
+  std::vector<cd> G((size_t)nr * np), H((size_t)4 * p * np), row(np);
+  std::vector<double> P((size_t)nr * nbq, 0.0);
+  int k = 0;
+  for (int f = 0; f < 4; ++f) {
+    const int t0 = (f == 0 || f == 1) ? 0 : 1;
+    for (int t = t0; t < t0 + p - 1; ++t, ++k) {
+      const int pt = o.face_cheb[f][t];
+      normal(pt, f, row);
+      row[pt] += cd(0.0, eta);                                   // G = N~ + i eta I
+      for (int j = 0; j < np; ++j) G[(size_t)k * np + j] = row[j];
+      for (int s = 0; s < q; ++s) P[(size_t)k * nbq + f * q + s] = o.G2C[(size_t)t * q + s];
+    }
+    for (int t = 0; t < p; ++t) {
+      const int pt = o.face_cheb[f][t];
+      normal(pt, f, row);
+      row[pt] -= cd(0.0, eta);                                   // H = N - i eta I
+      for (int j = 0; j < np; ++j) H[((size_t)f * p + t) * np + j] = row[j];
+    }
+  }
+  // Q H: Chebyshev -> Gauss per side
+  std::vector<cd> QH((size_t)nbq * np, cd(0.0));
+  for (int f = 0; f < 4; ++f)
+    for (int s = 0; s < q; ++s)
+      for (int t = 0; t < p; ++t) {
+        const double w = o.C2G[(size_t)s * p + t];
+        for (int j = 0; j < np; ++j) QH[((size_t)f * q + s) * np + j] += w * H[((size_t)f * p + t) * np + j];
+      }
+  // real representations, column-major
+  auto real_rep = [](const std::vector<cd>& M, int rows, int cols) {
+    std::vector<double> R((size_t)4 * rows * cols);
+    const size_t ld = 2 * (size_t)rows;
+    for (int i = 0; i < rows; ++i)
+      for (int j = 0; j < cols; ++j) {
+        const cd z = M[(size_t)i * cols + j];
+        R[(2 * j) * ld + 2 * i] = z.real();
+        R[(2 * j) * ld + 2 * i + 1] = z.imag();
+        R[(2 * j + 1) * ld + 2 * i] = -z.imag();
+        R[(2 * j + 1) * ld + 2 * i + 1] = z.real();
+      }
+    return R;
+  };
+  // equilibrate the Robin rows (1 / max |G_kj|), in G and in P: the solve
+  // applies B^{-1}(:, Robin rows) P = (D B)^{-1}(:, Robin rows) (D P)
+  std::vector<cd> Pc(P.begin(), P.end());
+  for (int kk = 0; kk < nr; ++kk) {
+    double mx = 0.0;
+    for (int j = 0; j < np; ++j) mx = std::max(mx, std::abs(G[(size_t)kk * np + j]));
+    const double s = 1.0 / mx;
+    for (int j = 0; j < np; ++j) G[(size_t)kk * np + j] *= s;
+    for (int j = 0; j < nbq; ++j) Pc[(size_t)kk * nbq + j] *= s;
+  }
+  ItiConsts c;
+  HPS_TRY(upload(&c.Gr, real_rep(G, nr, np)));
+  HPS_TRY(upload(&c.Pr, real_rep(Pc, nr, nbq)));
+  HPS_TRY(upload(&c.QHr, real_rep(QH, nbq, np)));
+  std::vector<int> Iir(2 * o.Ii.size()), ident(2 * np);
+  for (size_t a2 = 0; a2 < o.Ii.size(); ++a2) {
+    Iir[2 * a2] = 2 * o.Ii[a2];
+    Iir[2 * a2 + 1] = 2 * o.Ii[a2] + 1;
+  }
+  for (int i = 0; i < 2 * np; ++i) ident[i] = i;
+  HPS_TRY(upload(&c.Ii, o.Ii));
+  HPS_TRY(upload(&c.Iir, Iir));
+  HPS_TRY(upload(&c.ident, ident));
+  auto res = g_iti_cst.emplace(key, c);
   *out = &res.first->second;
   return HPS_OK;
 }
@@ -659,7 +764,7 @@ std::vector<const GemmCall*> solve_gemm_calls(hps_op* op) {
 
 int plan_static_solve(hps_op* op) {
   op->static_ok = false;
-  if (op->ext_side > 0 || op->root_h) return HPS_OK;  // parts of a subtree-recomputing operator
+  if (op->ext_side > 0 || op->root_h || op->iti) return HPS_OK;  // subtree parts and ItI: not offered
   void* base = nullptr;
   HPS_TRY(static_ws_ptr(&base));
   op->static_base = (char*)base;
@@ -713,6 +818,8 @@ int run_gemm_ctx(const SolveCtx& c, const GemmCall& call, hipStream_t st, int n_
 // ---------------------------------------------------------------------------
 // plan: allocations + every descriptor table
 // ---------------------------------------------------------------------------
+int finish_plan(hps_op* op);
+
 int plan_op(hps_op* op) {
   const int d = op->d, L = op->tree.depth, nd = op->nd;
   const MergeGeom& G = merge_geom(d);
@@ -1088,6 +1195,11 @@ int plan_op(hps_op* op) {
                              (long long)NR * m, m, m, NR, m, -1.0, 0.0, nm)},
              &P.gemmZt, true, false);
   }
+  return finish_plan(op);
+}
+
+// split-K workspace, allocation-free descriptor copy, descriptor upload
+int finish_plan(hps_op* op) {
   // split-K workspace, shared by all calls (they run one after another)
   if (op->split_elems > 0) {
     op->splitws = (double*)op_alloc(op, sizeof(double) * op->split_elems, false);
@@ -1391,6 +1503,340 @@ int run_adjoint_subtrees(hps_op* top, const double* w, double* lam_src, double* 
                                hipMemcpyDeviceToDevice, st));
     HPS_TRY(run_adjoint_down(sub, lam_src + j * pts_stride, nrhs, st));
   }
+  return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ItI variant (Appendix B), in the real representation of complex data (see
+// iti.hip): at a merge whose children have n reals per side, the unknowns
+// g_int are the incoming data of the children on the interfaces, in the
+// order [g5a, g8a, g6c, g7c, g5b, g6b, g7d, g8d] of eq. (2D_ItI_merge_2).
+// Unknown k belongs to child kItiUnk[k][0] on its face kItiUnk[k][1]; its
+// constraint row reads the outgoing data of the neighbour kItiUnk[k][2] on
+// face kItiUnk[k][3]:  g_k + T^y(f_y, .) g^y + h^y(f_y) = 0.  D, C, B and A
+// are formed densely (their zero blocks included) by block copies from the
+// children's T.
+// ---------------------------------------------------------------------------
+constexpr int kItiUnk[8][4] = {{0, 1, 1, 3}, {0, 2, 3, 0}, {2, 0, 1, 2}, {2, 3, 3, 1},
+                               {1, 3, 0, 1}, {1, 2, 2, 0}, {3, 1, 2, 3}, {3, 0, 0, 2}};
+
+// bytes of one ItI merge level's transient buffers (D12, D21, W, W^{-1}, C
+// and the Gauss-Jordan panels of W)
+long long iti_level_ws_bytes(int n, long long nm) {
+  const long long w = 4LL * n, mi = 8LL * n, d8 = sizeof(double);
+  return 4 * al256(d8 * nm * w * w) + al256(d8 * nm * mi * mi) + gj_ws_bytes((int)w, nm);
+}
+
+int plan_iti(hps_op* op) {
+  const int L = op->tree.depth, NR = op->NR, p = op->p;
+  const long long nl = op->nl;
+  const int m = op->npts, nb = op->nb, nr2 = 2 * (4 * p - 4), ni2 = op->ni;
+  const MergeGeom& G = merge_geom(2);
+  const ItiConsts* ic = op->ic;
+  // leaves: B (transient), B^{-1}, Y
+  op->Lbuf = (double*)op_alloc(op, sizeof(double) * nl * m * m, false);
+  op->Rbuf = (double*)op_alloc(op, sizeof(double) * nl * ni2);  // interior row scales
+  op->LU = (double*)op_alloc(op, sizeof(double) * nl * m * m);
+  op->Y = (double*)op_alloc(op, sizeof(double) * nl * m * nb);
+  op->flag = (int*)op_alloc(op, sizeof(int) * 4, false);
+  op->nbl.assign(L + 1, 0);
+  for (int l = 0; l <= L; ++l) op->nbl[l] = nb << (L - l);
+  // T of the leaves and of the levels below the root (two alternating buffers)
+  for (int k = 0; k < (L >= 2 ? 2 : 1); ++k) {
+    op->Tbuf[k] = (double*)op_alloc(op, sizeof(double) * nl * nb * nb, false);
+    if (!op->Tbuf[k]) { set_error("device allocation failed (T workspace)"); return HPS_ENOMEM; }
+  }
+  op->Tleaf = op->Tbuf[0];
+  if (!op->Lbuf || !op->Rbuf || !op->LU || !op->Y || !op->flag) {
+    set_error("device allocation failed (ItI leaf operators)");
+    return HPS_ENOMEM;
+  }
+  HPS_TRY(plan_gj(op, &op->leaf_gj, op->Lbuf, op->LU, m, nl));
+  // solve workspace
+  op->g.assign(L + 1, nullptr);
+  op->h.assign(L + 1, nullptr);
+  for (int l = 0; l <= L; ++l) {
+    const long long nodes = 1LL << (2 * l);
+    op->g[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
+    op->h[l] = (double*)op_alloc(op, sizeof(double) * nodes * NR * op->nbl[l], false);
+    if (!op->g[l] || !op->h[l]) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+  }
+  op->v = (double*)op_alloc(op, sizeof(double) * nl * NR * m, false);
+  op->uws = (double*)op_alloc(op, sizeof(double) * nl * NR * m, false);
+  op->fint = (double*)op_alloc(op, sizeof(double) * nl * NR * ni2, false);
+  if (!op->v || !op->uws || !op->fint) { set_error("device allocation failed (solve workspace)"); return HPS_ENOMEM; }
+  // leaf products: Y = B^{-1}(:, Robin rows) P, T = Q H Y; solve: v =
+  // B^{-1}(:, interior rows) f_int, h = Q H v, u = Y g (+ v)
+  add_gemm(op, {make_group(op->LU, (long long)m * m, m, ic->Pr, 0, nr2, op->Y, (long long)m * nb, m, m, nb, nr2, 1.0,
+                           0.0, nl)},
+           &op->gemmYleaf);
+  add_gemm(op, {make_group(ic->QHr, 0, nb, op->Y, (long long)m * nb, m, op->Tleaf, (long long)nb * nb, nb, nb, nb, m,
+                           1.0, 0.0, nl)},
+           &op->gemmTleaf);
+  add_gemm(op, {make_group(op->LU + (long long)nr2 * m, (long long)m * m, m, op->fint, (long long)NR * ni2, ni2, op->v,
+                           (long long)NR * m, m, m, NR, ni2, 1.0, 0.0, nl)},
+           &op->gemmVleaf);
+  add_gemm(op, {make_group(ic->QHr, 0, nb, op->v, (long long)NR * m, m, op->h[L], (long long)NR * nb, nb, nb, NR, m,
+                           1.0, 0.0, nl)},
+           &op->gemmHleaf);
+  add_gemm(op, {make_group(op->Y, (long long)m * nb, m, op->g[L], (long long)NR * nb, nb, op->uws, (long long)NR * m, m,
+                           m, NR, nb, 1.0, 1.0, nl, op->v, (long long)NR * m, m)},
+           &op->gemmUleaf);
+  add_gemm(op, {make_group(op->Y, (long long)m * nb, m, op->g[L], (long long)NR * nb, nb, op->uws, (long long)NR * m, m,
+                           m, NR, nb, 1.0, 0.0, nl)},
+           &op->gemmUleaf0);
+  {
+    BlockOp o = make_op(0, op->nbl[0], op->nbl[0], 0);
+    op_src(o, 0, 0, op->nbl[0]);
+    add_copy(op, {o}, &op->copyRoot);
+  }
+  // merge-level build workspace and the identity for W = I - D12 D21
+  {
+    long long need = 0;
+    int wmax = 1;
+    for (int lev = 0; lev < L; ++lev) {
+      const int n = op->nbl[lev + 1] / 4;
+      need = std::max(need, iti_level_ws_bytes(n, 1LL << (2 * lev)));
+      wmax = std::max(wmax, 4 * n);
+    }
+    op->lvl_ws = (char*)op_alloc(op, (size_t)need, false);
+    op->ident = (double*)op_alloc(op, sizeof(double) * (size_t)wmax * wmax, false);
+    if (!op->lvl_ws || !op->ident) { set_error("device allocation failed (ItI merge workspace)"); return HPS_ENOMEM; }
+    op->lvl_ws_bytes = need;
+    op->ident_ld = wmax;
+    std::vector<double> I((size_t)wmax * wmax, 0.0);
+    for (int i = 0; i < wmax; ++i) I[(size_t)i * wmax + i] = 1.0;
+    HPS_HIP_TRY(hipMemcpy(op->ident, I.data(), sizeof(double) * I.size(), hipMemcpyHostToDevice));
+  }
+  op->levels.assign(L, LevelPlan());
+  for (int lev = L - 1; lev >= 0; --lev) {
+    LevelPlan& P = op->levels[lev];
+    op->lvl_cur = 0;
+    P.lev = lev;
+    P.nm = 1LL << (2 * lev);
+    P.nbc = op->nbl[lev + 1];
+    P.nbp = op->nbl[lev];
+    P.n = P.nbc / 4;
+    const int n = P.n, w = 4 * n, mi = 8 * n, nbc = P.nbc, nbp = P.nbp;
+    P.m = mi;
+    const long long nm = P.nm, childT = (long long)nbc * nbc;
+    P.Z = (double*)op_alloc(op, sizeof(double) * nm * mi * mi);
+    P.S = (double*)op_alloc(op, sizeof(double) * nm * mi * nbp);
+    P.Bnz = (double*)op_alloc(op, sizeof(double) * nm * nbp * mi);
+    if (lev > 0) P.Tp = op->Tbuf[(L - lev) % 2];
+    P.D12 = (double*)lvl_take(op, sizeof(double) * nm * w * w);
+    P.D21 = (double*)lvl_take(op, sizeof(double) * nm * w * w);
+    P.Dbuf = (double*)lvl_take(op, sizeof(double) * nm * w * w);
+    P.Winv = (double*)lvl_take(op, sizeof(double) * nm * w * w);
+    P.Cm = (double*)lvl_take(op, sizeof(double) * nm * mi * nbp);
+    P.hint = (double*)op_alloc(op, sizeof(double) * nm * NR * mi, false);
+    P.gt = (double*)op_alloc(op, sizeof(double) * nm * NR * mi, false);
+    P.gint = (double*)op_alloc(op, sizeof(double) * nm * NR * mi, false);
+    if (!P.Z || !P.S || !P.Bnz || !P.D12 || !P.D21 || !P.Dbuf || !P.Winv || !P.Cm || !P.hint || !P.gt || !P.gint) {
+      set_error("device allocation failed (ItI merge level)");
+      return HPS_ENOMEM;
+    }
+    HPS_TRY(plan_gj(op, &P.gj, P.Dbuf, P.Winv, w, nm, true));
+    // D12 (rows: unknowns 0-3, columns: unknowns 4-7) and D21 (the reverse)
+    for (int half = 0; half < 2; ++half) {
+      std::vector<BlockOp> ops;
+      for (int r = 0; r < 4; ++r)
+        for (int s = 0; s < 4; ++s) {
+          const int k = half * 4 + r, k2 = (1 - half) * 4 + s;
+          BlockOp o = make_op((long long)r * n + (long long)s * n * w, w, n, n);
+          const int y = kItiUnk[k][2];
+          if (kItiUnk[k2][0] == y)
+            op_src(o, 0, y * childT + (long long)kItiUnk[k][3] * n + (long long)kItiUnk[k2][1] * n * nbc, nbc);
+          ops.push_back(o);
+        }
+      add_copy(op, ops, half == 0 ? &P.copyD : &P.copyD21);
+    }
+    // W = I - D12 D21
+    add_gemm(op, {make_group(P.D12, (long long)w * w, w, P.D21, (long long)w * w, w, P.Dbuf, (long long)w * w, w, w, w,
+                             w, -1.0, 1.0, nm, op->ident, 0, op->ident_ld)},
+             &P.gemmW);
+    // Z = D^{-1} (eq. ItI_D_inv): Z11 = W^{-1}, Z12 = -W^{-1} D12,
+    // Z21 = -D21 W^{-1}, Z22 = I - D21 Z12
+    {
+      BlockOp o = make_op(0, mi, w, w);
+      op_src(o, 0, 0, w);
+      add_copy(op, {o}, &P.copyZ11);
+    }
+    add_gemm(op, {make_group(P.Winv, (long long)w * w, w, P.D12, (long long)w * w, w, P.Z + (long long)w * mi,
+                             (long long)mi * mi, mi, w, w, w, -1.0, 0.0, nm),
+                  make_group(P.D21, (long long)w * w, w, P.Winv, (long long)w * w, w, P.Z + w, (long long)mi * mi, mi,
+                             w, w, w, -1.0, 0.0, nm)},
+             &P.gemmZ1);
+    add_gemm(op, {make_group(P.D21, (long long)w * w, w, P.Z + (long long)w * mi, (long long)mi * mi, mi,
+                             P.Z + w + (long long)w * mi, (long long)mi * mi, mi, w, w, w, -1.0, 1.0, nm, op->ident, 0,
+                             op->ident_ld)},
+             &P.gemmZPP);
+    // C (rows: unknowns, columns: parent groups); S = -Z C
+    {
+      std::vector<BlockOp> ops;
+      for (int k = 0; k < 8; ++k)
+        for (int gj = 0; gj < 8; ++gj) {
+          BlockOp o = make_op((long long)k * n + (long long)gj * n * mi, mi, n, n);
+          const int y = kItiUnk[k][2];
+          if (G.group_child[gj] == y)
+            op_src(o, 0, y * childT + (long long)kItiUnk[k][3] * n + (long long)G.group_face[gj] * n * nbc, nbc);
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.copyC);
+    }
+    add_gemm(op, {make_group(P.Z, (long long)mi * mi, mi, P.Cm, (long long)mi * nbp, mi, P.S, (long long)mi * nbp, mi,
+                             mi, nbp, mi, -1.0, 0.0, nm)},
+             &P.gemmS);
+    // B (rows: parent groups, columns: unknowns) and A (parent groups)
+    {
+      std::vector<BlockOp> ops;
+      for (int gi = 0; gi < 8; ++gi)
+        for (int k = 0; k < 8; ++k) {
+          BlockOp o = make_op((long long)gi * n + (long long)k * n * nbp, nbp, n, n);
+          const int c = G.group_child[gi];
+          if (kItiUnk[k][0] == c)
+            op_src(o, 0, c * childT + (long long)G.group_face[gi] * n + (long long)kItiUnk[k][1] * n * nbc, nbc);
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.copyB);
+    }
+    if (P.Tp) {
+      std::vector<BlockOp> ops;
+      for (int gi = 0; gi < 8; ++gi)
+        for (int gj = 0; gj < 8; ++gj) {
+          BlockOp o = make_op((long long)gi * n + (long long)gj * n * nbp, nbp, n, n);
+          const int c = G.group_child[gi];
+          if (G.group_child[gj] == c)
+            op_src(o, 0, c * childT + (long long)G.group_face[gi] * n + (long long)G.group_face[gj] * n * nbc, nbc);
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.fillT);
+      add_gemm(op, {make_group(P.Bnz, (long long)nbp * mi, nbp, P.S, (long long)mi * nbp, mi, P.Tp, (long long)nbp * nbp,
+                               nbp, nbp, nbp, mi, 1.0, 1.0, nm, P.Tp, (long long)nbp * nbp, nbp)},
+               &P.gemmT);
+    }
+    // solve: h_int, g~ = -Z h_int, h = h_ext + B g~, g_int = S g + g~
+    const long long hstride_c = (long long)NR * nbc;
+    {
+      std::vector<BlockOp> ops;
+      for (int k = 0; k < 8; ++k) {
+        BlockOp o = make_op((long long)k * n, mi, n, 0);
+        op_src(o, 0, kItiUnk[k][2] * hstride_c + (long long)kItiUnk[k][3] * n, nbc);
+        ops.push_back(o);
+      }
+      add_copy(op, ops, &P.copyHint);
+    }
+    add_gemm(op, {make_group(P.Z, (long long)mi * mi, mi, P.hint, (long long)NR * mi, mi, P.gt, (long long)NR * mi, mi,
+                             mi, NR, mi, -1.0, 0.0, nm)},
+             &P.gemmGt);
+    if (lev > 0) {
+      std::vector<BlockOp> ops;
+      for (int gi = 0; gi < 8; ++gi) {
+        BlockOp o = make_op((long long)gi * n, nbp, n, 0);
+        op_src(o, 0, G.group_child[gi] * hstride_c + (long long)G.group_face[gi] * n, nbc);
+        ops.push_back(o);
+      }
+      add_copy(op, ops, &P.copyHext);
+      add_gemm(op, {make_group(P.Bnz, (long long)nbp * mi, nbp, P.gt, (long long)NR * mi, mi, op->h[lev],
+                               (long long)NR * nbp, nbp, nbp, NR, mi, 1.0, 1.0, nm, op->h[lev], (long long)NR * nbp,
+                               nbp)},
+               &P.gemmHp);
+    }
+    add_gemm(op, {make_group(P.S, (long long)mi * nbp, mi, op->g[lev], (long long)NR * nbp, nbp, P.gint,
+                             (long long)NR * mi, mi, mi, NR, nbp, 1.0, 1.0, nm, P.gt, (long long)NR * mi, mi)},
+             &P.gemmDown);
+    {
+      std::vector<BlockOp> ops;
+      for (int c = 0; c < 4; ++c)
+        for (int f = 0; f < 4; ++f) {
+          BlockOp o = make_op(c * hstride_c + (long long)f * n, nbc, n, 0);
+          if (G.group_of[c][f] >= 0) {
+            op_src(o, 0, (long long)G.group_of[c][f] * n, nbp);
+          } else {
+            int k = 0;
+            while (!(kItiUnk[k][0] == c && kItiUnk[k][1] == f)) ++k;
+            op_src(o, 1, (long long)k * n, mi);
+          }
+          ops.push_back(o);
+        }
+      add_copy(op, ops, &P.copyGchild);
+    }
+  }
+  return finish_plan(op);
+}
+
+int run_build_iti(hps_op* op, const double* coeffs, hipStream_t st) {
+  const int L = op->tree.depth;
+  HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
+  stage_begin(op, "leaf_factor", st);
+  HPS_TRY(iti_leaf_assemble_launch(coeffs, op->cst->D1, op->cst->D2, op->ic->Gr, op->ic->Ii, op->p, op->nl,
+                                   op->Rbuf, op->Lbuf, st));
+  HPS_TRY(run_gj(op, op->leaf_gj, st));
+  stage_end(op, st);
+  stage_begin(op, "leaf_T", st);
+  HPS_TRY(run_gemm(op, op->gemmYleaf, st));
+  HPS_TRY(run_gemm(op, op->gemmTleaf, st));
+  stage_end(op, st);
+  static const char* names[] = {"merge_l0", "merge_l1", "merge_l2", "merge_l3", "merge_l4", "merge_l5",
+                                "merge_l6", "merge_l7", "merge_l8", "merge_l9", "merge_l10", "merge_l11"};
+  for (int lev = L - 1; lev >= 0; --lev) {
+    LevelPlan& P = op->levels[lev];
+    const double* Tchild = lev == L - 1 ? op->Tleaf : op->levels[lev + 1].Tp;
+    const long long cs = 4LL * P.nbc * P.nbc, w = 4LL * P.n, mi = P.m;
+    stage_begin(op, names[lev < 12 ? lev : 11], st);
+    HPS_TRY(run_copy(op, P.copyD, 0, P.D12, w * w, Tchild, cs, nullptr, 0, P.nm, st));
+    HPS_TRY(run_copy(op, P.copyD21, 0, P.D21, w * w, Tchild, cs, nullptr, 0, P.nm, st));
+    HPS_TRY(run_gemm(op, P.gemmW, st));
+    HPS_TRY(run_gj(op, P.gj, st));
+    HPS_TRY(run_copy(op, P.copyZ11, 0, P.Z, mi * mi, P.Winv, w * w, nullptr, 0, P.nm, st));
+    HPS_TRY(run_gemm(op, P.gemmZ1, st));
+    HPS_TRY(run_gemm(op, P.gemmZPP, st));
+    HPS_TRY(run_copy(op, P.copyC, 0, P.Cm, mi * P.nbp, Tchild, cs, nullptr, 0, P.nm, st));
+    HPS_TRY(run_gemm(op, P.gemmS, st));
+    HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)P.nbp * mi, Tchild, cs, nullptr, 0, P.nm, st));
+    if (P.Tp) {
+      HPS_TRY(run_copy(op, P.fillT, 0, P.Tp, (long long)P.nbp * P.nbp, Tchild, cs, nullptr, 0, P.nm, st));
+      HPS_TRY(run_gemm(op, P.gemmT, st));
+    }
+    stage_end(op, st);
+  }
+  return HPS_OK;
+}
+
+int run_solve_iti_chunk(hps_op* op, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st) {
+  const int L = op->tree.depth, NR = op->NR;
+  stage_begin(op, "solve", st);
+  HPS_TRY(run_copy(op, op->copyRoot, nrhs, op->g[0], 0, bdry, 0, nullptr, 0, 1, st));
+  if (src) {
+    HPS_TRY(iti_gather_src_launch(src, op->ic->Iir, op->Rbuf, op->ni, op->npts, op->nl, nrhs, NR, op->fint, st));
+    HPS_TRY(run_gemm(op, op->gemmVleaf, st, nrhs));
+    HPS_TRY(run_gemm(op, op->gemmHleaf, st, nrhs));
+    for (int lev = L - 1; lev >= 0; --lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_TRY(run_copy(op, P.copyHint, nrhs, P.hint, (long long)NR * P.m, op->h[lev + 1], 4LL * NR * P.nbc, nullptr, 0,
+                       P.nm, st));
+      HPS_TRY(run_gemm(op, P.gemmGt, st, nrhs));
+      if (lev > 0) {
+        HPS_TRY(run_copy(op, P.copyHext, nrhs, op->h[lev], (long long)NR * P.nbp, op->h[lev + 1], 4LL * NR * P.nbc,
+                         nullptr, 0, P.nm, st));
+        HPS_TRY(run_gemm(op, P.gemmHp, st, nrhs));
+      }
+    }
+  } else {
+    for (int lev = 0; lev < L; ++lev) {
+      LevelPlan& P = op->levels[lev];
+      HPS_HIP_TRY(hipMemsetAsync(P.gt, 0, sizeof(double) * P.nm * NR * P.m, st));
+    }
+  }
+  for (int lev = 0; lev < L; ++lev) {
+    LevelPlan& P = op->levels[lev];
+    HPS_TRY(run_gemm(op, P.gemmDown, st, nrhs));
+    HPS_TRY(run_copy(op, P.copyGchild, nrhs, op->g[lev + 1], 4LL * NR * P.nbc, op->g[lev], (long long)NR * P.nbp,
+                     P.gint, (long long)NR * P.m, P.nm, st));
+  }
+  HPS_TRY(run_gemm(op, src ? op->gemmUleaf : op->gemmUleaf0, st, nrhs));
+  HPS_TRY(leaf_scatter_int_launch(op->uws, op->ic->ident, op->npts, op->npts, op->nl, nrhs, NR, u, st));
+  stage_end(op, st);
   return HPS_OK;
 }
 
@@ -1723,6 +2169,7 @@ void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak) {
 
 int hps_level_info(hps_op_t* op, hps_level_info_t* out, int cap) {
   if (!op || (cap > 0 && !out)) { set_error("op must be non-NULL (and out when cap > 0)"); return -HPS_EINVAL; }
+  if (op->iti) { set_error("ItI merges invert W with pivoting over all of W and run no probes"); return -HPS_EUNSUPPORTED; }
   const int rc = collect_info(op);
   if (rc != HPS_OK) return -rc;
   const int n = std::min(cap, (int)op->info.size());
@@ -1862,6 +2309,57 @@ int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int 
   return HPS_OK;
 }
 
+int hps_build_iti(const hps_tree_t* tree, int p, double eta, const double* coeffs, int flags, void* stream,
+                  hps_op_t** out) {
+  if (out) *out = nullptr;
+  HPS_TRY(check_tree(tree, p));
+  if (!coeffs || !out) { set_error("coeffs and out must not be NULL"); return HPS_EINVAL; }
+  if (tree->dim != 2) { set_error("the ItI variant is implemented for 2D trees"); return HPS_EUNSUPPORTED; }
+  if (!(eta > 0.0) || !std::isfinite(eta)) { set_error("eta must be positive and finite"); return HPS_EINVAL; }
+  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_ROOT_T)) {
+    set_error("HPS_FLAG_FP32_COPY and HPS_FLAG_ROOT_T are not available for the ItI variant");
+    return HPS_EUNSUPPORTED;
+  }
+  hps_op* op = new hps_op();
+  op->tree = *tree;
+  op->p = p;
+  op->d = 2;
+  op->nd = 4;
+  op->flags = flags & (HPS_FLAG_NO_CHECK | HPS_FLAG_TIMING);
+  op->nl = 1LL << (2 * tree->depth);
+  op->npts = 2 * p * p;
+  op->ni = 2 * (p - 2) * (p - 2);
+  op->ne = 2 * (4 * p - 4);
+  op->nb = 2 * 4 * (p - 2);
+  op->r = (tree->hi - tree->lo) / 2.0 / (double)(1LL << tree->depth);
+  op->stream = (hipStream_t)stream;
+  op->iti = true;
+  op->eta = eta;
+  int rc = get_consts(2, p, op->r, &op->cst);
+  if (rc == HPS_OK) rc = get_iti_consts(p, op->r, eta, &op->ic);
+  if (rc == HPS_OK) rc = plan_iti(op);
+  if (rc == HPS_OK) rc = run_build_iti(op, coeffs, op->stream);
+  if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) {
+    int hflag[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+    if (e != hipSuccess) {
+      set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
+      rc = HPS_EDEVICE;
+    } else if (hflag[0] || hflag[1]) {
+      set_error("zero or non-finite pivot in an ItI leaf matrix B or a merge matrix W");
+      rc = HPS_ESINGULAR;
+    }
+  }
+  if (rc != HPS_OK) {
+    if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(op->stream);
+    hps_free(op);
+    return rc;
+  }
+  *out = op;
+  return HPS_OK;
+}
+
 int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, int precision, void* stream) {
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
   if (precision != HPS_FP64 && precision != HPS_FP32_REFINED) { set_error("unknown precision"); return HPS_EINVAL; }
@@ -1876,6 +2374,14 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
   }
   hipStream_t st = (hipStream_t)stream;
   clear_stages(op);
+  if (op->iti) {
+    const long long nbr = op->nbl[0], field = op->nl * op->npts;
+    for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
+      const int k = std::min(op->NR, nrhs - r0);
+      HPS_TRY(run_solve_iti_chunk(op, bdry + r0 * nbr, src ? src + r0 * field : nullptr, u + r0 * field, k, st));
+    }
+    return HPS_OK;
+  }
   if (op->sub) {
     const long long nbr = op->nbl[0], field = op->sub->rstride;
     for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
@@ -1898,7 +2404,10 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
 
 int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, void* stream) {
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
-  if (op->sub) { set_error("operators built with subtree recomputation solve through hps_solve"); return HPS_EUNSUPPORTED; }
+  if (op->sub || op->iti) {
+    set_error("the allocation-free solve serves DtN operators built by hps_build");
+    return HPS_EUNSUPPORTED;
+  }
   if (!op->static_ok) {
     char buf[200];
     std::snprintf(buf, sizeof(buf),
@@ -1931,6 +2440,7 @@ int hps_refine_sweeps(hps_op_t* op, int sweeps) {
 
 int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, void* stream) {
   if (!op || !w || !lam_src || nrhs < 1) { set_error("op, w, lam_src must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
+  if (op->iti) { set_error("the adjoint solve is not available for the ItI variant"); return HPS_EUNSUPPORTED; }
   hipError_t pending = hipGetLastError();
   if (pending != hipSuccess) {
     set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
@@ -1956,6 +2466,7 @@ int hps_coeff_grad(hps_op_t* op, const double* u, const double* lam, int nrhs, d
     set_error("op, u, lam, grad must be non-NULL and nrhs >= 1");
     return HPS_EINVAL;
   }
+  if (op->iti) { set_error("the coefficient gradient is not available for the ItI variant"); return HPS_EUNSUPPORTED; }
   // the gradient needs only the leaf differentiation matrices (the same for
   // every leaf of the tree, so a subtree plan's serve for all leaves)
   const hps_op* lo = op->sub ? op->sub : op;
@@ -2066,9 +2577,9 @@ long long hps_debug_download(const hps_op_t* op, int which, int level, double* o
   const int L = op->tree.depth;
   if (which >= 4 && (level < 0 || level >= L)) { set_error("level out of range"); return -HPS_EINVAL; }
   switch (which) {
-    case 0: src = op->LU; n = op->nl * op->ni * op->ni; break;
+    case 0: src = op->LU; n = op->iti ? op->nl * op->npts * op->npts : op->nl * op->ni * op->ni; break;
     case 1: src = op->perm; n = op->nl * op->ni; ints = true; break;
-    case 2: src = op->Y; n = op->nl * op->ni * op->nb; break;
+    case 2: src = op->Y; n = op->iti ? op->nl * op->npts * op->nb : op->nl * op->ni * op->nb; break;
     case 3: src = op->Tleaf; n = op->nl * op->nb * op->nb; break;
     case 4: src = op->levels[level].Z; n = op->levels[level].nm * op->levels[level].m * op->levels[level].m; break;
     case 5: src = op->levels[level].S; n = op->levels[level].nm * op->levels[level].m * op->levels[level].nbp; break;

@@ -23,6 +23,16 @@ struct DevConsts {
   int *Ii = nullptr, *Ie = nullptr, *PosI = nullptr;
 };
 
+// Per-(p, leaf size, eta) constants of the ItI variant, in the real
+// representation of complex matrices (see iti.hip): Robin rows G
+// (2(4p-4) x 2p^2), P (2(4p-4) x 8q), Q H (8q x 2p^2), all column-major;
+// interior points Ii, their real indices Iir (2 per point) and the identity
+// index list of a leaf's 2p^2 reals.
+struct ItiConsts {
+  double *Gr = nullptr, *Pr = nullptr, *QHr = nullptr;
+  int *Ii = nullptr, *Iir = nullptr, *ident = nullptr;
+};
+
 struct GemmCall {
   int first = 0, count = 0;
   long long nblocks = 0, nrblocks = 0;  // GEMM and split-K reduction workgroups
@@ -78,6 +88,13 @@ struct LevelPlan {
   double *py = nullptr, *pr = nullptr, *rho = nullptr, *Wns = nullptr, *Zns = nullptr;
   int* gate = nullptr;
   GemmCall probe1, probe2, nsW, nsZ;
+  // ItI merges (dense blocks of the real representation): D = I + [[0, D12],
+  // [D21, 0]], W = I - D12 D21 (in Dbuf), its inverse, the coupling C;
+  // Z = D^{-1}, S = -Z C, Bnz holds the whole B, copyHext the children's
+  // exterior outgoing data
+  double *D12 = nullptr, *D21 = nullptr, *Winv = nullptr, *Cm = nullptr;
+  CopyCall copyD21, copyZ11, copyC, copyHext;
+  GemmCall gemmW;
   // fp32 copies for the mixed-precision solve
   float *Z32 = nullptr, *S32 = nullptr, *Bnz32 = nullptr;
   float *hint32 = nullptr, *gt32 = nullptr, *gint32 = nullptr;
@@ -143,6 +160,18 @@ struct hps_op {
   char* lvl_ws = nullptr;
   long long lvl_ws_bytes = 0, lvl_cur = 0;
   double* Tbuf[2] = {nullptr, nullptr};
+  // ItI variant (hps_build_iti): complex data in the real representation;
+  // npts, ni, nb count reals (2 per complex value); LU holds (S B)^{-1} per
+  // leaf, S the row equilibration (Robin rows folded into G and P, interior
+  // row scales in Rbuf),
+  // uws the leaf solutions before they are scattered to the caller's layout,
+  // ident an identity matrix (ident_ld x ident_ld) for W = I - D12 D21
+  bool iti = false;
+  double eta = 0.0;
+  hps::ItiConsts* ic = nullptr;
+  double *uws = nullptr, *ident = nullptr;
+  int ident_ld = 0;
+  hps::GemmCall gemmUleaf, gemmUleaf0;
   std::vector<double*> g, h;           // per tree level 0..L: [nodes][NR][nb(level)]
   std::vector<int> nbl;                // boundary size per tree level
   double* v = nullptr;                 // [nl][NR][ni]

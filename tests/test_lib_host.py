@@ -138,3 +138,19 @@ def test_subtree_build_arguments_rejected():
         assert L.hps_last_error()
     t = hp.tree(2, 3)
     assert L.hps_build_subtrees(ctypes.byref(t), 8, None, 0, 1, None, ctypes.byref(h)) == hp.HPS_EINVAL
+
+
+def test_iti_build_arguments_rejected():
+    # argument checks of hps_build_iti return before any device work
+    import numpy as np
+    L = hp.lib()
+    buf = np.zeros(16)
+    ptr = ctypes.c_void_p(buf.ctypes.data)
+    h = ctypes.c_void_p()
+    cases = [(hp.tree(3, 2), 1.0, 0, hp.HPS_EUNSUPPORTED),
+             (hp.tree(2, 2), 0.0, 0, hp.HPS_EINVAL),
+             (hp.tree(2, 2), float("nan"), 0, hp.HPS_EINVAL),
+             (hp.tree(2, 2), 1.0, hp.FLAG_FP32_COPY, hp.HPS_EUNSUPPORTED)]
+    for t, eta, flags, code in cases:
+        rc = L.hps_build_iti(ctypes.byref(t), 8, eta, ptr, flags, None, ctypes.byref(h))
+        assert rc == code and not h.value, (t.dim, eta, flags, rc)

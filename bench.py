@@ -343,6 +343,47 @@ def subtree_recomputation(hp, W):
             "runs": out}
 
 
+def iti_helmholtz(hp, W):
+    """The ItI variant (hps_build_iti) on the paper's ItI problem (Section
+    5.1: Laplace u + (1 + e^{-50|x|^2}) u = f, u_n + i u = g, u = e^{20ix} +
+    e^{30iy}), p = 16, depths 5 and 6: build and one solve (device times),
+    resident bytes and the error against the exact solution at the interior
+    points."""
+    import numpy as np
+    import torch
+    out = []
+    p = 16
+    for L in (5, 6):
+        t = hp.tree(2, L)
+        pts = hp.leaf_points(t, p)
+        bpts = hp.boundary_points(t, p)
+        c, f, g, uex = W.iti_problem(pts, bpts)
+        ct = torch.tensor(c, device="cuda:0")
+        ft = torch.tensor(f[None], device="cuda:0")
+        gt = torch.tensor(g[None], device="cuda:0")
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record()
+        op = hp.build_iti(t, p, ct, 1.0)
+        e[1].record()
+        u = op.solve(gt, ft)
+        e[2].record()
+        e[2].synchronize()
+        ms_solve = _median_ms(lambda: op.solve(gt, ft, out=u), reps=3)
+        resident = op.nbytes
+        op.free()
+        q = (np.arange(p * p) % p > 0) & (np.arange(p * p) % p < p - 1) & \
+            (np.arange(p * p) // p > 0) & (np.arange(p * p) // p < p - 1)
+        uu = u[0].cpu().numpy()[:, q]
+        err = float(np.abs(uu - uex[:, q]).max() / np.abs(uex[:, q]).max())
+        out.append({"depth": L, "p": p, "unknowns": int(4 ** L * p * p), "build_ms": e[0].elapsed_time(e[1]),
+                    "solve_ms": ms_solve, "first_solve_ms": e[1].elapsed_time(e[2]),
+                    "resident_GB": resident / 1e9, "rel_err_vs_exact": err})
+        del ct, ft, gt, u
+        torch.cuda.empty_cache()
+    return {"workload": "ItI variant, paper's ItI problem (eta = 1), p=16", "runs": out}
+
+
 def misfit_gradients(hp, W, with_oracle: bool):
     """Misfit gradient workload: J(q) = ||E u(q) - u_obs||^2 at 256 points,
     2D Helmholtz k = 20, depth 5, p = 16, 32 seeded fields q: per field a
@@ -616,6 +657,7 @@ def main():
         out["divgrad3d"] = divgrad_3d(hp, W)
         out["misfit_gradient"] = misfit_gradients(hp, W, with_oracle=not args.no_cpu_baseline)
         out["subtree_recomputation"] = subtree_recomputation(hp, W)
+        out["iti"] = iti_helmholtz(hp, W)
     if not args.no_serving:
         out["serving"] = serving(hp, W)
     if not args.no_cpu_baseline:

@@ -260,6 +260,25 @@ def poly5_problem(pts: np.ndarray, bpts: np.ndarray):
     return c, f, poly5(bpts)[0], u
 
 
+def iti_problem(pts: np.ndarray, bpts: np.ndarray, lo: float = -1.0, hi: float = 1.0):
+    """The paper's ItI test problem (Section 5.1, eq. ItI_problem):
+    Laplace u + (1 + e^{-50 |x|^2}) u = f on [-1, 1]^2 with Robin data
+    u_n + i u = g, manufactured from u = e^{20 i x} + e^{30 i y}.  Returns
+    real coefficients [leaf, term, point], complex f at the leaf points,
+    complex g at the root boundary points (outward normal of each point's
+    side) and u at the leaf points."""
+    x, y = pts[..., 0], pts[..., 1]
+    c = coeffs_general2d(pts, {"xx": lambda x, y: np.ones_like(x), "yy": lambda x, y: np.ones_like(x),
+                               "0": lambda x, y: 1.0 + np.exp(-50 * (x ** 2 + y ** 2))})
+    u = np.exp(20j * x) + np.exp(30j * y)
+    f = -400 * np.exp(20j * x) - 900 * np.exp(30j * y) + c[:, _term(2, "0"), :] * u
+    bx, by = bpts[:, 0], bpts[:, 1]
+    ub = np.exp(20j * bx) + np.exp(30j * by)
+    ux, uy = 20j * np.exp(20j * bx), 30j * np.exp(30j * by)
+    un = np.where(np.isclose(by, lo), -uy, np.where(np.isclose(bx, hi), ux, np.where(np.isclose(by, hi), uy, -ux)))
+    return c, f, un + 1j * ub, u
+
+
 # --------------------------------------------------------------------------
 # Per-workload bundles
 # --------------------------------------------------------------------------

@@ -104,11 +104,18 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 // ---------------------------------------------------------------------------
 // device memory: a size-keyed cache of freed blocks, so repeated builds of the
-// same shape reuse their allocations instead of calling hipMalloc again.
+// same shape reuse their allocations instead of calling hipMalloc again.  The
+// cache holds at most kCacheBytes, in blocks of at most kCacheBlock; larger
+// blocks, and blocks beyond that total, go back to the device at once, so
+// that memory freed by the library is available to other allocators (a build
+// of a deep tree hands back hundreds of gigabytes).
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_pool_mu;
 std::multimap<size_t, void*> g_pool_free;
+size_t g_cached = 0;
+constexpr size_t kCacheBytes = 16ull << 30;
+constexpr size_t kCacheBlock = 2ull << 30;
 
 // bytes handed out by dalloc and not returned, and their high-water mark
 size_t g_in_use = 0, g_peak = 0;
@@ -128,6 +135,7 @@ void* dalloc(size_t bytes) {
     if (it != g_pool_free.end()) {
       void* p = it->second;
       g_pool_free.erase(it);
+      g_cached -= bytes;
       count_out(bytes);
       return p;
     }
@@ -136,8 +144,10 @@ void* dalloc(size_t bytes) {
   if (hipMalloc(&p, bytes) != hipSuccess) {
     // release cached blocks and retry once
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    (void)hipDeviceSynchronize();
     for (auto& kv : g_pool_free) (void)hipFree(kv.second);
     g_pool_free.clear();
+    g_cached = 0;
     (void)hipGetLastError();
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
@@ -154,7 +164,12 @@ void dfree(void* p, size_t bytes) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   const size_t b = round_size(bytes ? bytes : 1);
   g_in_use -= b;
+  if (b > kCacheBlock || g_cached + b > kCacheBytes) {
+    (void)hipFree(p);  // callers (hps_free) have waited for the device
+    return;
+  }
   g_pool_free.emplace(b, p);
+  g_cached += b;
 }
 
 // device copies of the precomputed leaf operators, per (d, p, leaf half-width)

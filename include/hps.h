@@ -245,8 +245,10 @@ int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, doubl
  * on shared panels; Section 3): each sweep computes the fp64 residual from
  * the coefficients and applies an fp32 HPS solve to it.  The factorizations
  * themselves are never redone in fp32.  Sets the number of correction sweeps
- * used by later refined solves of `op` (sweeps == 0 only queries); returns
- * the previous value, or a negative error code. */
+ * used by later refined solves of `op` (sweeps == 0 only queries; the
+ * default is 3: each sweep contracts the error by 1e-5 .. 1e-3 depending on
+ * the operator, and two sweeps leave up to 2e-8); returns the previous
+ * value, or a negative error code. */
 int hps_refine_sweeps(hps_op_t* op, int sweeps);
 
 /* Adjoint (transposed) solve.  The solve is linear in its data,

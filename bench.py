@@ -221,9 +221,18 @@ def refined_solve(hp, t, c_d, b_d, s_d):
     ms = _median_ms(lambda: op.solve(b_d, s_d, out=u, precision=hp.FP32_REFINED))
     diff = ((u - u64).abs().amax(dim=(1, 2)) / u64.abs().amax(dim=(1, 2))).max().item()
     op.free()
+    # capacity: fp64 operators freed once the fp32 copies exist
+    op64 = hp.build(t, P, c_d)
+    op32 = hp.build(t, P, c_d, flags=hp.FLAG_FP32_ONLY)
+    u32 = op32.solve(b_d, s_d, precision=hp.FP32_REFINED)
+    same = bool(torch.equal(u32, u))
+    res64, res32 = op64.nbytes, op32.nbytes
+    op64.free()
+    op32.free()
     torch.cuda.synchronize()
     return {"sweeps": sweeps, "solve16_ms": ms, "solves_per_s": NRHS * 1e3 / ms,
-            "max_rel_diff_to_fp64": diff}, u
+            "max_rel_diff_to_fp64": diff, "resident_GB_fp64": res64 / 1e9, "resident_GB_fp32_only": res32 / 1e9,
+            "fp32_only_equals_refined": same}, u
 
 
 def poisson_latency(hp, W):

@@ -55,6 +55,9 @@ enum {
   HPS_FLAG_FP32_COPY = 8,  /* keep fp32 copies of the solve operators (mixed precision) */
   HPS_FLAG_FULL_PIVOT = 16, /* invert every merge matrix D whole with partial pivoting
                                (no block elimination around D's zero blocks; m <= 8192) */
+  HPS_FLAG_FP32_ONLY = 32, /* with HPS_FLAG_FP32_COPY (implied): free the fp64 solve operators
+                              once their fp32 copies exist; the operator then serves only
+                              HPS_FP32_REFINED solves, at about half the resident bytes */
   HPS_FLAG_TEST_NO_REFINE = 1 << 30 /* test hook: skip the Newton-Schulz steps, so that an
                                        inaccurate block inverse takes the fallback below */
 };

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhps.so")
 
 HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_ESINGULAR, HPS_EDEVICE, HPS_EUNSUPPORTED = range(6)
-FLAG_ROOT_T, FLAG_NO_CHECK, FLAG_TIMING, FLAG_FP32_COPY, FLAG_FULL_PIVOT = 1, 2, 4, 8, 16
+FLAG_ROOT_T, FLAG_NO_CHECK, FLAG_TIMING, FLAG_FP32_COPY, FLAG_FULL_PIVOT, FLAG_FP32_ONLY = 1, 2, 4, 8, 16, 32
 FLAG_TEST_NO_REFINE = 1 << 30
 FP64, FP32_REFINED = 0, 1
 

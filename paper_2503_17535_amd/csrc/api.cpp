@@ -1912,7 +1912,11 @@ int add_gemm32(hps_op* op, const GemmCall& c, const Map32& m, GemmCall* out) {
   return HPS_OK;
 }
 
-float* alloc32(hps_op* op, long long n) { return (float*)op_alloc(op, sizeof(float) * std::max(1LL, n)); }
+// fp32 copies of operators count as resident; solve workspaces do not (as for
+// the fp64 solve's)
+float* alloc32(hps_op* op, long long n, bool resident = true) {
+  return (float*)op_alloc(op, sizeof(float) * std::max(1LL, n), resident);
+}
 
 // fp32 copies of the solve operators, fp32 / fp64 workspaces of the refined
 // solve, the coefficient copy for the fp64 residual, leaf adjacency tables.
@@ -1925,11 +1929,11 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
   op->LU32 = alloc32(op, nl * ni * ni);
   op->Y32 = alloc32(op, nl * ni * nb);
   op->Qi32 = alloc32(op, (long long)nb * ni);
-  op->v32 = alloc32(op, nl * NR * ni);
-  op->hx32 = alloc32(op, nl * NR * nb);
-  op->gam = (double*)op_alloc(op, sizeof(double) * nl * NR * nb);
-  op->r1 = (double*)op_alloc(op, sizeof(double) * nl * NR * ni);
-  op->Qu = (double*)op_alloc(op, sizeof(double) * nl * NR * nb);
+  op->v32 = alloc32(op, nl * NR * ni, false);
+  op->hx32 = alloc32(op, nl * NR * nb, false);
+  op->gam = (double*)op_alloc(op, sizeof(double) * nl * NR * nb, false);
+  op->r1 = (double*)op_alloc(op, sizeof(double) * nl * NR * ni, false);
+  op->Qu = (double*)op_alloc(op, sizeof(double) * nl * NR * nb, false);
   op->C2G = (double*)op_alloc(op, sizeof(double) * q * p);
   op->nbr = (int*)op_alloc(op, sizeof(int) * nl * 4);
   op->bidx = (long long*)op_alloc(op, sizeof(long long) * nl * 4);
@@ -1949,8 +1953,8 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
   op->h32.assign(L + 1, nullptr);
   for (int l = 0; l <= L; ++l) {
     const long long n = (1LL << (2 * l)) * NR * op->nbl[l];
-    op->g32[l] = alloc32(op, n);
-    op->h32[l] = alloc32(op, n);
+    op->g32[l] = alloc32(op, n, false);
+    op->h32[l] = alloc32(op, n, false);
     if (!op->g32[l] || !op->h32[l]) { set_error("device allocation failed (fp32 workspace)"); return HPS_ENOMEM; }
     m.add(op->g[l], n, op->g32[l]);
     m.add(op->h[l], n, op->h32[l]);
@@ -1961,9 +1965,9 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
     P.Z32 = alloc32(op, nZ);
     P.S32 = alloc32(op, nS);
     P.Bnz32 = alloc32(op, nB);
-    P.hint32 = alloc32(op, nw);
-    P.gt32 = alloc32(op, nw);
-    P.gint32 = alloc32(op, nw);
+    P.hint32 = alloc32(op, nw, false);
+    P.gt32 = alloc32(op, nw, false);
+    P.gint32 = alloc32(op, nw, false);
     if (!P.Z32 || !P.S32 || !P.Bnz32 || !P.hint32 || !P.gt32 || !P.gint32) {
       set_error("device allocation failed (fp32 merge copies)");
       return HPS_ENOMEM;
@@ -1993,7 +1997,7 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
     HPS_TRY(add_gemm32(op, P.gemmDown, m, &P.gemmDown32));
   }
   if (op->split_elems > 0) {
-    op->splitws32 = alloc32(op, op->split_elems);
+    op->splitws32 = alloc32(op, op->split_elems, false);
     if (!op->splitws32) { set_error("device allocation failed (split-K workspace)"); return HPS_ENOMEM; }
   }
   for (auto& g : op->hgroups32) g.part = g.ksplit > 1 ? op->splitws32 + g.part_off : nullptr;
@@ -2010,6 +2014,34 @@ int setup_fp32(hps_op* op, const double* coeffs, hipStream_t st) {
   HPS_HIP_TRY(hipMemcpy(op->nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice));
   HPS_HIP_TRY(hipMemcpy(op->bidx, bidx.data(), sizeof(long long) * bidx.size(), hipMemcpyHostToDevice));
   op->fp32 = true;
+  return HPS_OK;
+}
+
+// HPS_FLAG_FP32_ONLY: free the fp64 solve operators (leaf LU and Y, per
+// level Z, S and B's blocks) after their fp32 copies were made; the refined
+// solve reads only the copies, the pivot order and the coefficients.
+int drop_fp64(hps_op* op) {
+  HPS_HIP_TRY(hipStreamSynchronize(op->stream));
+  std::vector<void*> drop = {op->LU, op->Y};
+  for (auto& P : op->levels) {
+    drop.push_back(P.Z);
+    drop.push_back(P.S);
+    drop.push_back(P.Bnz);
+    P.Z = P.S = P.Bnz = nullptr;
+  }
+  op->LU = op->Y = nullptr;
+  std::vector<Alloc> keep;
+  for (const Alloc& al : op->allocs) {
+    if (std::find(drop.begin(), drop.end(), al.p) != drop.end()) {
+      op->resident -= round_size(al.bytes);
+      dfree(al.p, al.bytes);
+    } else {
+      keep.push_back(al);
+    }
+  }
+  op->allocs.swap(keep);
+  op->static_ok = false;
+  op->fp64_dropped = true;
   return HPS_OK;
 }
 
@@ -2221,7 +2253,8 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
     hps_free(op);
     return hps_build(tree, p, coeffs, flags | HPS_FLAG_FULL_PIVOT, stream, out);
   }
-  if (rc == HPS_OK && (flags & HPS_FLAG_FP32_COPY)) rc = setup_fp32(op, coeffs, op->stream);
+  if (rc == HPS_OK && (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_FP32_ONLY))) rc = setup_fp32(op, coeffs, op->stream);
+  if (rc == HPS_OK && (flags & HPS_FLAG_FP32_ONLY)) rc = drop_fp64(op);
   if (rc != HPS_OK) {
     if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(op->stream);
     hps_free(op);
@@ -2241,7 +2274,7 @@ int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int 
     set_error("subtree_depth must satisfy 1 <= subtree_depth < depth");
     return HPS_EINVAL;
   }
-  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_ROOT_T)) {
+  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_FP32_ONLY | HPS_FLAG_ROOT_T)) {
     set_error("HPS_FLAG_FP32_COPY and HPS_FLAG_ROOT_T are not available with subtree recomputation");
     return HPS_EUNSUPPORTED;
   }
@@ -2331,7 +2364,7 @@ int hps_build_iti(const hps_tree_t* tree, int p, double eta, const double* coeff
   if (!coeffs || !out) { set_error("coeffs and out must not be NULL"); return HPS_EINVAL; }
   if (tree->dim != 2) { set_error("the ItI variant is implemented for 2D trees"); return HPS_EUNSUPPORTED; }
   if (!(eta > 0.0) || !std::isfinite(eta)) { set_error("eta must be positive and finite"); return HPS_EINVAL; }
-  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_ROOT_T)) {
+  if (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_FP32_ONLY | HPS_FLAG_ROOT_T)) {
     set_error("HPS_FLAG_FP32_COPY and HPS_FLAG_ROOT_T are not available for the ItI variant");
     return HPS_EUNSUPPORTED;
   }
@@ -2382,6 +2415,10 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
     set_error("HPS_FP32_REFINED needs an operator built with HPS_FLAG_FP32_COPY");
     return HPS_EINVAL;
   }
+  if (precision == HPS_FP64 && op->fp64_dropped) {
+    set_error("the fp64 operators were freed (HPS_FLAG_FP32_ONLY): solve with HPS_FP32_REFINED");
+    return HPS_EUNSUPPORTED;
+  }
   hipError_t pending = hipGetLastError();
   if (pending != hipSuccess) {
     set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
@@ -2419,8 +2456,8 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
 
 int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, void* stream) {
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
-  if (op->sub || op->iti) {
-    set_error("the allocation-free solve serves DtN operators built by hps_build");
+  if (op->sub || op->iti || op->fp64_dropped) {
+    set_error("the allocation-free solve serves fp64 DtN operators built by hps_build");
     return HPS_EUNSUPPORTED;
   }
   if (!op->static_ok) {
@@ -2456,6 +2493,7 @@ int hps_refine_sweeps(hps_op_t* op, int sweeps) {
 int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, void* stream) {
   if (!op || !w || !lam_src || nrhs < 1) { set_error("op, w, lam_src must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
   if (op->iti) { set_error("the adjoint solve is not available for the ItI variant"); return HPS_EUNSUPPORTED; }
+  if (op->fp64_dropped) { set_error("the adjoint solve needs the fp64 operators (freed by HPS_FLAG_FP32_ONLY)"); return HPS_EUNSUPPORTED; }
   hipError_t pending = hipGetLastError();
   if (pending != hipSuccess) {
     set_error(std::string("earlier device error: ") + hipGetErrorString(pending));

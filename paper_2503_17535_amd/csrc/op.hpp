@@ -191,6 +191,7 @@ struct hps_op {
   // mixed-precision solve (HPS_FLAG_FP32_COPY): fp32 operator copies and
   // workspaces, fp64 iterate and residuals, leaf adjacency
   bool fp32 = false;
+  bool fp64_dropped = false;                   // HPS_FLAG_FP32_ONLY: fp64 solve operators freed
   int refine_sweeps = 3;
   double* coef = nullptr;                      // [nl][n_terms][npts]
   double* C2G = nullptr;                       // q x p row-major

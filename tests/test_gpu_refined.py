@@ -84,3 +84,34 @@ def test_refined_full_size_helmholtz():
     say("[case] rel err vs oracle after 1/2/3/4 sweeps: " + " ".join(f"{e:.2e}" for e in errs))
     assert errs[2] < TOL_REFINED   # the default is 3 sweeps
     op.free()
+
+
+def test_fp32_only_operator():
+    """HPS_FLAG_FP32_ONLY: the fp64 solve operators are freed after their fp32
+    copies exist.  The operator keeps serving refined solves, bitwise equal
+    to those of an operator that kept both copies, at about half the resident
+    bytes; fp64 solves are refused."""
+    import paper_2503_17535_amd as hp
+    say("[case] fp32-only operator")
+    p, L, nrhs = 16, 4, 3
+    t = hp.tree(2, L)
+    pts = hp.leaf_points(t, p)
+    bpts = hp.boundary_points(t, p)
+    c, bd, src = W.helmholtz_inputs(pts, bpts, 20.0, nrhs)
+    ct = torch.tensor(c, device=DEV)
+    bd_t, src_t = torch.tensor(bd, device=DEV), torch.tensor(src, device=DEV)
+    fp64 = hp.build(t, p, ct)
+    both = hp.build(t, p, ct, flags=hp.FLAG_FP32_COPY)
+    only = hp.build(t, p, ct, flags=hp.FLAG_FP32_ONLY)
+    ub = both.solve(bd_t, src_t, precision=hp.FP32_REFINED)
+    uo = only.solve(bd_t, src_t, precision=hp.FP32_REFINED)
+    torch.cuda.synchronize()
+    say(f"[case] resident MiB: fp64 {fp64.nbytes / 2**20:.1f}, fp64 + fp32 {both.nbytes / 2**20:.1f}, "
+        f"fp32 only {only.nbytes / 2**20:.1f}")
+    assert torch.equal(ub, uo)
+    assert only.nbytes < 0.65 * fp64.nbytes
+    with pytest.raises(hp.HPSError) as e:
+        only.solve(bd_t, src_t)
+    assert e.value.code == hp.HPS_EUNSUPPORTED
+    for op in (fp64, both, only):
+        op.free()

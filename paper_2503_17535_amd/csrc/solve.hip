@@ -151,13 +151,15 @@ constexpr int SRC_PF = 2;
 constexpr int SRC_STAGE = 8;  // right-hand sides per pass of the pivot-order staging
 // src_key(row) gives a row's source key (loaded once per row), src(j, key)
 // the source of rhs j.
-template <int RPT, typename T, class SrcKey, class Src>
+// MAXR: right-hand-side capacity of the wave (registers b[RPT][MAXR])
+template <int RPT, typename T, int MAXR = SRC_MAXR, class SrcKey, class Src>
 __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const int* __restrict__ perm_g,
                                               const int* __restrict__ pos_g, SrcKey src_key, Src src, int NI,
                                               int nrhs, T* __restrict__ v, T* s_y, T* s_stage) {
   constexpr int PF = SRC_PF;
+  constexpr int STAGE = MAXR < SRC_STAGE ? MAXR : SRC_STAGE;
   const int lane = threadIdx.x;
-  T b[RPT][SRC_MAXR];
+  T b[RPT][MAXR];
   int mypos[RPT];
   int permv[RPT];  // perm[lane + 64 i]: any perm entry by readlane, without memory
   int key[RPT];
@@ -174,7 +176,7 @@ __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const in
     for (int i = 0; i < RPT; ++i) {
       const int row = lane + SRCW_THREADS * i;
 #pragma unroll
-      for (int j = 0; j < SRC_MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? src(j, key[i]) : 0.0;
+      for (int j = 0; j < MAXR; ++j) b[i][j] = (row < NI && j < nrhs) ? src(j, key[i]) : 0.0;
     }
     // every load above completes here: otherwise the compiler cannot tell,
     // in the step loops, whether b still has loads pending and waits for all
@@ -183,18 +185,18 @@ __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const in
   } else {
     // fp64 values first; the narrowing conversion comes after one wait for
     // all of them (the empty asm keeps it from moving next to each load)
-    double b0[RPT][SRC_MAXR];
+    double b0[RPT][MAXR];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int row = lane + SRCW_THREADS * i;
 #pragma unroll
-      for (int j = 0; j < SRC_MAXR; ++j) b0[i][j] = (row < NI && j < nrhs) ? (double)src(j, key[i]) : 0.0;
+      for (int j = 0; j < MAXR; ++j) b0[i][j] = (row < NI && j < nrhs) ? (double)src(j, key[i]) : 0.0;
     }
     __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
-      for (int j = 0; j < SRC_MAXR; ++j) {
+      for (int j = 0; j < MAXR; ++j) {
         __asm__ volatile("" : "+v"(b0[i][j]));
         b[i][j] = (T)b0[i][j];
       }
@@ -246,38 +248,38 @@ __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const in
         for (int i = 0; i < RPT; ++i)
           if (i == ip)
 #pragma unroll
-            for (int j = 0; j < SRC_MAXR; ++j) s_y[j] = b[i][j];
+            for (int j = 0; j < MAXR; ++j) s_y[j] = b[i][j];
       }
       __builtin_amdgcn_wave_barrier();
       const bool live = s < NI;  // uniform: the tail of the last group does nothing
-      T y[SRC_MAXR];
+      T y[MAXR];
 #pragma unroll
-      for (int j = 0; j < SRC_MAXR; ++j) y[j] = live ? s_y[j] : T(0);
+      for (int j = 0; j < MAXR; ++j) y[j] = live ? s_y[j] : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const T l = mypos[i] > s ? ring[u][i] : T(0);
 #pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= l * y[j];
+        for (int j = 0; j < MAXR; ++j) b[i][j] -= l * y[j];
       }
       __builtin_amdgcn_wave_barrier();  // s_y is rewritten next step
       fetch_l(u, s + PF);  // refill this slot
     }
   }
   // ---- to pivot order: lane l takes unknowns k = l + 64 i (value of row
-  // perm[k]), staged through LDS SRC_STAGE right-hand sides at a time
+  // perm[k]), staged through LDS STAGE right-hand sides at a time
 #pragma unroll
-  for (int h = 0; h < SRC_MAXR; h += SRC_STAGE) {
+  for (int h = 0; h < MAXR; h += STAGE) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
       if (mypos[i] >= 0)
 #pragma unroll
-        for (int jj = 0; jj < SRC_STAGE; ++jj) s_stage[mypos[i] * SRC_STAGE + jj] = b[i][h + jj];
+        for (int jj = 0; jj < STAGE; ++jj) s_stage[mypos[i] * STAGE + jj] = b[i][h + jj];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int k = lane + SRCW_THREADS * i;
 #pragma unroll
-      for (int jj = 0; jj < SRC_STAGE; ++jj) b[i][h + jj] = k < NI ? s_stage[k * SRC_STAGE + jj] : T(0);
+      for (int jj = 0; jj < STAGE; ++jj) b[i][h + jj] = k < NI ? s_stage[k * STAGE + jj] : T(0);
     }
     __builtin_amdgcn_wave_barrier();  // s_stage is rewritten by the next pass
   }
@@ -306,21 +308,21 @@ __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const in
         for (int i = 0; i < RPT; ++i)
           if (i == ip)
 #pragma unroll
-            for (int j = 0; j < SRC_MAXR; ++j) {
+            for (int j = 0; j < MAXR; ++j) {
               b[i][j] *= dinv;
               s_y[j] = b[i][j];
             }
       }
       __builtin_amdgcn_wave_barrier();
-      T y[SRC_MAXR];
+      T y[MAXR];
 #pragma unroll
-      for (int j = 0; j < SRC_MAXR; ++j) y[j] = live ? s_y[j] : T(0);
+      for (int j = 0; j < MAXR; ++j) y[j] = live ? s_y[j] : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int k = lane + SRCW_THREADS * i;
         const T uu = k < s ? ring[u][i] : T(0);
 #pragma unroll
-        for (int j = 0; j < SRC_MAXR; ++j) b[i][j] -= uu * y[j];
+        for (int j = 0; j < MAXR; ++j) b[i][j] -= uu * y[j];
       }
       __builtin_amdgcn_wave_barrier();
       fetch_u(u, s - PF);
@@ -332,27 +334,30 @@ __device__ __forceinline__ void leaf_src_wave(const T* __restrict__ LU, const in
     const int k = lane + SRCW_THREADS * i;
     if (k >= NI) continue;
 #pragma unroll
-    for (int j = 0; j < SRC_MAXR; ++j)
+    for (int j = 0; j < MAXR; ++j)
       if (j < nrhs) v[(long long)j * NI + k] = b[i][j];
   }
 }
 
-template <int RPT>
-// at least two wavefronts per SIMD: the step loop's latency is hidden by
-// occupancy as much as by the prefetch ring
-__global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void leaf_src_kernel(const double* __restrict__ LUall,
+// at least WPE wavefronts per SIMD: the step loop's latency is hidden by
+// occupancy more than by a deeper prefetch ring (a ring of 4-8 columns at one
+// wavefront per SIMD measured 25 % slower); solves of at most 4 right-hand
+// sides use a narrow instance with fewer registers and more waves
+template <int RPT, int MAXR, int WPE>
+__global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(WPE))) void leaf_src_kernel(const double* __restrict__ LUall,
                                                                 const int* __restrict__ permall,
                                                                 const int* __restrict__ posall,
                                                                 const double* __restrict__ src, const int* __restrict__ Ii,
                                                                 int NI, int npts, long long rstride, int nrhs,
                                                                 double* __restrict__ vout, int NRcap) {
-  __shared__ double s_y[SRC_MAXR];
-  __shared__ double s_stage[RPT * SRCW_THREADS * SRC_STAGE];
+  constexpr int STAGE = MAXR < SRC_STAGE ? MAXR : SRC_STAGE;
+  __shared__ double s_y[MAXR];
+  __shared__ double s_stage[RPT * SRCW_THREADS * STAGE];
   const long long leaf = blockIdx.x;
   const double* f = src + leaf * npts;
   auto key = [=](int k) { return Ii[k]; };
   auto at = [=](int j, int ik) { return f[(long long)j * rstride + ik]; };
-  leaf_src_wave<RPT, double>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, key, at, NI, nrhs,
+  leaf_src_wave<RPT, double, MAXR>(LUall + leaf * (long long)NI * NI, permall + leaf * NI, posall + leaf * NI, key, at, NI, nrhs,
                              vout + leaf * (long long)NRcap * NI, s_y, s_stage);
 }
 
@@ -367,15 +372,29 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
   }
   const int rpt = (NI + SRCW_THREADS - 1) / SRCW_THREADS;
   dim3 grid((unsigned)nl), block(SRCW_THREADS);
-  switch (rpt) {
-    case 1: hipLaunchKernelGGL(leaf_src_kernel<1>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
-    case 2: hipLaunchKernelGGL(leaf_src_kernel<2>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
-    case 3: hipLaunchKernelGGL(leaf_src_kernel<3>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
-    case 4: hipLaunchKernelGGL(leaf_src_kernel<4>, grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, v, NRcap); break;
-    default:
-      set_error("leaf_src: too many interior points");
-      return HPS_EUNSUPPORTED;
+#define HPS_SRC_LAUNCH(R, M, W)                                                                                       \
+  hipLaunchKernelGGL((leaf_src_kernel<R, M, W>), grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, \
+                     v, NRcap)
+  if (rpt < 1 || rpt > 4) {
+    set_error("leaf_src: too many interior points");
+    return HPS_EUNSUPPORTED;
   }
+  if (nrhs <= 4) {
+    switch (rpt) {
+      case 1: HPS_SRC_LAUNCH(1, 4, 4); break;
+      case 2: HPS_SRC_LAUNCH(2, 4, 4); break;
+      case 3: HPS_SRC_LAUNCH(3, 4, 4); break;
+      default: HPS_SRC_LAUNCH(4, 4, 4); break;
+    }
+  } else {
+    switch (rpt) {
+      case 1: HPS_SRC_LAUNCH(1, SRC_MAXR, 2); break;
+      case 2: HPS_SRC_LAUNCH(2, SRC_MAXR, 2); break;
+      case 3: HPS_SRC_LAUNCH(3, SRC_MAXR, 2); break;
+      default: HPS_SRC_LAUNCH(4, SRC_MAXR, 2); break;
+    }
+  }
+#undef HPS_SRC_LAUNCH
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

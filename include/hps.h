@@ -331,6 +331,23 @@ int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap);
 /* Resident device bytes of a built operator. */
 size_t hps_op_bytes(const hps_op_t* op);
 
+/* Allocator callback (optional).  When set, every device block of an
+ * operator (its stored operators, build and solve workspaces) comes from
+ * alloc(bytes, ctx) and goes back through free(ptr, bytes, ctx), so that a
+ * framework's caching allocator (PyTorch's, for example) can supply the
+ * library's memory and account for it.  alloc returns a device pointer
+ * aligned to 256 bytes, or NULL, which the library reports as HPS_ENOMEM
+ * (after freeing what the failed call had allocated).  Both NULL restores the
+ * library's own pool; exactly one NULL is HPS_EINVAL.  The setting applies to
+ * allocations made after the call; every block goes back through the
+ * allocator that supplied it, which must stay valid until the operators built
+ * with it are freed.  free is called only after the device has finished with
+ * the block (hps_free synchronizes the device first).  The small per-(p, leaf
+ * size) constant tables are always the library's own. */
+typedef void* (*hps_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*hps_free_fn)(void* ptr, size_t bytes, void* ctx);
+int hps_set_allocator(hps_alloc_fn alloc, hps_free_fn free, void* ctx);
+
 /* Device memory of the library (all operators and their build workspaces,
  * the peak memory the paper reports for 3D trees, Section 4): bytes currently
  * handed out (in_use) and

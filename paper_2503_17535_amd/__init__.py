@@ -28,7 +28,13 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats",
-           "hps_build_subtrees", "hps_build_iti")
+           "hps_build_subtrees", "hps_build_iti", "hps_set_allocator")
+
+
+# allocator callback types of hps_set_allocator
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_allocator_refs = []  # the installed callbacks stay referenced while the library may call them
 
 
 class HPSError(RuntimeError):
@@ -83,6 +89,7 @@ def lib():
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
         L.hps_build_subtrees.argtypes = [TP, I, P, I, I, P, ctypes.POINTER(P)]
         L.hps_build_iti.argtypes = [TP, I, D, P, I, P, ctypes.POINTER(P)]
+        L.hps_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
         L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
         L.hps_mem_stats.argtypes = [ctypes.POINTER(S), ctypes.POINTER(S), I]
@@ -117,6 +124,44 @@ def lib():
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_allocator(alloc=None, free=None):
+    """hps_set_allocator: alloc(nbytes) -> device pointer (int) or None, and
+    free(ptr, nbytes), called for every device block of the operators built
+    afterwards; both None restores the library's own pool.  Earlier
+    callbacks stay referenced (blocks go back through the allocator that
+    supplied them)."""
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both be None")
+    if alloc is None:
+        _check(lib().hps_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        return
+
+    def _a(n, ctx):
+        try:
+            p = alloc(int(n))
+        except Exception:  # an exception becomes an allocation failure (HPS_ENOMEM)
+            return None
+        return p or None
+
+    def _f(p, n, ctx):
+        free(int(p), int(n))
+    ca, cf = _ALLOC_FN(_a), _FREE_FN(_f)
+    _allocator_refs.append((ca, cf))
+    _check(lib().hps_set_allocator(ca, cf, None))
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device memory through PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / caching_allocator_delete on the
+    current device and stream), or back to the library's pool."""
+    if not enable:
+        set_allocator(None, None)
+        return
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  lambda p, n: torch.cuda.caching_allocator_delete(p))
 
 
 def mem_stats(reset_peak: bool = False) -> tuple[int, int]:

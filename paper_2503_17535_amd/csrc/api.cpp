@@ -127,6 +127,11 @@ void count_out(size_t bytes) {
   if (g_in_use > g_peak) g_peak = g_in_use;
 }
 
+// allocator callback (hps_set_allocator): operator blocks come from it when set
+hps_alloc_fn g_cb_alloc = nullptr;
+hps_free_fn g_cb_free = nullptr;
+void* g_cb_ctx = nullptr;
+
 void* dalloc(size_t bytes) {
   bytes = round_size(bytes ? bytes : 1);
   {
@@ -170,6 +175,43 @@ void dfree(void* p, size_t bytes) {
   }
   g_pool_free.emplace(b, p);
   g_cached += b;
+}
+
+// An operator's block: from the allocator callback when one is set (its
+// free function and context are recorded in *rec), else from the pool.
+void* op_dalloc(size_t bytes, Alloc* rec) {
+  hps_alloc_fn a = nullptr;
+  hps_free_fn f = nullptr;
+  void* ctx = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    a = g_cb_alloc;
+    f = g_cb_free;
+    ctx = g_cb_ctx;
+  }
+  rec->cb_free = nullptr;
+  rec->cb_ctx = nullptr;
+  if (!a) return dalloc(bytes);
+  const size_t b = round_size(bytes ? bytes : 1);
+  void* p = a(b, ctx);  // the callback runs outside the pool lock
+  if (!p) return nullptr;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  count_out(b);
+  rec->cb_free = f;
+  rec->cb_ctx = ctx;
+  return p;
+}
+
+void op_dfree(const Alloc& al) {
+  if (!al.cb_free) {
+    dfree(al.p, al.bytes);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_in_use -= round_size(al.bytes ? al.bytes : 1);
+  }
+  al.cb_free(al.p, round_size(al.bytes ? al.bytes : 1), al.cb_ctx);
 }
 
 // device copies of the precomputed leaf operators, per (d, p, leaf half-width)
@@ -349,9 +391,11 @@ namespace hps {
 namespace {
 
 void* op_alloc(hps_op* op, size_t bytes, bool resident = true) {
-  void* p = dalloc(bytes);
+  Alloc rec{nullptr, bytes, nullptr, nullptr};
+  void* p = op_dalloc(bytes, &rec);
   if (p) {
-    op->allocs.push_back({p, bytes});
+    rec.p = p;
+    op->allocs.push_back(rec);
     if (resident) op->resident += round_size(bytes);
   }
   return p;
@@ -2034,7 +2078,7 @@ int drop_fp64(hps_op* op) {
   for (const Alloc& al : op->allocs) {
     if (std::find(drop.begin(), drop.end(), al.p) != drop.end()) {
       op->resident -= round_size(al.bytes);
-      dfree(al.p, al.bytes);
+      op_dfree(al);
     } else {
       keep.push_back(al);
     }
@@ -2206,6 +2250,18 @@ size_t hps_op_footprint(const hps_tree_t* tree, int p, int flags) {
 }
 
 size_t hps_op_bytes(const hps_op_t* op) { return op ? op->resident + (op->sub ? op->sub->resident : 0) : 0; }
+
+int hps_set_allocator(hps_alloc_fn alloc, hps_free_fn free, void* ctx) {
+  if ((alloc == nullptr) != (free == nullptr)) {
+    set_error("alloc and free must both be set or both be NULL");
+    return HPS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_cb_alloc = alloc;
+  g_cb_free = free;
+  g_cb_ctx = alloc ? ctx : nullptr;
+  return HPS_OK;
+}
 
 void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -2559,7 +2615,7 @@ void hps_free(hps_op_t* op) {
   (void)hipDeviceSynchronize();
   clear_stages(op);
   if (op->sub) hps_free(op->sub);
-  for (auto& a : op->allocs) dfree(a.p, a.bytes);
+  for (auto& a : op->allocs) op_dfree(a);
   delete op;
 }
 

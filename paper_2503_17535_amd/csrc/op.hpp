@@ -104,6 +104,8 @@ struct LevelPlan {
 struct Alloc {
   void* p;
   size_t bytes;
+  hps_free_fn cb_free;  // non-NULL: the block came from an allocator callback
+  void* cb_ctx;
 };
 
 struct TimedStage {

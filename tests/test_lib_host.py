@@ -154,3 +154,14 @@ def test_iti_build_arguments_rejected():
     for t, eta, flags, code in cases:
         rc = L.hps_build_iti(ctypes.byref(t), 8, eta, ptr, flags, None, ctypes.byref(h))
         assert rc == code and not h.value, (t.dim, eta, flags, rc)
+
+
+def test_set_allocator_arguments():
+    # both or neither callback; restoring the pool needs no device
+    L = hp.lib()
+    a = hp._ALLOC_FN(lambda n, ctx: None)
+    assert L.hps_set_allocator(a, hp._FREE_FN(), None) == hp.HPS_EINVAL
+    assert L.hps_set_allocator(hp._ALLOC_FN(), hp._FREE_FN(), None) == hp.HPS_OK
+    with pytest.raises(ValueError):
+        hp.set_allocator(lambda n: 0, None)
+    hp.set_allocator(None, None)

@@ -1,8 +1,8 @@
 """CPU oracle for the HPS hot path — TEST INFRASTRUCTURE ONLY.
 
 A plain, slow, obviously correct fp64 NumPy/SciPy implementation of what the
-GPU library computes, written from the paper (arXiv 2503.17535, Sections 3.1-3.3,
-Appendices A, B and C).  It shares no code with the HIP library and neither
+GPU library computes, written from the paper (arXiv 2503.17535, Sections 3.1-3.3 and
+4.2, Appendices A, B and C).  It shares no code with the HIP library and neither
 imports the other; only the seeded input generators in ``workloads`` serve
 both.
 
@@ -20,6 +20,9 @@ Modules:
   an independent check of ``hps``.
 * ``adjoint``  — transposed solve and the misfit gradient.
 * ``iti``      — the 2D impedance-to-impedance variant (Appendix B), complex128.
+* ``adaptive`` — the adaptive 3D discretization (Section 4.2): refinement
+  criterion, union of trees, level restriction, non-uniform merges with
+  one-to-four / four-to-one Gauss panel operators, adaptive downward pass.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests against
 closed forms, library routines, the dense system or values printed in the

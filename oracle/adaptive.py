@@ -242,7 +242,9 @@ class Panels:
         down = np.zeros((q2, 4 * q2))
         for b in range(q):
             for a in range(q):
-                s1, s2 = int(g[a] > 0.0), int(g[b] > 0.0)
+                # the middle node of an odd rule lies on the seam (the
+                # eigenvalue method leaves it within rounding of 0): lower quadrant
+                s1, s2 = int(g[a] > 1e-12), int(g[b] > 1e-12)
                 j = QUADRANTS.index((s1, s2))
                 t1 = 2.0 * g[a] + (1.0 if s1 == 0 else -1.0)
                 t2 = 2.0 * g[b] + (1.0 if s2 == 0 else -1.0)

@@ -133,6 +133,21 @@ def test_panel_operators_reproduce_polynomials():
     assert np.allclose(pan.down @ np.vstack(pan.up), np.eye(q * q), atol=1e-12)
 
 
+def test_seam_points_read_the_lower_quadrant():
+    # odd q: the middle Gauss node sits on the seam between quadrants; its
+    # four-to-one row uses the lower quadrant's panel (the reading stated in
+    # the module docstring), whatever sign rounding gives the node
+    q = 5
+    pan = A.Panels(q)
+    q2 = q * q
+    mid = q // 2
+    row = pan.down[mid + q * mid]
+    assert np.count_nonzero(row[:q2]) > 0 and np.count_nonzero(row[q2:]) == 0
+    row = pan.down[(q - 1) + q * mid]   # upper in t1, seam in t2 -> quadrant (1, 0)
+    j = A.QUADRANTS.index((1, 0))
+    assert np.count_nonzero(row[j * q2:(j + 1) * q2]) == np.count_nonzero(row) > 0
+
+
 def test_refinement_leaves_polynomials_unrefined():
     p = 6
     f = lambda x: 1.0 + x[:, 0] ** 5 - 2.0 * x[:, 1] ** 3 * x[:, 2] ** 2 + x[:, 0] * x[:, 1] * x[:, 2]

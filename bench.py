@@ -393,6 +393,72 @@ def iti_helmholtz(hp, W):
     return {"workload": "ItI variant, paper's ItI problem (eta = 1), p=16", "runs": out}
 
 
+def adaptive_3d(hp, W):
+    """Section 4.2 on the paper's wavefront problem (Poisson on [0, 1]^3,
+    u = arctan(10 |x - c| - 0.7), centre off the dyadic grid): the adaptive
+    tree (criterion on the GPU), its build (the second one, with the device
+    memory cache warm; host planning included) and solve (device times), root
+    D, peak device memory and error against the exact u, beside the uniform
+    tree of the same finest level where it fits (Section 4.2's table)."""
+    import time
+
+    import numpy as np
+    import torch
+    dev = "cuda:0"
+    funcs = [lambda x: W.wavefront_u(x), lambda x: W.wavefront_f(x)]
+
+    def run(build, pts, bpts):
+        c = torch.tensor(W.coeffs_poisson(pts), device=dev)
+        g = torch.tensor(W.wavefront_u(bpts)[None], device=dev)
+        f = torch.tensor(W.wavefront_f(pts)[None], device=dev)
+        build(c).free()  # warm the library's device memory cache
+        torch.cuda.synchronize()
+        base, _ = hp.mem_stats(reset_peak=True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        op = build(c)
+        e[1].record()
+        e[1].synchronize()
+        u = op.solve(g, f)
+        torch.cuda.synchronize()
+        _, peak = hp.mem_stats()
+        ms_solve = _median_ms(lambda: op.solve(g, f, out=u), reps=3)
+        ue = W.wavefront_u(pts)
+        err = float(np.abs(u[0].cpu().numpy() - ue).max() / np.abs(ue).max())
+        rec = {"build_ms": e[0].elapsed_time(e[1]), "solve_ms": ms_solve, "peak_device_GB": (peak - base) / 1e9,
+               "resident_GB": op.nbytes / 1e9, "rel_err_vs_exact": err}
+        op.free()
+        return rec
+
+    out = []
+    for p, eps, cap in ((8, 1e-4, 4), (10, 1e-5, 3)):
+        t0 = time.perf_counter()
+        t = hp.adaptive_tree(funcs, p, eps, cap)
+        tree_s = time.perf_counter() - t0
+        pts, bpts = t.points(p, 0), t.points(p, 2)
+        box = {}
+
+        def build_a(c, t=t, p=p, box=box):
+            op = hp.build_adaptive(t, p, c)
+            box["D"] = op.root_D
+            return op
+
+        ra = run(build_a, pts, bpts)
+        ra.update({"leaves": t.n_leaves, "levels": sorted({int(x) for x in t.leaves[:, 0]}), "root_D": box["D"],
+                   "tree_s": tree_s})
+        L = int(t.leaves[:, 0].max())
+        tu = hp.tree(3, L, 0.0, 1.0)
+        su = hp.sizes(tu, p)
+        ru = {"leaves": int(su.n_leaves), "root_D": int(su.root_D)}
+        try:
+            ru.update(run(lambda c, tu=tu, p=p: hp.build(tu, p, c), hp.leaf_points(tu, p), hp.boundary_points(tu, p)))
+        except hp.HPSError as e:  # e.g. the root Schur complement beyond the Gauss-Jordan limit
+            ru["skipped"] = str(e)
+        out.append({"p": p, "eps": eps, "max_level": cap, "adaptive": ra, "uniform": ru})
+        torch.cuda.empty_cache()
+    return {"workload": "adaptive 3D, paper's wavefront problem (Poisson, u = arctan(10 r - 0.7))", "runs": out}
+
+
 def misfit_gradients(hp, W, with_oracle: bool):
     """Misfit gradient workload: J(q) = ||E u(q) - u_obs||^2 at 256 points,
     2D Helmholtz k = 20, depth 5, p = 16, 32 seeded fields q: per field a
@@ -677,6 +743,7 @@ def main():
         out["misfit_gradient"] = misfit_gradients(hp, W, with_oracle=not args.no_cpu_baseline)
         out["subtree_recomputation"] = subtree_recomputation(hp, W)
         out["iti"] = iti_helmholtz(hp, W)
+        out["adaptive3d"] = adaptive_3d(hp, W)
     if not args.no_serving:
         out["serving"] = serving(hp, W)
     if not args.no_cpu_baseline:

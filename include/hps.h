@@ -207,6 +207,73 @@ int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int 
 int hps_build_iti(const hps_tree_t* tree, int p, double eta, const double* coeffs, int flags,
                   void* stream, hps_op_t** out);
 
+/* ---- Adaptive 3D discretization (Section 4.2) ----
+ * An adaptive octree over the cube [lo, hi]^3: its leaves as int[n_leaves][4]
+ * = (level, ix, iy, iz), the leaf being the box of side (hi - lo) / 2^level
+ * with lower corner lo + side * (ix, iy, iz), listed in depth-first order
+ * (the eight children of a node in the merge's child order: (x, y, z) offsets
+ * 000, 100, 110, 010, 001, 101, 111, 011).  Leaves must tile the cube, the
+ * root must be split, and face neighbours may differ by at most one level
+ * (the level restriction); levels up to 20.  Host memory. */
+typedef struct {
+  double lo, hi;
+  long long n_leaves;
+  const int* leaves;
+} hps_atree_t;
+
+/* Build over an adaptive octree: the leaf stage of each leaf size (as
+ * hps_build in 3D), then the non-uniform merges.  Each interior interface of
+ * a merge is discretized on the coarser of its two sides, Gauss panel by
+ * panel; where the other side has the four panels of a quadrant split, its
+ * Dirichlet data are the coarse panel's interpolant at its Gauss points and
+ * its Neumann data enter the flux balance through the interpolants of its
+ * four panels evaluated at the coarse Gauss points.  D is inverted by
+ * Gauss-Jordan with partial pivoting over all of D (m <= 8192).
+ *   coeffs  dev  [n_leaves][10][p^3]  coefficient samples in the leaves' order
+ *   flags   HPS_FLAG_TIMING or 0 (others: HPS_EUNSUPPORTED)
+ * The call synchronizes once; HPS_ESINGULAR on a zero or non-finite pivot.
+ * hps_solve then reads bdry as [nrhs][n_root] at the root's Gauss points (in
+ * the order hps_adaptive_points(which = 2) lists them), src / u as
+ * [nrhs][n_leaves][p^3] in the leaves' order; precision HPS_FP64.  The
+ * operator serves hps_solve, hps_free, hps_op_bytes and hps_stage_times; the
+ * adjoint, gradient, allocation-free, batched, level-info and refined-precision
+ * calls return HPS_EUNSUPPORTED. */
+int hps_build_adaptive(const hps_atree_t* tree, int p, const double* coeffs, int flags, void* stream,
+                       hps_op_t** out);
+
+/* Root boundary points of an adaptive operator (return value) and the size of
+ * its root merge matrix D (*d_size, if non-NULL); negative on error. */
+long long hps_adaptive_root_size(const hps_op_t* op, long long* d_size);
+
+/* Points of an adaptive tree (host, [..][3] doubles, x fastest):
+ *   which 0: every leaf's p^3 Chebyshev points [n_leaves][p^3][3];
+ *   which 1: the Chebyshev points of every leaf's eight children
+ *            [n_leaves][8][p^3][3] (the points x_1 of eq. refinement_check);
+ *   which 2: the root's Gauss boundary points [n_root][3] (tree restricted).
+ * hps_adaptive_root_points returns n_root (negative on error). */
+int hps_adaptive_points(const hps_atree_t* tree, int p, int which, double* out);
+long long hps_adaptive_root_points(const hps_atree_t* tree, int p);
+
+/* Refinement criterion, eq. (refinement_check): split[i] = 1 unless
+ * max |f1 - L_8f1 f0| < eps max |f| on leaf i, where f0 [nl][p^3] (dev) are
+ * samples at the leaves' Chebyshev points, f1 [nl][8][p^3] (dev) at their
+ * children's (hps_adaptive_points 0 and 1), L_8f1 the tensor interpolation
+ * from a leaf's points to its children's, and max |f| the largest |f0| over
+ * all leaves given.  split: host [nl].  nl <= 65535.  Synchronizes. */
+int hps_adaptive_check(int p, long long nl, const double* f0, const double* f1, double eps, int* split,
+                       void* stream);
+
+/* Tree edits (host).  Each writes the resulting leaves in depth-first order
+ * to out (int[..][4]) when cap is large enough and returns their number
+ * (larger than cap: nothing written, call again); negative on error.
+ *   split:   every leaf i with split[i] != 0 replaced by its eight children;
+ *   union:   the leaves of the union of two trees (a node is split when
+ *            either tree splits it);
+ *   balance: leaves split until face neighbours differ by at most one level. */
+long long hps_adaptive_split(const int* leaves, long long n, const int* split, int* out, long long cap);
+long long hps_adaptive_union(const int* a, long long na, const int* b, long long nb, int* out, long long cap);
+long long hps_adaptive_balance(const int* leaves, long long n, int* out, long long cap);
+
 /* Solve stage (Algorithm down_pass, with the source entering through the
  * linear upward pass of the particular solution, Section 3):
  *   bdry  dev  [nrhs][n_root_bdry]        Dirichlet data g at the root Gauss points

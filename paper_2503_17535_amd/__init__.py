@@ -28,7 +28,9 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats",
-           "hps_build_subtrees", "hps_build_iti", "hps_set_allocator")
+           "hps_build_subtrees", "hps_build_iti", "hps_set_allocator",
+           "hps_build_adaptive", "hps_adaptive_root_size", "hps_adaptive_points", "hps_adaptive_root_points",
+           "hps_adaptive_check", "hps_adaptive_split", "hps_adaptive_union", "hps_adaptive_balance")
 
 
 # allocator callback types of hps_set_allocator
@@ -46,6 +48,11 @@ class HPSError(RuntimeError):
 class Tree(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("depth", ctypes.c_int),
                 ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
+class ATree(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("n_leaves", ctypes.c_longlong), ("leaves", ctypes.c_void_p)]
 
 
 class Sizes(ctypes.Structure):
@@ -90,6 +97,20 @@ def lib():
         L.hps_build_subtrees.argtypes = [TP, I, P, I, I, P, ctypes.POINTER(P)]
         L.hps_build_iti.argtypes = [TP, I, D, P, I, P, ctypes.POINTER(P)]
         L.hps_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
+        AP = ctypes.POINTER(ATree)
+        L.hps_build_adaptive.argtypes = [AP, I, P, I, P, ctypes.POINTER(P)]
+        L.hps_adaptive_root_size.argtypes = [P, ctypes.POINTER(LL)]
+        L.hps_adaptive_root_size.restype = LL
+        L.hps_adaptive_points.argtypes = [AP, I, I, P]
+        L.hps_adaptive_root_points.argtypes = [AP, I]
+        L.hps_adaptive_root_points.restype = LL
+        L.hps_adaptive_check.argtypes = [I, LL, P, P, D, P, P]
+        L.hps_adaptive_split.argtypes = [P, LL, P, P, LL]
+        L.hps_adaptive_split.restype = LL
+        L.hps_adaptive_union.argtypes = [P, LL, P, LL, P, LL]
+        L.hps_adaptive_union.restype = LL
+        L.hps_adaptive_balance.argtypes = [P, LL, P, LL]
+        L.hps_adaptive_balance.restype = LL
         L.hps_solve.argtypes = [P, P, P, P, I, I, P]
         L.hps_solve_noalloc.argtypes = [P, P, P, P, I, P]
         L.hps_mem_stats.argtypes = [ctypes.POINTER(S), ctypes.POINTER(S), I]
@@ -117,7 +138,8 @@ def lib():
         L.hps_level_info.argtypes = [P, ctypes.POINTER(LevelInfo), I]
         for name in EXPORTS:
             if name not in ("hps_op_footprint", "hps_op_bytes", "hps_free", "hps_last_error", "hps_batcher_free",
-                            "hps_mem_stats",
+                            "hps_mem_stats", "hps_adaptive_root_size", "hps_adaptive_root_points",
+                            "hps_adaptive_split", "hps_adaptive_union", "hps_adaptive_balance",
                             "hps_debug_download", "hps_debug_gemm", "hps_coeff_grad", "hps_interp_weights",
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32"):
@@ -460,3 +482,165 @@ def build_subtrees(t: Tree, p: int, coeffs, subtree_depth: int, flags: int = 0, 
     if subtree_depth < 1:
         raise ValueError("subtree_depth must be >= 1")
     return Operator(t, p, coeffs, flags, stream, subtree_depth=subtree_depth)
+
+
+# ---------------------------------------------------------------------------
+# adaptive 3D discretization (Section 4.2)
+# ---------------------------------------------------------------------------
+def _edit(fn, *args):
+    """Run a tree edit (hps_adaptive_split / union / balance) with a growing
+    output buffer; returns the new leaves [n, 4] (int32)."""
+    cap = 1024
+    while True:
+        out = np.empty((cap, 4), dtype=np.int32)
+        n = fn(*args, out.ctypes.data, cap)
+        if n < 0:
+            _check(int(-n))
+        if n <= cap:
+            return out[:n].copy()
+        cap = int(n)
+
+
+class AdaptiveTree:
+    """Leaves (level, ix, iy, iz) of an octree over [lo, hi]^3 in depth-first
+    order (int32 [n, 4], host)."""
+
+    def __init__(self, leaves, lo: float = 0.0, hi: float = 1.0):
+        self.leaves = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+        self.lo, self.hi = float(lo), float(hi)
+
+    @property
+    def n_leaves(self) -> int:
+        return int(self.leaves.shape[0])
+
+    def struct(self) -> ATree:
+        return ATree(self.lo, self.hi, self.n_leaves, self.leaves.ctypes.data)
+
+    @staticmethod
+    def uniform(depth: int, lo: float = 0.0, hi: float = 1.0) -> "AdaptiveTree":
+        t = AdaptiveTree(np.zeros((1, 4), dtype=np.int32), lo, hi)
+        for _ in range(depth):
+            t = t.split(np.ones(t.n_leaves, dtype=np.int32))
+        return t
+
+    def split(self, flags) -> "AdaptiveTree":
+        flags = np.ascontiguousarray(np.asarray(flags, dtype=np.int32))
+        L = lib()
+        return AdaptiveTree(_edit(L.hps_adaptive_split, self.leaves.ctypes.data, self.n_leaves, flags.ctypes.data),
+                            self.lo, self.hi)
+
+    def union(self, other: "AdaptiveTree") -> "AdaptiveTree":
+        L = lib()
+        return AdaptiveTree(_edit(L.hps_adaptive_union, self.leaves.ctypes.data, self.n_leaves,
+                                  other.leaves.ctypes.data, other.n_leaves), self.lo, self.hi)
+
+    def balance(self) -> "AdaptiveTree":
+        L = lib()
+        return AdaptiveTree(_edit(L.hps_adaptive_balance, self.leaves.ctypes.data, self.n_leaves), self.lo, self.hi)
+
+    def points(self, p: int, which: int = 0) -> np.ndarray:
+        """0: leaf Chebyshev points [n, p^3, 3]; 1: the children's [n, 8, p^3, 3];
+        2: root Gauss boundary points [n_root, 3]."""
+        t = self.struct()
+        if which == 0:
+            out = np.empty((self.n_leaves, p ** 3, 3))
+        elif which == 1:
+            out = np.empty((self.n_leaves, 8, p ** 3, 3))
+        else:
+            n = lib().hps_adaptive_root_points(ctypes.byref(t), p)
+            if n < 0:
+                _check(int(-n))
+            out = np.empty((int(n), 3))
+        _check(lib().hps_adaptive_points(ctypes.byref(t), p, which, out.ctypes.data))
+        return out
+
+
+def adaptive_check(p: int, f0, f1, eps: float, stream=None) -> np.ndarray:
+    """hps_adaptive_check: split flags (int32 [nl]) of eq. refinement_check
+    from samples f0 [nl, p^3] and f1 [nl, 8, p^3] (CUDA float64)."""
+    nl = f0.shape[0]
+    out = np.empty(nl, dtype=np.int32)
+    _check(lib().hps_adaptive_check(p, nl, _dev_ptr(f0, "f0", (nl, p ** 3)), _dev_ptr(f1, "f1", (nl, 8, p ** 3)),
+                                    float(eps), out.ctypes.data, _stream_ptr(stream)))
+    return out
+
+
+def adaptive_tree(funcs, p: int, eps: float, max_level: int, lo: float = 0.0, hi: float = 1.0,
+                  device="cuda:0") -> AdaptiveTree:
+    """Section 4.2's tree: for each function (callable on points [N, 3] -> [N])
+    split every leaf that fails the criterion until none does (or the level
+    cap is reached), then the union of the trees and the level restriction.
+    The criterion runs on the GPU (hps_adaptive_check)."""
+    import torch
+    trees = []
+    for f in funcs:
+        t = AdaptiveTree(np.zeros((1, 4), dtype=np.int32), lo, hi)
+        while True:
+            x0 = t.points(p, 0)
+            x1 = t.points(p, 1)
+            f0 = torch.tensor(np.asarray(f(x0.reshape(-1, 3)), dtype=np.float64).reshape(t.n_leaves, p ** 3),
+                              device=device)
+            f1 = torch.tensor(np.asarray(f(x1.reshape(-1, 3)), dtype=np.float64).reshape(t.n_leaves, 8, p ** 3),
+                              device=device)
+            flags = adaptive_check(p, f0, f1, eps)
+            flags[t.leaves[:, 0] >= max_level] = 0
+            if not flags.any():
+                break
+            t = t.split(flags)
+        trees.append(t)
+    out = trees[0]
+    for t in trees[1:]:
+        out = out.union(t)
+    return out.balance()
+
+
+class AdaptiveOperator:
+    """An operator over an adaptive octree (hps_build_adaptive), resident in
+    device memory."""
+
+    def __init__(self, t: AdaptiveTree, p: int, coeffs, flags: int = 0, stream=None):
+        self.tree, self.p, self.flags = t, p, flags
+        self.n_leaves, self.pts_per_leaf = t.n_leaves, p ** 3
+        ptr = _dev_ptr(coeffs, "coeffs", (t.n_leaves, 10, p ** 3))
+        self._t = t.struct()
+        h = ctypes.c_void_p()
+        _check(lib().hps_build_adaptive(ctypes.byref(self._t), p, ptr, flags, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        d = ctypes.c_longlong()
+        n = lib().hps_adaptive_root_size(self._h, ctypes.byref(d))
+        if n < 0:
+            _check(int(-n))
+        self.n_root_bdry, self.root_D = int(n), int(d.value)
+
+    def solve(self, bdry, src=None, out=None, stream=None):
+        import torch
+        nrhs = bdry.shape[0]
+        shp = (nrhs, self.n_leaves, self.pts_per_leaf)
+        bptr = _dev_ptr(bdry, "bdry", (nrhs, self.n_root_bdry))
+        sptr = None if src is None else _dev_ptr(src, "src", shp)
+        if out is None:
+            out = torch.empty(shp, dtype=torch.float64, device=bdry.device)
+        uptr = _dev_ptr(out, "u", shp)
+        _check(lib().hps_solve(self._h, bptr, sptr, uptr, nrhs, FP64, _stream_ptr(stream)))
+        return out
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().hps_op_bytes(self._h))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_adaptive(t: AdaptiveTree, p: int, coeffs, flags: int = 0, stream=None) -> AdaptiveOperator:
+    """hps_build_adaptive: the adaptive 3D discretization (Section 4.2)."""
+    return AdaptiveOperator(t, p, coeffs, flags, stream)
+

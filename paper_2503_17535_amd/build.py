@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhps.so")
-SOURCES = ["precompute.cpp", "api.cpp", "batch.cpp", "gemm.hip", "leaf2d.hip", "leaf3d.hip", "gj.hip", "solve.hip", "grad.hip", "refine.hip", "guard.hip", "noalloc.hip", "iti.hip"]
+SOURCES = ["precompute.cpp", "api.cpp", "batch.cpp", "gemm.hip", "leaf2d.hip", "leaf3d.hip", "gj.hip", "solve.hip", "grad.hip", "refine.hip", "guard.hip", "noalloc.hip", "iti.hip", "adaptive.cpp", "adaptive.hip"]
 ARCH = "gfx950"
 
 

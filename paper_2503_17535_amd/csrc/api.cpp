@@ -823,7 +823,7 @@ std::vector<const GemmCall*> solve_gemm_calls(hps_op* op) {
 
 int plan_static_solve(hps_op* op) {
   op->static_ok = false;
-  if (op->ext_side > 0 || op->root_h || op->iti) return HPS_OK;  // subtree parts and ItI: not offered
+  if (op->ext_side > 0 || op->root_h || op->iti || op->ad) return HPS_OK;  // subtree parts, ItI, adaptive: not offered
   void* base = nullptr;
   HPS_TRY(static_ws_ptr(&base));
   op->static_base = (char*)base;
@@ -2194,6 +2194,28 @@ int check_tree(const hps_tree_t* t, int p) {
 }
 
 }  // namespace
+
+// helpers for the other host sources (adaptive.cpp)
+void* op_alloc_x(hps_op* op, size_t bytes, bool resident) { return op_alloc(op, bytes, resident); }
+int add_gemm_x(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call) {
+  return add_gemm(op, std::move(groups), call);
+}
+void add_copy_x(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) { add_copy(op, ops, call); }
+int run_gemm_x(hps_op* op, const GemmCall& c, hipStream_t st, int n_override) {
+  if (c.count == 0) return HPS_OK;
+  return run_gemm(op, c, st, n_override);
+}
+int run_copy_x(hps_op* op, const CopyCall& c, int ncols_rt, double* dst, const double* s0, const double* s1,
+               hipStream_t st) {
+  if (c.ntasks == 0) return HPS_OK;
+  return run_copy(op, c, ncols_rt, dst, 0, s0, 0, s1, 0, 1, st);
+}
+int plan_gj_x(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch) {
+  return plan_gj(op, g, A, Z, m, batch, false);
+}
+int run_gj_x(hps_op* op, const GJPlan& g, hipStream_t st) { return run_gj(op, g, st); }
+int get_consts_x(int d, int p, double r, DevConsts** out) { return get_consts(d, p, r, out); }
+int finish_plan_x(hps_op* op) { return finish_plan(op); }
 }  // namespace hps
 
 using namespace hps;
@@ -2271,6 +2293,7 @@ void hps_mem_stats(size_t* in_use, size_t* peak, int reset_peak) {
 }
 
 int hps_level_info(hps_op_t* op, hps_level_info_t* out, int cap) {
+  if (op && op->ad) { set_error("merge-level probe information is not kept for adaptive operators"); return -HPS_EUNSUPPORTED; }
   if (!op || (cap > 0 && !out)) { set_error("op must be non-NULL (and out when cap > 0)"); return -HPS_EINVAL; }
   if (op->iti) { set_error("ItI merges invert W with pivoting over all of W and run no probes"); return -HPS_EUNSUPPORTED; }
   const int rc = collect_info(op);
@@ -2482,6 +2505,10 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
   }
   hipStream_t st = (hipStream_t)stream;
   clear_stages(op);
+  if (op->ad) {
+    if (precision != HPS_FP64) { set_error("adaptive operators solve in fp64"); return HPS_EUNSUPPORTED; }
+    return adaptive_solve(op, bdry, src, u, nrhs, st);
+  }
   if (op->iti) {
     const long long nbr = op->nbl[0], field = op->nl * op->npts;
     for (int r0 = 0; r0 < nrhs; r0 += op->NR) {
@@ -2511,6 +2538,7 @@ int hps_solve(hps_op_t* op, const double* bdry, const double* src, double* u, in
 }
 
 int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, double* u, int nrhs, void* stream) {
+  if (op && op->ad) { set_error("the allocation-free solve serves fp64 DtN operators built by hps_build"); return HPS_EUNSUPPORTED; }
   if (!op || !bdry || !u || nrhs < 1) { set_error("op, bdry, u must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
   if (op->sub || op->iti || op->fp64_dropped) {
     set_error("the allocation-free solve serves fp64 DtN operators built by hps_build");
@@ -2540,6 +2568,7 @@ int hps_solve_noalloc(hps_op_t* op, const double* bdry, const double* src, doubl
 }
 
 int hps_refine_sweeps(hps_op_t* op, int sweeps) {
+  if (op && op->ad) { set_error("adaptive operators have no mixed-precision solve"); return -HPS_EUNSUPPORTED; }
   if (!op || sweeps < 0 || sweeps > 64) { set_error("op must be non-NULL and 0 <= sweeps <= 64"); return -HPS_EINVAL; }
   const int old = op->refine_sweeps;
   if (sweeps > 0) op->refine_sweeps = sweeps;
@@ -2547,6 +2576,7 @@ int hps_refine_sweeps(hps_op_t* op, int sweeps) {
 }
 
 int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* lam_bdry, int nrhs, void* stream) {
+  if (op && op->ad) { set_error("the adjoint solve is not available for adaptive operators"); return HPS_EUNSUPPORTED; }
   if (!op || !w || !lam_src || nrhs < 1) { set_error("op, w, lam_src must be non-NULL and nrhs >= 1"); return HPS_EINVAL; }
   if (op->iti) { set_error("the adjoint solve is not available for the ItI variant"); return HPS_EUNSUPPORTED; }
   if (op->fp64_dropped) { set_error("the adjoint solve needs the fp64 operators (freed by HPS_FLAG_FP32_ONLY)"); return HPS_EUNSUPPORTED; }
@@ -2571,6 +2601,7 @@ int hps_solve_adjoint(hps_op_t* op, const double* w, double* lam_src, double* la
 }
 
 int hps_coeff_grad(hps_op_t* op, const double* u, const double* lam, int nrhs, double* grad, void* stream) {
+  if (op && op->ad) { set_error("the coefficient gradient is not available for adaptive operators"); return HPS_EUNSUPPORTED; }
   if (!op || !u || !lam || !grad || nrhs < 1) {
     set_error("op, u, lam, grad must be non-NULL and nrhs >= 1");
     return HPS_EINVAL;
@@ -2615,6 +2646,7 @@ void hps_free(hps_op_t* op) {
   (void)hipDeviceSynchronize();
   clear_stages(op);
   if (op->sub) hps_free(op->sub);
+  if (op->ad) adaptive_free(op->ad);
   for (auto& a : op->allocs) op_dfree(a);
   delete op;
 }
@@ -2678,6 +2710,7 @@ int hps_debug_gemm(int m, int n, int k, double alpha, const double* a, int lda, 
 }
 
 long long hps_debug_download(const hps_op_t* op, int which, int level, double* out, long long cap) {
+  if (op && op->ad) { set_error("internal buffers of adaptive operators are not exposed"); return -HPS_EUNSUPPORTED; }
   if (!op || !out) { set_error("op and out must not be NULL"); return -HPS_EINVAL; }
   if (hipStreamSynchronize(op->stream) != hipSuccess) { set_error("stream sync failed"); return -HPS_EDEVICE; }
   const void* src = nullptr;

@@ -197,7 +197,7 @@ int hps_solve_batch(hps_batcher_t* b, const hps_batch_item_t* items, int nitems,
     if (!op) { set_error("batch item " + std::to_string(i) + ": op is NULL"); return HPS_EINVAL; }
     if (op->d != 2) { set_error("batched solve supports 2D operators"); return HPS_EUNSUPPORTED; }
     if (op->sub) { set_error("batched solve needs every leaf operator resident (not subtree recomputation)"); return HPS_EUNSUPPORTED; }
-    if (op->iti || op->fp64_dropped) { set_error("batched solve serves fp64 DtN operators"); return HPS_EUNSUPPORTED; }
+    if (op->iti || op->fp64_dropped || op->ad) { set_error("batched solve serves fp64 DtN operators"); return HPS_EUNSUPPORTED; }
     if (it.nrhs < 1 || it.nrhs > std::min(op->NR, kBatchMaxRhs)) {
       set_error("batch item " + std::to_string(i) + ": nrhs must be in 1..16");
       return HPS_EINVAL;

@@ -115,6 +115,12 @@ struct TimedStage {
 
 }  // namespace hps
 
+namespace hps {
+struct AdaptivePlan;  // adaptive 3D operators (adaptive.cpp)
+void adaptive_free(AdaptivePlan* A);
+int adaptive_solve(hps_op* op, const double* bdry, const double* src, double* u, int nrhs, hipStream_t st);
+}  // namespace hps
+
 struct hps_op {
   hps_tree_t tree{};
   int p = 0, d = 0, flags = 0, nd = 0;
@@ -220,6 +226,8 @@ struct hps_op {
   std::vector<hps::Alloc> allocs;
   size_t resident = 0;
   std::vector<hps::TimedStage> stages;
+  // adaptive 3D operator (hps_build_adaptive): its tree, plans and arenas
+  hps::AdaptivePlan* ad = nullptr;
 };
 
 namespace hps {

@@ -165,3 +165,69 @@ def test_set_allocator_arguments():
     with pytest.raises(ValueError):
         hp.set_allocator(lambda n: 0, None)
     hp.set_allocator(None, None)
+
+
+def test_adaptive_tree_edits_match_oracle():
+    # split / balance / union / points of the library against the adaptive oracle (host only)
+    from oracle import adaptive as A
+    t = hp.AdaptiveTree.uniform(1)
+    f = np.zeros(8, np.int32)
+    f[0] = 1
+    t = t.split(f)
+    f = np.zeros(t.n_leaves, np.int32)
+    f[0] = 1
+    t = t.split(f)
+    f = np.zeros(t.n_leaves, np.int32)
+    f[7] = 1
+    t = t.split(f)
+    b = t.balance()
+    ob = A.AdaptiveTree(A.balance(set(map(tuple, t.leaves))))
+    assert [tuple(int(v) for v in k) for k in b.leaves] == ob.leaves
+    assert A.is_balanced(ob) and not A.is_balanced(A.AdaptiveTree(set(map(tuple, t.leaves))))
+    u = hp.AdaptiveTree.uniform(2).union(b)
+    ou = A.AdaptiveTree(A.union([set(A.AdaptiveTree.uniform(2).leaves), set(ob.leaves)]))
+    assert [tuple(int(v) for v in k) for k in u.leaves] == ou.leaves
+    disc = ohps.LeafDisc(3, 6)
+    assert np.array_equal(b.points(6, 0), ob.leaf_points(disc))
+    x1 = b.points(6, 1)
+    for i in (0, 5, b.n_leaves - 1):
+        for c, ch in enumerate(A.children(ob.leaves[i])):
+            assert np.array_equal(x1[i, c], ob.points(disc, ch))
+    c = np.zeros((len(ob.leaves), 10, 216))
+    c[:, 0:3] = -1.0
+    oop = A.build(ob, 6, c)
+    assert np.abs(b.points(6, 2) - A.root_boundary_points(oop)).max() < 1e-15
+
+
+def test_adaptive_build_arguments_rejected():
+    # argument checks of hps_build_adaptive return before any device work
+    L = hp.lib()
+    buf = np.zeros(16)
+    ptr = ctypes.c_void_p(buf.ctypes.data)
+    h = ctypes.c_void_p()
+
+    def build(leaves, p=6, flags=0, lo=0.0, hi=1.0):
+        arr = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+        t = hp.ATree(lo, hi, arr.shape[0], arr.ctypes.data)
+        return L.hps_build_adaptive(ctypes.byref(t), p, ptr, flags, None, ctypes.byref(h))
+
+    good = hp.AdaptiveTree.uniform(1).leaves
+    unbalanced = hp.AdaptiveTree.uniform(1)
+    f = np.zeros(8, np.int32)
+    f[0] = 1
+    unbalanced = unbalanced.split(f)
+    f = np.zeros(unbalanced.n_leaves, np.int32)
+    f[6] = 1  # the child of octant 0 next to octant 1
+    unbalanced = unbalanced.split(f)
+    cases = [(good[::-1], 6, 0, hp.HPS_EINVAL),                 # not depth-first
+             (good[:7], 6, 0, hp.HPS_EINVAL),                   # a hole
+             (np.vstack([good, good[:1]]), 6, 0, hp.HPS_EINVAL),  # a leaf twice
+             ([[0, 0, 0, 0]], 6, 0, hp.HPS_EINVAL),             # no merge
+             (unbalanced.leaves, 6, 0, hp.HPS_EINVAL),          # level restriction
+             (good, 3, 0, hp.HPS_EINVAL),                       # p
+             (good, 6, hp.FLAG_FP32_COPY, hp.HPS_EUNSUPPORTED)]
+    for leaves, p, flags, code in cases:
+        rc = build(leaves, p, flags)
+        assert rc == code and not h.value, (p, flags, rc)
+    assert build(good, 6, 0, lo=1.0, hi=0.0) == hp.HPS_EINVAL
+    assert L.hps_adaptive_check(6, 1, None, None, 1e-3, None, None) == hp.HPS_EINVAL

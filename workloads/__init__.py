@@ -282,6 +282,30 @@ def iti_problem(pts: np.ndarray, bpts: np.ndarray, lo: float = -1.0, hi: float =
 # --------------------------------------------------------------------------
 # Per-workload bundles
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# Adaptive 3D workload (the paper's wavefront problem, Section 5: Poisson on
+# [0, 1]^3 with u = arctan(10 |x - c| - 0.7)).  Its printed centre (1/2, 1/2,
+# 1/2) is a point of every uniform and adaptive grid, where the source has a
+# 1/r singularity; the centre here sits slightly off the dyadic grid.
+# --------------------------------------------------------------------------
+WAVEFRONT_CENTER = (0.5 + 0.0137, 0.5 - 0.0091, 0.5 + 0.0053)
+
+
+def wavefront_u(pts: np.ndarray, center=WAVEFRONT_CENTER) -> np.ndarray:
+    r = np.sqrt(np.sum((pts - np.asarray(center)) ** 2, axis=-1))
+    return np.arctan(10.0 * r - 0.7)
+
+
+def wavefront_f(pts: np.ndarray, center=WAVEFRONT_CENTER) -> np.ndarray:
+    """-Laplace u (the operator of coeffs_poisson): u'' + (2 / r) u' with
+    t = 10 r - 0.7, u' = 10 / (1 + t^2), u'' = -200 t / (1 + t^2)^2."""
+    r = np.sqrt(np.sum((pts - np.asarray(center)) ** 2, axis=-1))
+    t = 10.0 * r - 0.7
+    d1 = 10.0 / (1.0 + t * t)
+    d2 = -200.0 * t / (1.0 + t * t) ** 2
+    return -(d2 + 2.0 * d1 / r)
+
+
 WORKLOADS = {
     1: dict(dim=2, depth=2, p=8, name="poisson2d_L2_p8"),
     2: dict(dim=2, depth=6, p=16, k=40.0, nrhs=16, name="helmholtz2d_k40_L6_p16"),

@@ -431,7 +431,7 @@ def adaptive_3d(hp, W):
         return rec
 
     out = []
-    for p, eps, cap in ((8, 1e-4, 4), (10, 1e-5, 3)):
+    for p, eps, cap in ((8, 1e-4, 4), (10, 1e-5, 3), (12, 1e-5, 3)):
         t0 = time.perf_counter()
         t = hp.adaptive_tree(funcs, p, eps, cap)
         tree_s = time.perf_counter() - t0

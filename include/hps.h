@@ -54,7 +54,7 @@ enum {
   HPS_FLAG_TIMING = 4,     /* record per-stage HIP events (read with hps_stage_times)   */
   HPS_FLAG_FP32_COPY = 8,  /* keep fp32 copies of the solve operators (mixed precision) */
   HPS_FLAG_FULL_PIVOT = 16, /* invert every merge matrix D whole with partial pivoting
-                               (no block elimination around D's zero blocks; m <= 8192) */
+                               (no block elimination around D's zero blocks; m <= 16384) */
   HPS_FLAG_FP32_ONLY = 32, /* with HPS_FLAG_FP32_COPY (implied): free the fp64 solve operators
                               once their fp32 copies exist; the operator then serves only
                               HPS_FP32_REFINED solves, at about half the resident bytes */
@@ -107,7 +107,7 @@ int hps_boundary_points(const hps_tree_t* tree, int p, double* xyz);
  * get up to two Newton-Schulz steps Z <- 2Z - (Z D) Z (each squares I - Z D).
  * If a node stays above 1e-10, or a pivot inside a block is zero, the build
  * is redone with HPS_FLAG_FULL_PIVOT (partial pivoting over all of D); where
- * that is unsupported (m > 8192) hps_build returns HPS_ESINGULAR naming the
+ * that is unsupported (m > 16384) hps_build returns HPS_ESINGULAR naming the
  * level and node. */
 typedef struct {
   int level;            /* tree level of the parents (0 = root)                     */
@@ -190,8 +190,8 @@ int hps_build_subtrees(const hps_tree_t* tree, int p, const double* coeffs, int 
  * complement W = I - D12 D21 (eq. ItI_D_inv), S = -D^{-1} C, T = A + B S.
  * Every corner carries the Robin condition of the side that starts at it on a
  * counterclockwise walk of the leaf boundary (SW: S, SE: E, NE: N, NW: W).
- *   tree    2D (depth limited by W of the root merge: 16 (p - 2) 2^(depth-1)
- *           reals <= 8192, i.e. depth <= 7 at p = 16)
+ *   tree    2D (depth limited by W of the root merge: 8 (p - 2) 2^(depth-1)
+ *           reals <= 16384, i.e. depth <= 8 at p = 16)
  *   eta     impedance parameter, > 0
  *   coeffs  dev  [n_leaves][6][p^2] real coefficient samples (as hps_build)
  *   flags   HPS_FLAG_NO_CHECK, HPS_FLAG_TIMING (others: HPS_EUNSUPPORTED)
@@ -228,7 +228,7 @@ typedef struct {
  * Dirichlet data are the coarse panel's interpolant at its Gauss points and
  * its Neumann data enter the flux balance through the interpolants of its
  * four panels evaluated at the coarse Gauss points.  D is inverted by
- * Gauss-Jordan with partial pivoting over all of D (m <= 8192).
+ * Gauss-Jordan with partial pivoting over all of D (m <= 16384).
  *   coeffs  dev  [n_leaves][10][p^3]  coefficient samples in the leaves' order
  *   flags   HPS_FLAG_TIMING or 0 (others: HPS_EUNSUPPORTED)
  * The call synchronizes once; HPS_ESINGULAR on a zero or non-finite pivot.

@@ -1026,8 +1026,8 @@ int hps_build_adaptive(const hps_atree_t* tree, int p, const double* coeffs, int
   op->nb = o.n_b;
   op->stream = (hipStream_t)stream;
   int rc = build_structure(A, dfs);
-  if (rc == HPS_OK && A.max_m > 8192) {
-    set_error("adaptive tree: a merge matrix D exceeds the Gauss-Jordan limit (m = 8192)");
+  if (rc == HPS_OK && A.max_m > 16384) {
+    set_error("adaptive tree: a merge matrix D exceeds the Gauss-Jordan limit (m = 16384)");
     rc = HPS_EUNSUPPORTED;
   }
   if (rc == HPS_OK) rc = plan_adaptive(op, A);

@@ -587,7 +587,7 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch,
   if (g->small) return HPS_OK;
   g->nb = gj_panel_width(m);
   if (g->nb == 0) {
-    set_error("matrix of size " + std::to_string(m) + " exceeds the blocked Gauss-Jordan limit (8192)");
+    set_error("matrix of size " + std::to_string(m) + " exceeds the blocked Gauss-Jordan limit (16384)");
     return HPS_EUNSUPPORTED;
   }
   const int mnb = gj_panel_max_nb();
@@ -2163,7 +2163,7 @@ int check_build(hps_op* op, bool* retry) {
     if (op->info[lev].block_inverse && (hflag[1] || !(op->info[lev].residual <= kNsAccept))) bad = lev;
   if (bad < 0) return HPS_OK;
   bool full_ok = true;
-  for (const auto& I : op->info) full_ok = full_ok && I.m <= 8192;
+  for (const auto& I : op->info) full_ok = full_ok && I.m <= 16384;
   if (full_ok) {
     *retry = true;
     return HPS_OK;
@@ -2172,7 +2172,7 @@ int check_build(hps_op* op, bool* retry) {
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "merge level %d node %lld: inverse of D (m = %d) by block elimination has probe residual "
-                "%.2e after %d Newton-Schulz steps%s, and m exceeds the whole-D pivoting limit (8192)",
+                "%.2e after %d Newton-Schulz steps%s, and m exceeds the whole-D pivoting limit (16384)",
                 bad, I.worst_node, I.m, I.residual, I.ns_steps, hflag[1] ? " (zero pivot in a block)" : "");
   set_error(buf);
   return HPS_ESINGULAR;

@@ -470,6 +470,7 @@ int gj_panel_width(int m) {
   if (m <= 2048) return 16;
   if (m <= 4096) return 8;
   if (m <= 8192) return 4;
+  if (m <= 16384) return 2;
   return 0;
 }
 int gj_panel_max_nb() { return PANEL_MAX_NB; }
@@ -487,8 +488,10 @@ int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, doubl
     hipLaunchKernelGGL((gj_panel_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else if (m <= 8192)
     hipLaunchKernelGGL((gj_panel_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
+  else if (m <= 16384)
+    hipLaunchKernelGGL((gj_panel_kernel<32, 2>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, flag);
   else {
-    set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
+    set_error("blocked Gauss-Jordan: matrix larger than 16384 not supported");
     return HPS_EUNSUPPORTED;
   }
   HPS_HIP_TRY(hipGetLastError());
@@ -513,8 +516,10 @@ int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double
     hipLaunchKernelGGL((gj_step_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else if (m <= 8192)
     hipLaunchKernelGGL((gj_step_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+  else if (m <= 16384)
+    hipLaunchKernelGGL((gj_step_kernel<32, 2>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
   else {
-    set_error("blocked Gauss-Jordan: matrix larger than 8192 not supported");
+    set_error("blocked Gauss-Jordan: matrix larger than 16384 not supported");
     return HPS_EUNSUPPORTED;
   }
   HPS_HIP_TRY(hipGetLastError());

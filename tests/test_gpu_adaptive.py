@@ -129,6 +129,33 @@ def test_polynomial_exact_across_level_jumps():
     assert err < 1e-11
 
 
+def test_large_root_polynomial_exact():
+    """p = 12 wavefront tree (root D = 8400, beyond 8192: the widest
+    Gauss-Jordan panel instance): a polynomial of per-variable degree p - 3
+    is reproduced to rounding."""
+    import paper_2503_17535_amd as hp
+    p = 12
+    funcs = [lambda x: W.wavefront_u(x), lambda x: W.wavefront_f(x)]
+    t = hp.adaptive_tree(funcs, p, 1e-5, 3)
+    pts, bpts = t.points(p, 0), t.points(p, 2)
+    from numpy.polynomial import polynomial as npoly
+    cf = [np.array([0.2, -0.3, 0.1, 0.05] + [0.0] * (p - 7) + [0.4 + 0.1 * a]) for a in range(3)]
+    vals = lambda x: [npoly.polyval(x[..., a], cf[a]) for a in range(3)]
+    d2s = lambda x: [npoly.polyval(x[..., a], npoly.polyder(cf[a], 2)) for a in range(3)]
+    v, d2 = vals(pts), d2s(pts)
+    lap = d2[0] * v[1] * v[2] + v[0] * d2[1] * v[2] + v[0] * v[1] * d2[2]
+    vb = vals(bpts)
+    op = hp.build_adaptive(t, p, torch.tensor(W.coeffs_poisson(pts), device=DEV))
+    say(f"[case] adaptive p={p} leaves={t.n_leaves} root D {op.root_D}")
+    assert op.root_D > 8192
+    u = op.solve(torch.tensor((vb[0] * vb[1] * vb[2])[None], device=DEV), torch.tensor(-lap[None], device=DEV))
+    ue = v[0] * v[1] * v[2]
+    err = np.abs(u.cpu().numpy()[0] - ue).max() / np.abs(ue).max()
+    op.free()
+    say(f"[case] rel error vs exact polynomial {err:.3e}")
+    assert err < 1e-10
+
+
 def test_refinement_check_matches_oracle_tree():
     """The tree built with the GPU criterion equals the oracle's (same
     functions, tolerance, level cap): bit-exact integer output."""

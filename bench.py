@@ -305,17 +305,19 @@ def divgrad_3d(hp, W):
             "rel_err_vs_manufactured": err}
 
 
-def subtree_recomputation(hp, W):
+def subtree_recomputation(hp, W, deep: bool = False):
     """2D p = 16 trees of depth 8 and 9 (16.8M and 67.1M unknowns), the sizes
     of the paper's subtree-recomputation runs: build + one solve with a
     source (local solves, merges, downward pass: what the paper times) of the
     resident operator and of the recomputing one (hps_build_subtrees with
     5- and 6-level subtrees), the library's peak device memory of each, and
-    the error against the problem's exact polynomial solution."""
+    the error against the problem's exact polynomial solution.  With deep,
+    also depth 10 (268M unknowns, 7-level subtrees), whose resident operator
+    (679 GB) does not fit one GPU: recomputation only."""
     import numpy as np
     import torch
     out = []
-    for L, sd in ((8, 5), (9, 6)):
+    for L, sd in ((8, 5), (9, 6)) + (((10, 7),) if deep else ()):
         p = 16
         t = hp.tree(2, L)
         pts = hp.leaf_points(t, p)
@@ -330,7 +332,10 @@ def subtree_recomputation(hp, W):
         scale = np.abs(uex).max()
         rec = {"depth": L, "p": p, "unknowns": int(4 ** L * p * p), "subtree_depth": sd,
                "resident_operator_GB": hp.footprint(t, p) / 1e9}
-        for mode in ("resident", "recompute"):
+        fits = rec["resident_operator_GB"] < 250.0
+        if not fits:
+            rec["resident"] = {"skipped": "resident operator larger than the GPU's memory"}
+        for mode in (("resident", "recompute") if fits else ("recompute",)):
             torch.cuda.synchronize()
             base, _ = hp.mem_stats(reset_peak=True)
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -617,6 +622,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--deep", action="store_true",
+                    help="add the depth-10 (268M unknowns) subtree-recomputation run (about 2 minutes, most of it "
+                         "generating its inputs on the host)")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline workload (no 2D Poisson, 3D, misfit-gradient or recomputation legs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -741,7 +749,7 @@ def main():
         out["poisson2d_latency"] = poisson_latency(hp, W)
         out["divgrad3d"] = divgrad_3d(hp, W)
         out["misfit_gradient"] = misfit_gradients(hp, W, with_oracle=not args.no_cpu_baseline)
-        out["subtree_recomputation"] = subtree_recomputation(hp, W)
+        out["subtree_recomputation"] = subtree_recomputation(hp, W, deep=args.deep)
         out["iti"] = iti_helmholtz(hp, W)
         out["adaptive3d"] = adaptive_3d(hp, W)
     if not args.no_serving:

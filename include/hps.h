@@ -274,6 +274,18 @@ long long hps_adaptive_split(const int* leaves, long long n, const int* split, i
 long long hps_adaptive_union(const int* a, long long na, const int* b, long long nb, int* out, long long cap);
 long long hps_adaptive_balance(const int* leaves, long long n, int* out, long long cap);
 
+/* Build and first solve in one call, for a source known at build time (the
+ * paper's form of the algorithm computes the particular solution's fluxes
+ * during the merge stage, Section 3): the same operator and bitwise the same
+ * u as hps_build followed by hps_solve.  The sources' leaf solves and the
+ * upward pass through the merge levels that are already built run on a
+ * second stream (created and destroyed by the call, default priority) beside
+ * the Gauss-Jordan chains of the top merge levels; the rest follows on
+ * `stream`.  Arguments as hps_build and hps_solve (precision HPS_FP64; src
+ * NULL: build, then solve).  Synchronizes once, as the checked build does. */
+int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int flags, const double* bdry,
+                    const double* src, double* u, int nrhs, void* stream, hps_op_t** out);
+
 /* Solve stage (Algorithm down_pass, with the source entering through the
  * linear upward pass of the particular solution, Section 3):
  *   bdry  dev  [nrhs][n_root_bdry]        Dirichlet data g at the root Gauss points

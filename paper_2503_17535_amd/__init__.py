@@ -29,7 +29,7 @@ EXPORTS = ("hps_sizes", "hps_leaf_points", "hps_boundary_points", "hps_op_footpr
            "hps_batcher_create", "hps_solve_batch", "hps_batcher_free", "hps_refine_sweeps",
            "hps_debug_gemm_f32", "hps_level_info", "hps_solve_noalloc", "hps_mem_stats",
            "hps_build_subtrees", "hps_build_iti", "hps_set_allocator",
-           "hps_build_adaptive", "hps_adaptive_root_size", "hps_adaptive_points", "hps_adaptive_root_points",
+           "hps_build_solve", "hps_build_adaptive", "hps_adaptive_root_size", "hps_adaptive_points", "hps_adaptive_root_points",
            "hps_adaptive_check", "hps_adaptive_split", "hps_adaptive_union", "hps_adaptive_balance")
 
 
@@ -96,6 +96,7 @@ def lib():
         L.hps_build.argtypes = [TP, I, P, I, P, ctypes.POINTER(P)]
         L.hps_build_subtrees.argtypes = [TP, I, P, I, I, P, ctypes.POINTER(P)]
         L.hps_build_iti.argtypes = [TP, I, D, P, I, P, ctypes.POINTER(P)]
+        L.hps_build_solve.argtypes = [TP, I, P, I, P, P, P, I, P, ctypes.POINTER(P)]
         L.hps_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
         AP = ctypes.POINTER(ATree)
         L.hps_build_adaptive.argtypes = [AP, I, P, I, P, ctypes.POINTER(P)]
@@ -441,6 +442,27 @@ def debug_gemm(A, B, C, alpha=1.0, beta=0.0, trans_a=False, trans_b=False, strea
 
 def build(t: Tree, p: int, coeffs, flags: int = 0, stream=None) -> Operator:
     return Operator(t, p, coeffs, flags, stream)
+
+
+def build_solve(t: Tree, p: int, coeffs, bdry, src=None, out=None, flags: int = 0, stream=None):
+    """hps_build_solve: build and first solve in one call (the sources' leaf
+    part overlaps the top merge levels); returns (operator, u)."""
+    import torch
+    s = sizes(t, p)
+    ptr = _dev_ptr(coeffs, "coeffs", (s.n_leaves, s.n_terms, s.pts_per_leaf))
+    nrhs = bdry.shape[0]
+    bptr = _dev_ptr(bdry, "bdry", (nrhs, s.n_root_bdry))
+    sptr = None if src is None else _dev_ptr(src, "src", (nrhs, s.n_leaves, s.pts_per_leaf))
+    if out is None:
+        out = torch.empty((nrhs, s.n_leaves, s.pts_per_leaf), dtype=torch.float64, device=bdry.device)
+    uptr = _dev_ptr(out, "u", (nrhs, s.n_leaves, s.pts_per_leaf))
+    h = ctypes.c_void_p()
+    _check(lib().hps_build_solve(ctypes.byref(t), p, ptr, flags, bptr, sptr, uptr, nrhs, _stream_ptr(stream),
+                                 ctypes.byref(h)))
+    op = Operator.__new__(Operator)
+    op.tree, op.p, op.flags, op.subtree_depth, op.sizes = t, p, flags, 0, s
+    op._h = h
+    return op, out
 
 
 class ItiOperator(Operator):

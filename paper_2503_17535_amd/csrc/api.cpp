@@ -1335,7 +1335,8 @@ int collect_info(hps_op* op) {
   return HPS_OK;
 }
 
-int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags = true) {
+int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags = true,
+              const std::function<int(int)>* after = nullptr) {
   const int L = op->tree.depth, nd = op->nd;
   if (reset_flags) HPS_HIP_TRY(hipMemsetAsync(op->flag, 0, sizeof(int) * 4, st));
   if (op->ext_side > 0) {
@@ -1356,6 +1357,7 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags
   HPS_TRY(run_gemm(op, op->gemmTleaf, st));
   stage_end(op, st);
   }
+  if (after) HPS_TRY((*after)(L));
   static const char* names[] = {"merge_l0", "merge_l1", "merge_l2", "merge_l3", "merge_l4", "merge_l5",
                                 "merge_l6", "merge_l7", "merge_l8", "merge_l9", "merge_l10", "merge_l11"};
   for (int lev = L - 1; lev >= 0; --lev) {
@@ -1380,6 +1382,7 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags
       HPS_TRY(run_gemm(op, P.gemmT, st));
     }
     stage_end(op, st);
+    if (after) HPS_TRY((*after)(lev));
   }
   return HPS_OK;
 }
@@ -1388,28 +1391,40 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags
 // solutions and the upward pass of their fluxes; without sources the
 // interface data of every merge start at zero.  Operators whose leaves are
 // subtree roots take the leaf-level fluxes h[L] as already filled.
+// Source part of a solve at the leaves: v = L_ii^{-1} f_int and h = Q_i v.
+int run_solve_leaf_src(hps_op* op, const SolveCtx& c, const double* src, int nrhs, hipStream_t st) {
+  const int NR = op->NR;
+  if (op->d == 2) {
+    HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, c.at(op->v),
+                            NR, st, op->rstride));
+  } else {
+    HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
+    HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
+  }
+  return run_gemm_ctx(c, op->gemmHleaf, st, nrhs);
+}
+
+// Upward pass of the sources' fluxes over merge levels lev_hi down to lev_lo:
+// h_int gathered from the children, g~ = -Z h_int, h = h_ext + B g~.
+int run_solve_levels_up(hps_op* op, const SolveCtx& c, int lev_hi, int lev_lo, int nrhs, hipStream_t st) {
+  const int nd = op->nd, NR = op->NR;
+  for (int lev = lev_hi; lev >= lev_lo; --lev) {
+    LevelPlan& P = op->levels[lev];
+    HPS_TRY(run_copy(op, P.copyHint, nrhs, c.at(P.hint), (long long)NR * P.m, c.at(op->h[lev + 1]),
+                     (long long)nd * NR * P.nbc, nullptr, 0, P.nm, st));
+    HPS_TRY(run_gemm_ctx(c, P.gemmGt, st, nrhs));
+    if (lev > 0 || op->root_h) HPS_TRY(run_gemm_ctx(c, P.gemmHp, st, nrhs));
+  }
+  return HPS_OK;
+}
+
 int run_solve_up(hps_op* op, const SolveCtx& c, const double* bdry, const double* src, bool has_src, int nrhs,
                  bool graph_safe, hipStream_t st) {
-  const int L = op->tree.depth, nd = op->nd, NR = op->NR;
+  const int L = op->tree.depth, NR = op->NR;
   if (bdry) HPS_TRY(run_copy(op, op->copyRoot, nrhs, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st));
   if (has_src) {
-    if (op->ext_side == 0) {
-      if (op->d == 2) {
-        HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs,
-                                c.at(op->v), NR, st, op->rstride));
-      } else {
-        HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
-        HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
-      }
-      HPS_TRY(run_gemm_ctx(c, op->gemmHleaf, st, nrhs));
-    }
-    for (int lev = L - 1; lev >= 0; --lev) {
-      LevelPlan& P = op->levels[lev];
-      HPS_TRY(run_copy(op, P.copyHint, nrhs, c.at(P.hint), (long long)NR * P.m, c.at(op->h[lev + 1]),
-                       (long long)nd * NR * P.nbc, nullptr, 0, P.nm, st));
-      HPS_TRY(run_gemm_ctx(c, P.gemmGt, st, nrhs));
-      if (lev > 0 || op->root_h) HPS_TRY(run_gemm_ctx(c, P.gemmHp, st, nrhs));
-    }
+    if (op->ext_side == 0) HPS_TRY(run_solve_leaf_src(op, c, src, nrhs, st));
+    HPS_TRY(run_solve_levels_up(op, c, L - 1, 0, nrhs, st));
   } else {
     for (int lev = 0; lev < L; ++lev) {
       LevelPlan& P = op->levels[lev];
@@ -2336,6 +2351,148 @@ int hps_build(const hps_tree_t* tree, int p, const double* coeffs, int flags, vo
   if (rc == HPS_OK && (flags & HPS_FLAG_FP32_ONLY)) rc = drop_fp64(op);
   if (rc != HPS_OK) {
     if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(op->stream);
+    hps_free(op);
+    return rc;
+  }
+  *out = op;
+  return HPS_OK;
+}
+
+// The second stream of hps_build_solve, one per device, created at its first
+// use and kept for the process (creating a queue per call costs more than the
+// overlap gains).  It runs on every other CU: its long source-solve waves
+// would otherwise hold every CU, and the build's products and chain steps
+// beside them would wait for free ones.
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu >= 16) {
+    std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+    for (int cu = 0; cu < ncu; ++cu)
+      if (cu % 2 == 0) mask[(size_t)cu / 32] |= 1u << (cu % 32);
+    if (hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      s = nullptr;
+    }
+  }
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[dev] = s;
+  return s;
+}
+
+int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int flags, const double* bdry,
+                    const double* src, double* u, int nrhs, void* stream, hps_op_t** out) {
+  if (out) *out = nullptr;
+  HPS_TRY(check_tree(tree, p));
+  if (!coeffs || !out || !bdry || !u || nrhs < 1) {
+    set_error("coeffs, bdry, u and out must be non-NULL and nrhs >= 1");
+    return HPS_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto build_then_solve = [&](int fl) -> int {
+    HPS_TRY(hps_build(tree, p, coeffs, fl, stream, out));
+    const int rc = hps_solve(*out, bdry, src, u, nrhs, HPS_FP64, stream);
+    if (rc != HPS_OK) {
+      hps_free(*out);
+      *out = nullptr;
+    }
+    return rc;
+  };
+  if (!src) return build_then_solve(flags);
+  hipError_t pending = hipGetLastError();
+  if (pending != hipSuccess) {
+    set_error(std::string("earlier device error: ") + hipGetErrorString(pending));
+    return HPS_EDEVICE;
+  }
+  hps_op* op = new hps_op();
+  op->tree = *tree;
+  op->p = p;
+  op->d = tree->dim;
+  op->nd = 1 << op->d;
+  op->flags = flags;
+  op->nl = 1LL << (op->d * tree->depth);
+  const LeafOps& o = leaf_ops(op->d, p);
+  op->npts = o.npts;
+  op->ni = o.n_i;
+  op->ne = o.n_e;
+  op->nb = o.n_b;
+  op->r = (tree->hi - tree->lo) / 2.0 / (double)(1LL << tree->depth);
+  op->stream = st;
+  int rc = get_consts(op->d, p, op->r, &op->cst);
+  if (rc == HPS_OK) rc = plan_op(op);
+  if (rc != HPS_OK) {
+    hps_free(op);
+    return rc;
+  }
+  const int L = op->tree.depth, k = std::min(op->NR, nrhs);
+  // The source's leaf part (and the upward pass through the levels already
+  // built) goes to a second stream once the build has passed the last level
+  // with at least 64 nodes: the levels above it are Gauss-Jordan chains on a
+  // few large matrices that leave most of the GPU idle.  Only products that
+  // do not split K (the split-K workspace is shared) go there.
+  int fork = L;
+  for (int lev = L - 1; lev >= 0; --lev)
+    if (op->levels[lev].nm >= 64) fork = lev;
+  bool overlap = op->gemmHleaf.nrblocks == 0 && (op->d == 2 || op->gemmVleaf.nrblocks == 0);
+  for (int lev = L - 1; lev >= fork; --lev)
+    overlap = overlap && op->levels[lev].gemmGt.nrblocks == 0 && op->levels[lev].gemmHp.nrblocks == 0;
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, side_ev = nullptr;
+  if (overlap) {
+    side = side_stream();
+    if (!side || hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&side_ev, hipEventDisableTiming) != hipSuccess)
+      overlap = false;
+  }
+  const SolveCtx c = own_ctx(op);
+  bool forked = false;
+  std::function<int(int)> after = [&](int lev) -> int {
+    if (!overlap || lev != fork) return HPS_OK;
+    HPS_HIP_TRY(hipEventRecord(fork_ev, st));
+    HPS_HIP_TRY(hipStreamWaitEvent(side, fork_ev, 0));
+    HPS_TRY(run_solve_leaf_src(op, c, src, k, side));
+    if (fork < L) HPS_TRY(run_solve_levels_up(op, c, L - 1, fork, k, side));
+    HPS_HIP_TRY(hipEventRecord(side_ev, side));
+    forked = true;
+    return HPS_OK;
+  };
+  rc = run_build(op, coeffs, st, true, &after);
+  if (rc == HPS_OK) {
+    if (forked) {
+      if (hipStreamWaitEvent(st, side_ev, 0) != hipSuccess) { set_error("stream wait failed"); rc = HPS_EDEVICE; }
+      if (rc == HPS_OK) rc = run_copy(op, op->copyRoot, k, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st);
+      if (rc == HPS_OK && fork > 0) rc = run_solve_levels_up(op, c, fork - 1, 0, k, st);
+      if (rc == HPS_OK) rc = run_solve_down(op, c, true, u, k, st);
+    } else {
+      rc = run_solve_chunk(op, c, bdry, src, u, k, false, st);
+    }
+  }
+  if (side) (void)hipStreamSynchronize(side);
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
+  if (side_ev) (void)hipEventDestroy(side_ev);
+  bool retry_full_pivot = false;
+  if (rc == HPS_OK && !(flags & HPS_FLAG_NO_CHECK)) rc = check_build(op, &retry_full_pivot);
+  if (retry_full_pivot) {
+    (void)hipStreamSynchronize(st);
+    hps_free(op);
+    return build_then_solve(flags | HPS_FLAG_FULL_PIVOT);
+  }
+  const long long nbr = op->nbl[0], field = op->nl * op->npts;
+  for (int r0 = k; rc == HPS_OK && r0 < nrhs; r0 += op->NR) {
+    const int kk = std::min(op->NR, nrhs - r0);
+    rc = run_solve_chunk(op, c, bdry + r0 * nbr, src + r0 * field, u + r0 * field, kk, false, st);
+  }
+  if (rc == HPS_OK && (flags & (HPS_FLAG_FP32_COPY | HPS_FLAG_FP32_ONLY))) rc = setup_fp32(op, coeffs, st);
+  if (rc == HPS_OK && (flags & HPS_FLAG_FP32_ONLY)) rc = drop_fp64(op);
+  if (rc != HPS_OK) {
+    if (rc != HPS_EDEVICE) (void)hipStreamSynchronize(st);
     hps_free(op);
     return rc;
   }

@@ -42,11 +42,13 @@ int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batc
 int gj_panel_width(int m);
 int gj_panel_max_nb();
 int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, int w, long long batch,
-                     hipStream_t st);
+                     hipStream_t st, int cb, int cw);
+int gj_block_prep_launch(const double* A, const int* piv, int m, int b0, int w, int ob, double* Wk, double* Pk,
+                         long long batch, hipStream_t st);
 int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, int* flag,
                     long long batch, hipStream_t st);
 int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, const double* Wp, int wp,
-                   int* flag, long long batch, hipStream_t st);
+                   int* flag, long long batch, hipStream_t st, int cb, int cw);
 int gj_init_launch(int* pos, long long n, hipStream_t st);
 int gj_unscramble_launch(const double* R, double* Z, int m, const int* pos, const int* piv, long long batch,
                          hipStream_t st);
@@ -566,11 +568,22 @@ void* lvl_take(hps_op* op, long long bytes) {
 
 bool gj_is_small(int m, long long batch) { return m <= kGjSmallAlways || (m <= gj_small_max() && batch >= 256); }
 
+// The two-level form (column blocks of kGjBlockCols) where the one-level
+// form's per-panel update of every column is bound by HBM traffic: large
+// matrices, and batches whose matrices together exceed ~1.2 GB (the leaves of
+// 3D p = 12 and ItI p = 16 operators)
+constexpr int kGjBlockCols = 256;
+bool gj_two_level(int m, long long batch) {
+  return m >= 2049 || (m >= 2 * kGjBlockCols && (double)batch * m * m >= 1.5e8);
+}
+
 // bytes plan_gj takes from the level workspace for a blocked inverse
 long long gj_ws_bytes(int m, long long batch) {
   if (gj_is_small(m, batch)) return 0;
-  return 2 * al256((long long)sizeof(int) * batch * m) +
-         al256((long long)sizeof(double) * 2 * batch * m * gj_panel_max_nb());
+  long long b = 2 * al256((long long)sizeof(int) * batch * m) +
+                al256((long long)sizeof(double) * 2 * batch * m * gj_panel_max_nb());
+  if (gj_two_level(m, batch)) b += 2 * al256((long long)sizeof(double) * batch * m * kGjBlockCols);
+  return b;
 }
 
 // level_ws: workspace from the shared merge-level region (else owned by op)
@@ -599,12 +612,60 @@ int plan_gj(hps_op* op, GJPlan* g, double* A, double* Z, int m, long long batch,
     set_error("device allocation failed (Gauss-Jordan workspace)");
     return HPS_ENOMEM;
   }
+  if (gj_two_level(m, batch)) {
+    // per column block [b0, b0 + w): A(:, j) += Wk Pk(:, j) for the columns
+    // left and right of the block (in place: C0 = C)
+    const int ob = kGjBlockCols;
+    g->ob = ob;
+    g->Wk = (double*)take((long long)sizeof(double) * batch * m * ob);
+    g->Pk = (double*)take((long long)sizeof(double) * batch * m * ob);
+    if (!g->Wk || !g->Pk) {
+      set_error("device allocation failed (Gauss-Jordan block workspace)");
+      return HPS_ENOMEM;
+    }
+    const long long mm = (long long)m * m, mo = (long long)m * ob;
+    for (int b0 = 0; b0 < m; b0 += ob) {
+      const int w = std::min(ob, m - b0), r0 = b0 + w;
+      std::vector<GemmGroup> gs;
+      if (b0 > 0)
+        gs.push_back(make_group(g->Wk, mo, m, g->Pk, mo, ob, A, mm, m, m, b0, w, 1.0, 1.0, batch, A, mm, m));
+      if (r0 < m)
+        gs.push_back(make_group(g->Wk, mo, m, g->Pk + (long long)r0 * ob, mo, ob, A + (long long)r0 * m, mm, m, m,
+                                m - r0, w, 1.0, 1.0, batch, A + (long long)r0 * m, mm, m));
+      GemmCall call;
+      add_gemm(op, gs, &call);
+      g->blk.push_back(call);
+    }
+  }
   return HPS_OK;
 }
 
 int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
   if (g.small) return gj_small_launch(g.A, g.Z, g.m, g.flag, g.batch, st);
   HPS_TRY(gj_init_launch(g.pos, g.batch * g.m, st));
+  if (g.ob > 0) {
+    // two-level form: inside each column block the panels update only the
+    // block (the pivot search still runs over every unused row); then the
+    // block's combined elimination operator updates the other columns on the
+    // matrix cores
+    const long long wbuf = g.batch * g.m * gj_panel_max_nb();
+    int K = 0;
+    for (int b0 = 0; b0 < g.m; b0 += g.ob, ++K) {
+      const int w = std::min(g.ob, g.m - b0);
+      const int np = (w + g.nb - 1) / g.nb;
+      HPS_TRY(gj_panel_launch(g.A, g.m, b0, std::min(g.nb, w), g.pos, g.piv, g.W, g.flag, g.batch, st));
+      for (int k = 1; k < np; ++k) {
+        const int j0 = b0 + k * g.nb, wk = std::min(g.nb, b0 + w - j0);
+        HPS_TRY(gj_step_launch(g.A, g.m, j0, wk, g.pos, g.piv, g.W + (k % 2) * wbuf, g.W + ((k - 1) % 2) * wbuf,
+                               g.nb, g.flag, g.batch, st, b0, w));
+      }
+      const int jl = b0 + (np - 1) * g.nb;
+      HPS_TRY(gj_update_launch(g.A, g.W + ((np - 1) % 2) * wbuf, g.piv, g.m, jl, b0 + w - jl, g.batch, st, b0, w));
+      HPS_TRY(gj_block_prep_launch(g.A, g.piv, g.m, b0, w, g.ob, g.Wk, g.Pk, g.batch, st));
+      HPS_TRY(run_gemm(op, g.blk[K], st));
+    }
+    return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
+  }
   // panel k writes W buffer k % 2; launch k (k >= 1) factors panel k beside
   // the update by panel k - 1 of the columns outside both panels
   const long long wbuf = g.batch * g.m * gj_panel_max_nb();
@@ -613,10 +674,10 @@ int run_gj(hps_op* op, const GJPlan& g, hipStream_t st) {
   for (int k = 1; k < np; ++k) {
     const int j0 = k * g.nb, w = std::min(g.nb, g.m - j0);
     HPS_TRY(gj_step_launch(g.A, g.m, j0, w, g.pos, g.piv, g.W + (k % 2) * wbuf, g.W + ((k - 1) % 2) * wbuf, g.nb,
-                           g.flag, g.batch, st));
+                           g.flag, g.batch, st, 0, 0));
   }
   const int jl = (np - 1) * g.nb;
-  HPS_TRY(gj_update_launch(g.A, g.W + ((np - 1) % 2) * wbuf, g.piv, g.m, jl, g.m - jl, g.batch, st));
+  HPS_TRY(gj_update_launch(g.A, g.W + ((np - 1) % 2) * wbuf, g.piv, g.m, jl, g.m - jl, g.batch, st, 0, 0));
   return gj_unscramble_launch(g.A, g.Z, g.m, g.pos, g.piv, g.batch, st);
 }
 

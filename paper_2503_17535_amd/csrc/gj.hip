@@ -18,6 +18,7 @@
 //    rows and columns.  Used for the few large merges near the root.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
 
 // Gauss-Jordan update by the panel at jp of width w:
 //   A(:, j) += W A(piv[jp .. jp+w), j)   (W = panel - E_P, written by the panel kernel)
-// for the nout columns j = q (q < jx) and j = q + wx (q >= jx), q < nout: all
+// for the nout columns j = cbase + q (q < jx) and j = cbase + q + wx (q >= jx), q < nout: all
 // columns outside [jx, jx + wx) = [jp, jp + w) or a wider range, or (jx = 0)
 // the nout columns from wx on.  A workgroup owns GU_COLS whole columns (the
 // qblk-th group): it first stages the (old) pivot-row entries of its columns
@@ -362,11 +363,11 @@ constexpr int GU_KC = 8;  // panel columns per chunk of W loads
 template <int THREADS, int ROWS>
 __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const double* __restrict__ W,
                                                const int* __restrict__ piv, int m, int jp, int w, int jx, int wx,
-                                               int nout, int qblk) {
+                                               int nout, int qblk, int cbase = 0) {
   __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
   const int tid = threadIdx.x;
   const int q0 = qblk * GU_COLS;         // first column index q of this workgroup
-  auto colof = [&](int q) { return q < jx ? q : q + wx; };
+  auto colof = [&](int q) { return cbase + (q < jx ? q : q + wx); };
   for (int e = tid; e < PANEL_MAX_NB * GU_COLS; e += THREADS) {
     const int c = e / GU_COLS, jj = e % GU_COLS, q = q0 + jj;
     s_p[c][jj] = (c < w && q < nout) ? A[piv[jp + c] + (long long)colof(q) * m] : 0.0;
@@ -414,24 +415,27 @@ __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const dou
 }
 
 constexpr int GU_THREADS = 256;
+// (columns restricted to [cb, cb + cw))
 __global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restrict__ Aall, const double* __restrict__ Wall,
-                                                               const int* __restrict__ pivall, int m, int j0, int w) {
+                                                               const int* __restrict__ pivall, int m, int j0, int w,
+                                                               int cb, int cw) {
   const long long b = blockIdx.y;
   gj_update_body<GU_THREADS, 4>(Aall + b * (long long)m * m, Wall + b * (long long)m * PANEL_MAX_NB,
-                                pivall + b * (long long)m, m, j0, w, j0, w, m - w, blockIdx.x);
+                                pivall + b * (long long)m, m, j0, w, j0 - cb, w, cw - w, blockIdx.x, cb);
 }
 
 // One step of the blocked elimination in a single launch: workgroup 0 of each
 // matrix applies the previous panel's update to the panel's own columns (same
 // code and order of operations as the other columns' update), then factors
 // the panel at j0; the other workgroups apply the previous panel's update to
-// every column outside both panels.  The two parts touch disjoint columns;
+// every column of [cb, cb + cw) outside both panels (the whole matrix, or the
+// column block of the two-level form).  The two parts touch disjoint columns;
 // the panel writes its W into the other buffer of the pair.
 template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                  int* __restrict__ posall, int* __restrict__ pivall,
                                                                  double* __restrict__ Wall, const double* __restrict__ Wpall,
-                                                                 int wp, int* __restrict__ flag) {
+                                                                 int wp, int* __restrict__ flag, int cb, int cw) {
   const long long b = blockIdx.y;
   double* A = Aall + b * (long long)m * m;
   int* piv = pivall + b * (long long)m;
@@ -446,16 +450,21 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restri
     gj_panel_body<RPT, NB>(A, m, j0, nbw, posall + b * (long long)m, piv, Wall + b * (long long)m * PANEL_MAX_NB,
                            flag);
   } else {
-    gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, jp, wp + nbw, m - wp - nbw, blockIdx.x - 1);
+    gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, jp - cb, wp + nbw, cw - wp - nbw, blockIdx.x - 1, cb);
   }
 }
 
 int gj_update_launch(double* A, const double* W, const int* piv, int m, int j0, int w, long long batch,
-                     hipStream_t st) {
-  const int nout = m - w;
+                     hipStream_t st, int cb, int cw) {
+  if (cw <= 0) { cb = 0; cw = m; }
+  const int nout = cw - w;
   if (nout <= 0) return HPS_OK;
+  if (cb < 0 || cb + cw > m || j0 < cb || j0 + w > cb + cw) {
+    set_error("Gauss-Jordan update: column range out of bounds");
+    return HPS_EINVAL;
+  }
   dim3 grid((unsigned)((nout + GU_COLS - 1) / GU_COLS), (unsigned)batch);
-  hipLaunchKernelGGL(gj_update_kernel, grid, dim3(GU_THREADS), 0, st, A, W, piv, m, j0, w);
+  hipLaunchKernelGGL(gj_update_kernel, grid, dim3(GU_THREADS), 0, st, A, W, piv, m, j0, w, cb, cw);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }
@@ -499,29 +508,78 @@ int gj_panel_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, doubl
 }
 
 int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double* W, const double* Wp, int wp,
-                   int* flag, long long batch, hipStream_t st) {
-  const int nout = m - wp - nbw;
+                   int* flag, long long batch, hipStream_t st, int cb, int cw) {
+  if (cw <= 0) { cb = 0; cw = m; }
+  const int nout = cw - wp - nbw;
   dim3 grid((unsigned)(1 + (nout > 0 ? (nout + GU_COLS - 1) / GU_COLS : 0)), (unsigned)batch), block(PANEL_THREADS);
-  if (batch > 65535 || wp > PANEL_MAX_NB || j0 < wp) {
+  if (batch > 65535 || wp > PANEL_MAX_NB || j0 < wp || j0 - wp < cb || cb < 0 || cb + cw > m || j0 + nbw > cb + cw) {
     set_error("blocked Gauss-Jordan step: batch or panel layout out of range");
     return HPS_EINVAL;
   }
   if (m <= 512)
-    hipLaunchKernelGGL((gj_step_kernel<1, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<1, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else if (m <= 1024)
-    hipLaunchKernelGGL((gj_step_kernel<2, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<2, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else if (m <= 2048)
-    hipLaunchKernelGGL((gj_step_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<4, 16>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else if (m <= 4096)
-    hipLaunchKernelGGL((gj_step_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<8, 8>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else if (m <= 8192)
-    hipLaunchKernelGGL((gj_step_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<16, 4>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else if (m <= 16384)
-    hipLaunchKernelGGL((gj_step_kernel<32, 2>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag);
+    hipLaunchKernelGGL((gj_step_kernel<32, 2>), grid, block, 0, st, A, m, j0, nbw, pos, piv, W, Wp, wp, flag, cb, cw);
   else {
     set_error("blocked Gauss-Jordan: matrix larger than 16384 not supported");
     return HPS_EUNSUPPORTED;
   }
+  HPS_HIP_TRY(hipGetLastError());
+  return HPS_OK;
+}
+
+// Two-level form, per column block [b0, b0 + w) after its inner panels:
+// Wk(:, c) = A(:, b0 + c) - e_{piv[b0 + c]} (the block's combined elimination
+// operator minus the pivot-row identity) and Pk(c, j) = A(piv[b0 + c], j) for
+// every column j (the pivot rows' values before the block's update of the
+// other columns); then A(:, j) += Wk Pk(:, j) for every j outside the block,
+// as two grouped GEMMs.
+__global__ __launch_bounds__(256) void gj_block_w_kernel(const double* __restrict__ Aall, const int* __restrict__ pivall,
+                                                         int m, int b0, int w, int ob, double* __restrict__ Wkall) {
+  const long long b = blockIdx.y;
+  const double* A = Aall + b * (long long)m * m;
+  const int* piv = pivall + b * (long long)m;
+  double* Wk = Wkall + b * (long long)m * ob;
+  const long long n = (long long)m * w;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    Wk[e] = A[r + (long long)(b0 + c) * m] - (r == piv[b0 + c] ? 1.0 : 0.0);
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_pivot_rows_kernel(const double* __restrict__ Aall,
+                                                            const int* __restrict__ pivall, int m, int b0, int w,
+                                                            int ob, double* __restrict__ Pkall) {
+  const long long b = blockIdx.y;
+  const double* A = Aall + b * (long long)m * m;
+  const int* piv = pivall + b * (long long)m;
+  double* Pk = Pkall + b * (long long)ob * m;
+  const long long n = (long long)w * m;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % w), j = (int)(e / w);
+    Pk[c + (long long)j * ob] = A[piv[b0 + c] + (long long)j * m];
+  }
+}
+
+int gj_block_prep_launch(const double* A, const int* piv, int m, int b0, int w, int ob, double* Wk, double* Pk,
+                         long long batch, hipStream_t st) {
+  if (batch > 65535 || w > ob || b0 < 0 || b0 + w > m) {
+    set_error("Gauss-Jordan block preparation: layout out of range");
+    return HPS_EINVAL;
+  }
+  const long long n = (long long)m * w;
+  const unsigned gx = (unsigned)std::min<long long>(2048, (n + 255) / 256);
+  hipLaunchKernelGGL(gj_block_w_kernel, dim3(gx, (unsigned)batch), dim3(256), 0, st, A, piv, m, b0, w, ob, Wk);
+  HPS_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(gj_pivot_rows_kernel, dim3(gx, (unsigned)batch), dim3(256), 0, st, A, piv, m, b0, w, ob, Pk);
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

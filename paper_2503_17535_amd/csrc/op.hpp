@@ -52,6 +52,11 @@ struct GJPlan {
   int nb = 0;
   int *pos = nullptr, *piv = nullptr;
   double* W = nullptr;
+  // two-level form (large m): column blocks of ob columns, the inner panels
+  // update only their block, then one GEMM pair per block updates the rest
+  int ob = 0;
+  double *Wk = nullptr, *Pk = nullptr;
+  std::vector<GemmCall> blk;
 };
 
 struct LevelPlan {

@@ -205,6 +205,8 @@ int gj_small_launch(const double* D, double* Z, int m, int* flag, long long batc
 // ---------------------------------------------------------------------------
 constexpr int PANEL_THREADS = 512;
 constexpr int PANEL_MAX_NB = 16;
+constexpr int GU_COLS = 8;  // columns per workgroup of the update
+constexpr int GU_KC = 8;    // panel columns per chunk of W loads in the update
 
 // Initialize the pivot bookkeeping of a batch (pos = -1).
 __global__ void gj_init_kernel(int* pos, long long n) {
@@ -233,7 +235,8 @@ constexpr int rank_code_bits(int n) { return n < 256 ? 8 : 1 + rank_code_bits(n 
 // best of the NW candidates and applies the rank-1 Gauss-Jordan update.
 template <int RPT, int NB>
 __device__ __forceinline__ void gj_panel_body(double* __restrict__ A, int m, int j0, int nbw, int* __restrict__ pos,
-                                              int* __restrict__ piv, double* __restrict__ W, int* __restrict__ flag) {
+                                              int* __restrict__ piv, double* __restrict__ W, int* __restrict__ flag,
+                                              const double* __restrict__ Wp = nullptr, int jp = 0, int wp = 0) {
   constexpr int NW = PANEL_THREADS / 64;
   constexpr int CB = rank_code_bits(RPT * PANEL_THREADS);
   constexpr int CMAX = (1 << CB) - 1;
@@ -245,6 +248,17 @@ __device__ __forceinline__ void gj_panel_body(double* __restrict__ A, int m, int
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+  // With Wp: the previous panel's update of this panel's columns is applied
+  // here, in registers, in the same order of operations as the update of the
+  // other columns (gj_update_body), instead of a store and reload.
+  __shared__ double s_pp[PANEL_MAX_NB][PANEL_MAX_NB];  // old pivot rows of the previous panel
+  if (Wp) {
+    for (int e = tid; e < PANEL_MAX_NB * PANEL_MAX_NB; e += PANEL_THREADS) {
+      const int k = e / PANEL_MAX_NB, c = e % PANEL_MAX_NB;
+      s_pp[k][c] = (k < wp && c < nbw) ? A[piv[jp + k] + (long long)(j0 + c) * m] : 0.0;
+    }
+    __syncthreads();
+  }
   double a[RPT][NB];
   unsigned used = 0;
 #pragma unroll
@@ -254,6 +268,23 @@ __device__ __forceinline__ void gj_panel_body(double* __restrict__ A, int m, int
     for (int c = 0; c < NB; ++c)
       a[i][c] = (row < m && c < nbw) ? A[row + (long long)(j0 + c) * m] : 0.0;
     if (row >= m || pos[row] >= 0) used |= 1u << i;
+  }
+  if (Wp) {
+    const int wpad = (wp + GU_KC - 1) / GU_KC * GU_KC;
+    for (int k = 0; k < wpad; ++k) {
+      double w[RPT];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = tid + PANEL_THREADS * i;
+        w[i] = (row < m && k < wp) ? Wp[row + (long long)k * m] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double pc = s_pp[k][c];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) a[i][c] += w[i] * pc;
+      }
+    }
   }
 
   gj_static_for<0, NB>([&](auto cc_) __attribute__((always_inline)) {
@@ -358,8 +389,6 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restr
 // qblk-th group): it first stages the (old) pivot-row entries of its columns
 // in LDS, then rewrites its columns, so no other workgroup can overwrite a
 // pivot row before it is read.
-constexpr int GU_COLS = 8;
-constexpr int GU_KC = 8;  // panel columns per chunk of W loads
 template <int THREADS, int ROWS>
 __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const double* __restrict__ W,
                                                const int* __restrict__ piv, int m, int jp, int w, int jx, int wx,
@@ -425,9 +454,9 @@ __global__ __launch_bounds__(GU_THREADS) void gj_update_kernel(double* __restric
 }
 
 // One step of the blocked elimination in a single launch: workgroup 0 of each
-// matrix applies the previous panel's update to the panel's own columns (same
-// code and order of operations as the other columns' update), then factors
-// the panel at j0; the other workgroups apply the previous panel's update to
+// matrix applies the previous panel's update to the panel's own columns in
+// registers (same order of operations as the other columns' update), then
+// factors the panel at j0; the other workgroups apply the previous panel's update to
 // every column of [cb, cb + cw) outside both panels (the whole matrix, or the
 // column block of the two-level form).  The two parts touch disjoint columns;
 // the panel writes its W into the other buffer of the pair.
@@ -442,13 +471,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restri
   const double* Wp = Wpall + b * (long long)m * PANEL_MAX_NB;
   const int jp = j0 - wp;
   if (blockIdx.x == 0) {
-    // in groups of GU_COLS columns (measured faster than one group of 16)
-    for (int qb = 0; qb * GU_COLS < nbw; ++qb) {
-      gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, 0, j0, nbw, qb);
-      __syncthreads();  // the updated columns are visible to the workgroup; s_p is free again
-    }
     gj_panel_body<RPT, NB>(A, m, j0, nbw, posall + b * (long long)m, piv, Wall + b * (long long)m * PANEL_MAX_NB,
-                           flag);
+                           flag, Wp, jp, wp);
   } else {
     gj_update_body<PANEL_THREADS, 2>(A, Wp, piv, m, jp, wp, jp - cb, wp + nbw, cw - wp - nbw, blockIdx.x - 1, cb);
   }

@@ -1184,16 +1184,20 @@ int plan_op(hps_op* op) {
           }
       add_copy(op, ops, &P.copyB);
     }
-    // --- parent T = A + B S
+    // --- parent T = A + B S: the product B S first, then A added in place on
+    // its nonzero blocks (a child's exterior faces against its own), so T is
+    // written once and only A's blocks are read back
     if (formT) {
       const int ngrp = 2 * d * G.sub_per_face;
       std::vector<BlockOp> ops;
       for (int gr = 0; gr < ngrp; ++gr)
         for (int gc = 0; gc < ngrp; ++gc) {
-          BlockOp o = make_op((long long)gr * n + (long long)gc * n * nbp, nbp, n, n);
           const int c = G.group_child[gr];
-          if (G.group_child[gc] == c)
-            op_src(o, 0, c * childT + (long long)G.group_face[gr] * n + (long long)G.group_face[gc] * n * nbc, nbc);
+          if (G.group_child[gc] != c) continue;
+          const long long off = (long long)gr * n + (long long)gc * n * nbp;
+          BlockOp o = make_op(off, nbp, n, n);
+          op_src(o, 0, c * childT + (long long)G.group_face[gr] * n + (long long)G.group_face[gc] * n * nbc, nbc);
+          op_src(o, 1, off, nbp);
           ops.push_back(o);
         }
       add_copy(op, ops, &P.fillT);
@@ -1201,8 +1205,7 @@ int plan_op(hps_op* op) {
       for (int gr = 0; gr < ngrp; ++gr) {
         const int c = G.group_child[gr], F = G.group_face[gr];
         GemmGroup g = make_group(Tchild, nd * childT, nbc, P.S, (long long)m * nbp, m, P.Tp + (long long)gr * n,
-                                 (long long)nbp * nbp, nbp, n, nbp, n, 1.0, 1.0, nm, P.Tp + (long long)gr * n,
-                                 (long long)nbp * nbp, nbp);
+                                 (long long)nbp * nbp, nbp, n, nbp, n, 1.0, 0.0, nm);
         g.nseg = d;
         for (int k = 0; k < d; ++k) {
           const int i = G.int_list[c][k];
@@ -1439,8 +1442,9 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags
     HPS_TRY(run_gemm(op, P.gemmS, st));
     HPS_TRY(run_copy(op, P.copyB, 0, P.Bnz, (long long)nd * P.dn * P.dn, Tchild, childstride, nullptr, 0, P.nm, st));
     if (P.Tp) {
-      HPS_TRY(run_copy(op, P.fillT, 0, P.Tp, (long long)P.nbp * P.nbp, Tchild, childstride, nullptr, 0, P.nm, st));
       HPS_TRY(run_gemm(op, P.gemmT, st));
+      HPS_TRY(run_copy(op, P.fillT, 0, P.Tp, (long long)P.nbp * P.nbp, Tchild, childstride, P.Tp,
+                       (long long)P.nbp * P.nbp, P.nm, st));
     }
     stage_end(op, st);
     if (after) HPS_TRY((*after)(lev));

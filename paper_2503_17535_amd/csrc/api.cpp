@@ -527,21 +527,25 @@ int run_copy(hps_op* op, const CopyCall& c, int ncols_rt, double* dst, long long
 
 void stage_begin(hps_op* op, const char* name, hipStream_t st) {
   if (!(op->flags & HPS_FLAG_TIMING)) return;
+  // timing is diagnostic: a stage whose events cannot be created is skipped
   TimedStage t;
   t.name = name;
-  hipEventCreate(&t.a);
-  hipEventCreate(&t.b);
-  hipEventRecord(t.a, st);
+  if (hipEventCreate(&t.a) != hipSuccess) return;
+  if (hipEventCreate(&t.b) != hipSuccess) {
+    (void)hipEventDestroy(t.a);
+    return;
+  }
+  (void)hipEventRecord(t.a, st);
   op->stages.push_back(t);
 }
 void stage_end(hps_op* op, hipStream_t st) {
   if (!(op->flags & HPS_FLAG_TIMING) || op->stages.empty()) return;
-  hipEventRecord(op->stages.back().b, st);
+  (void)hipEventRecord(op->stages.back().b, st);
 }
 void clear_stages(hps_op* op) {
   for (auto& s : op->stages) {
-    hipEventDestroy(s.a);
-    hipEventDestroy(s.b);
+    (void)hipEventDestroy(s.a);
+    (void)hipEventDestroy(s.b);
   }
   op->stages.clear();
 }
@@ -2853,7 +2857,7 @@ int hps_stage_times(hps_op_t* op, const char** names, double* ms, int cap) {
     if (n >= cap) break;
     if (hipEventSynchronize(s.b) != hipSuccess) { set_error("event sync failed"); return -HPS_EDEVICE; }
     float t = 0.f;
-    hipEventElapsedTime(&t, s.a, s.b);
+    if (hipEventElapsedTime(&t, s.a, s.b) != hipSuccess) t = -1.f;
     if (names) names[n] = s.name;
     if (ms) ms[n] = t;
     ++n;

@@ -214,3 +214,21 @@ def test_adaptive_root_D_smaller_than_uniform():
     # only where both sides are fine
     assert A.root_D_size(t, p) < A.root_D_size(A.AdaptiveTree.uniform(t.max_level), p)
     assert A.root_D_size(t, p) >= A.root_D_size(A.AdaptiveTree.uniform(1), p)
+
+
+def test_criterion_error_closed_form():
+    # f = x^p on the unit cube: the degree-(p-1) interpolant through the p
+    # Chebyshev-Lobatto nodes misses it by the nodal polynomial, so the
+    # criterion's numerator is 2^-p max over the children's nodes y of
+    # |prod_j (y - x_j)| (reference coordinates, x = (x_ref + 1) / 2)
+    p = 6
+    disc = hps.LeafDisc(3, p)
+    t = A.AdaptiveTree.uniform(0, 0.0, 1.0)
+    f = lambda x: x[:, 0] ** p
+    root = (0, 0, 0, 0)
+    x1 = np.concatenate([t.points(disc, ch) for ch in A.children(root)])
+    err = np.abs(f(x1) - A.child_interp(p) @ f(t.points(disc, root))).max()
+    xr = disc.x
+    y = np.concatenate([(xr - 1.0) / 2.0, (xr + 1.0) / 2.0])
+    nodal = np.array([np.prod(yy - xr) for yy in y])
+    assert abs(err - 2.0 ** -p * np.abs(nodal).max()) < 1e-13

@@ -802,7 +802,12 @@ int plan_guard(hps_op* op, LevelPlan& P) {
   const int ldx = op->probe_ld;
   P.py = (double*)lvl_take(op, sizeof(double) * nm * mp);
   P.pr = (double*)lvl_take(op, sizeof(double) * nm * mp);
-  P.rho = (double*)op_alloc(op, sizeof(double) * (kNsSteps + 1) * nm, false);
+  if (op->rho_used + (kNsSteps + 1) * nm > op->rho_n) {
+    set_error("internal: probe residual block too small");
+    return HPS_EINVAL;
+  }
+  P.rho = op->rho_all + op->rho_used;
+  op->rho_used += (kNsSteps + 1) * nm;
   P.gate = (int*)op_alloc(op, sizeof(int) * nm, false);
   if (!P.py || !P.pr || !P.rho || !P.gate) {
     set_error("device allocation failed (merge inverse probe)");
@@ -983,7 +988,13 @@ int plan_op(hps_op* op) {
       }
   }
   op->Tleaf = op->Tbuf[0];
-  op->flag = (int*)op_alloc(op, sizeof(int) * 4, false);
+  // status block: flags (padded to 8 doubles), then the probe residuals of
+  // every merge level (kNsSteps + 1 per node)
+  op->rho_n = 0;
+  op->rho_used = 0;
+  for (int lev = 0; lev < L; ++lev) op->rho_n += (kNsSteps + 1) * (1LL << (d * lev));
+  op->flag = (int*)op_alloc(op, sizeof(double) * (8 + op->rho_n), false);
+  op->rho_all = op->flag ? (double*)op->flag + 8 : nullptr;
   if ((!ext && (!op->LU || !op->Y || !op->perm || !op->pos)) || !op->Tleaf || !op->flag) {
     set_error("device allocation failed (leaf operators)");
     return HPS_ENOMEM;
@@ -1334,40 +1345,69 @@ int finish_plan(hps_op* op) {
   }
   for (auto& g : op->hgroups) g.part = g.ksplit > 1 ? op->splitws + g.part_off : nullptr;
   HPS_TRY(plan_static_solve(op));
-  // upload descriptor tables
-  op->dgroups = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * std::max<size_t>(1, op->hgroups.size()), false);
-  op->dops = (BlockOp*)op_alloc(op, sizeof(BlockOp) * std::max<size_t>(1, op->hops.size()), false);
-  op->ditems = (CopyItem*)op_alloc(op, sizeof(CopyItem) * std::max<size_t>(1, op->hitems.size()), false);
-  op->dtasks = (CopyTask*)op_alloc(op, sizeof(CopyTask) * std::max<size_t>(1, op->htasks.size()), false);
-  if (!op->dgroups || !op->dops || !op->ditems || !op->dtasks) {
+  // upload the descriptor tables: one allocation, one copy
+  struct Table {
+    const void* src;
+    size_t bytes;
+    void** dst;
+  };
+  const size_t ns = op->static_ok ? op->hgroups_static.size() : 0;
+  const Table tabs[5] = {
+      {op->hgroups.data(), sizeof(GemmGroup) * op->hgroups.size(), (void**)&op->dgroups},
+      {op->hops.data(), sizeof(BlockOp) * op->hops.size(), (void**)&op->dops},
+      {op->hitems.data(), sizeof(CopyItem) * op->hitems.size(), (void**)&op->ditems},
+      {op->htasks.data(), sizeof(CopyTask) * op->htasks.size(), (void**)&op->dtasks},
+      {op->hgroups_static.data(), sizeof(GemmGroup) * ns, (void**)&op->dgroups_static}};
+  size_t off[5], total = 0;
+  for (int t = 0; t < 5; ++t) {
+    off[t] = total;
+    total += (size_t)al256((long long)std::max<size_t>(tabs[t].bytes, 1));
+  }
+  char* dev = (char*)op_alloc(op, total, false);
+  if (!dev) {
     set_error("device allocation failed (descriptors)");
     return HPS_ENOMEM;
   }
-  HPS_HIP_TRY(hipMemcpy(op->ditems, op->hitems.data(), sizeof(CopyItem) * op->hitems.size(), hipMemcpyHostToDevice));
-  HPS_HIP_TRY(hipMemcpy(op->dtasks, op->htasks.data(), sizeof(CopyTask) * op->htasks.size(), hipMemcpyHostToDevice));
-  HPS_HIP_TRY(hipMemcpy(op->dgroups, op->hgroups.data(), sizeof(GemmGroup) * op->hgroups.size(), hipMemcpyHostToDevice));
-  HPS_HIP_TRY(hipMemcpy(op->dops, op->hops.data(), sizeof(BlockOp) * op->hops.size(), hipMemcpyHostToDevice));
-  if (op->static_ok) {
-    op->dgroups_static = (GemmGroup*)op_alloc(op, sizeof(GemmGroup) * op->hgroups_static.size(), false);
-    if (!op->dgroups_static) { set_error("device allocation failed (descriptors)"); return HPS_ENOMEM; }
-    HPS_HIP_TRY(hipMemcpy(op->dgroups_static, op->hgroups_static.data(), sizeof(GemmGroup) * op->hgroups_static.size(),
-                          hipMemcpyHostToDevice));
+  std::vector<char> host(total, 0);
+  for (int t = 0; t < 5; ++t) {
+    if (tabs[t].bytes) std::memcpy(host.data() + off[t], tabs[t].src, tabs[t].bytes);
+    *tabs[t].dst = dev + off[t];
+  }
+  if (!op->static_ok) op->dgroups_static = nullptr;
+  HPS_HIP_TRY(hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice));
+  return HPS_OK;
+}
+
+// the build's status block on the host: flags, then every level's residuals
+// (synchronizes the op's stream)
+int download_status(hps_op* op, std::vector<double>* out) {
+  out->assign(8 + op->rho_n, 0.0);
+  hipError_t e = hipMemcpyAsync(out->data(), op->flag, sizeof(double) * out->size(), hipMemcpyDeviceToHost,
+                                op->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
+  if (e != hipSuccess) {
+    set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
+    return HPS_EDEVICE;
   }
   return HPS_OK;
 }
 
-// Per-level probe results (synchronizes the op's stream).  Node residuals
-// are read from the last probe each node went through.
-int collect_info(hps_op* op) {
+// Per-level probe results; status is the downloaded status block (nullptr:
+// download it here).  Node residuals are read from the last probe each node
+// went through.
+int collect_info(hps_op* op, const std::vector<double>* status = nullptr) {
   if (op->info_ready) return HPS_OK;
-  HPS_HIP_TRY(hipStreamSynchronize(op->stream));
+  std::vector<double> own;
+  if (!status) {
+    HPS_TRY(download_status(op, &own));
+    status = &own;
+  }
   const int L = op->tree.depth;
   op->info.assign(L, hps_level_info_t());
   for (int lev = 0; lev < L; ++lev) {
     const LevelPlan& P = op->levels[lev];
     const int nk = (P.schur && !(op->flags & HPS_FLAG_TEST_NO_REFINE)) ? kNsSteps + 1 : 1;
-    std::vector<double> rho((size_t)nk * P.nm);
-    HPS_HIP_TRY(hipMemcpy(rho.data(), P.rho, sizeof(double) * rho.size(), hipMemcpyDeviceToHost));
+    const double* rho = status->data() + 8 + (P.rho - op->rho_all);
     hps_level_info_t& I = op->info[lev];
     I.level = lev;
     I.m = P.m;
@@ -2228,20 +2268,17 @@ int run_solve_refined_chunk(hps_op* op, const double* bdry, const double* src, d
 // block) and pivoting over all of D can redo it.
 int check_build(hps_op* op, bool* retry) {
   *retry = false;
-  int hflag[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpyAsync(hflag, op->flag, sizeof(hflag), hipMemcpyDeviceToHost, op->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(op->stream);
-  if (e != hipSuccess) {
-    set_error(std::string("build failed on the device: ") + hipGetErrorString(e));
-    return HPS_EDEVICE;
-  }
+  std::vector<double> status;
+  HPS_TRY(download_status(op, &status));
+  int hflag[4];
+  std::memcpy(hflag, status.data(), sizeof(hflag));
   if (hflag[0]) {
     set_error(std::string("zero or non-finite pivot in ") +
               ((hflag[0] & 1) ? "a leaf factorization (L_ii)" : "a merge matrix D"));
     return HPS_ESINGULAR;
   }
   op->info_ready = false;
-  HPS_TRY(collect_info(op));
+  HPS_TRY(collect_info(op, &status));
   int bad = -1;
   for (int lev = 0; lev < (int)op->info.size(); ++lev)
     if (op->info[lev].block_inverse && (hflag[1] || !(op->info[lev].residual <= kNsAccept))) bad = lev;

@@ -250,40 +250,71 @@ __device__ __forceinline__ void gj_panel_body(double* __restrict__ A, int m, int
 
   // With Wp: the previous panel's update of this panel's columns is applied
   // here, in registers, in the same order of operations as the update of the
-  // other columns (gj_update_body), instead of a store and reload.
+  // other columns (gj_update_body), instead of a store and reload.  Its
+  // factors are the previous panel's pivot rows of these columns (old
+  // values), which this workgroup already holds: the row whose pos is jp + k
+  // publishes row k.  The panel, pos and the first chunk of W are loaded
+  // together, so the step waits for memory once before its first pivot.
   __shared__ double s_pp[PANEL_MAX_NB][PANEL_MAX_NB];  // old pivot rows of the previous panel
-  if (Wp) {
-    for (int e = tid; e < PANEL_MAX_NB * PANEL_MAX_NB; e += PANEL_THREADS) {
-      const int k = e / PANEL_MAX_NB, c = e % PANEL_MAX_NB;
-      s_pp[k][c] = (k < wp && c < nbw) ? A[piv[jp + k] + (long long)(j0 + c) * m] : 0.0;
-    }
-    __syncthreads();
-  }
+  constexpr int KC = RPT >= 16 ? 1 : (RPT >= 8 ? 2 : (RPT >= 4 ? 4 : GU_KC));  // W rows per chunk
+  static_assert(GU_KC % KC == 0, "W chunks tile the padded panel width");
+  const int wpad = Wp ? (wp + GU_KC - 1) / GU_KC * GU_KC : 0;
   double a[RPT][NB];
-  unsigned used = 0;
+  int pv[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = tid + PANEL_THREADS * i;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       a[i][c] = (row < m && c < nbw) ? A[row + (long long)(j0 + c) * m] : 0.0;
-    if (row >= m || pos[row] >= 0) used |= 1u << i;
+    pv[i] = row < m ? pos[row] : -1;
   }
+  double w[KC][RPT];
   if (Wp) {
-    const int wpad = (wp + GU_KC - 1) / GU_KC * GU_KC;
-    for (int k = 0; k < wpad; ++k) {
-      double w[RPT];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int row = tid + PANEL_THREADS * i;
-        w[i] = (row < m && k < wp) ? Wp[row + (long long)k * m] : 0.0;
+        w[k][i] = (row < m && k < wp) ? Wp[row + (long long)k * m] : 0.0;
+      }
+  }
+  unsigned used = 0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = tid + PANEL_THREADS * i;
+    if (row >= m || pv[i] >= 0) used |= 1u << i;
+  }
+  if (Wp) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = tid + PANEL_THREADS * i;
+      const int k = pv[i] - jp;
+      if (row < m && k >= 0 && k < wp) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) s_pp[k][c] = a[i][c];
+      }
+    }
+    for (int e = tid; e < (wpad - wp) * NB; e += PANEL_THREADS) s_pp[wp + e / NB][e % NB] = 0.0;
+    __syncthreads();
+    for (int k0 = 0; k0 < wpad; k0 += KC) {
+      if (k0 > 0) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const int row = tid + PANEL_THREADS * i;
+            w[k][i] = (row < m && k0 + k < wp) ? Wp[row + (long long)(k0 + k) * m] : 0.0;
+          }
       }
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double pc = s_pp[k][c];
+      for (int k = 0; k < KC; ++k)
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) a[i][c] += w[i] * pc;
-      }
+        for (int c = 0; c < NB; ++c) {
+          const double pc = s_pp[k0 + k][c];
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) a[i][c] += w[k][i] * pc;
+        }
     }
   }
 
@@ -393,36 +424,48 @@ template <int THREADS, int ROWS>
 __device__ __forceinline__ void gj_update_body(double* __restrict__ A, const double* __restrict__ W,
                                                const int* __restrict__ piv, int m, int jp, int w, int jx, int wx,
                                                int nout, int qblk, int cbase = 0) {
+  static_assert(THREADS >= PANEL_MAX_NB * GU_COLS, "one staged pivot-row entry per thread at most");
   __shared__ double s_p[PANEL_MAX_NB][GU_COLS];
   const int tid = threadIdx.x;
   const int q0 = qblk * GU_COLS;         // first column index q of this workgroup
   auto colof = [&](int q) { return cbase + (q < jx ? q : q + wx); };
-  for (int e = tid; e < PANEL_MAX_NB * GU_COLS; e += THREADS) {
-    const int c = e / GU_COLS, jj = e % GU_COLS, q = q0 + jj;
-    s_p[c][jj] = (c < w && q < nout) ? A[piv[jp + c] + (long long)colof(q) * m] : 0.0;
-  }
-  __syncthreads();
   double* colp[GU_COLS];
 #pragma unroll
   for (int jj = 0; jj < GU_COLS; ++jj) colp[jj] = A + (long long)colof(q0 + jj < nout ? q0 + jj : q0) * m;
-  for (int r0 = 0; r0 < m; r0 += THREADS * ROWS) {
-    double acc[ROWS][GU_COLS];
+  double acc[ROWS][GU_COLS];
+  double wr[GU_KC][ROWS];
+  auto load_cols = [&](int r0) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       const int r = r0 + tid + THREADS * i;
 #pragma unroll
       for (int jj = 0; jj < GU_COLS; ++jj) acc[i][jj] = (r < m && q0 + jj < nout) ? colp[jj][r] : 0.0;
     }
+  };
+  auto load_w = [&](int r0, int c0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int cc = 0; cc < GU_KC; ++cc)
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        const int r = r0 + tid + THREADS * i;
+        wr[cc][i] = (r < m && c0 + cc < w) ? W[r + (long long)(c0 + cc) * m] : 0.0;
+      }
+  };
+  // the pivot index first, then the first row chunk's columns and W, then the
+  // (dependent) pivot-row entry: two memory round trips before the barrier
+  const int sc = tid / GU_COLS, sjj = tid % GU_COLS, sq = q0 + sjj;
+  const bool stage = tid < PANEL_MAX_NB * GU_COLS && sc < w && sq < nout;
+  const int prow = stage ? piv[jp + sc] : 0;
+  load_cols(0);
+  if (w > 0) load_w(0, 0);
+  const double pval = stage ? A[prow + (long long)colof(sq) * m] : 0.0;
+  if (tid < PANEL_MAX_NB * GU_COLS) s_p[sc][sjj] = pval;
+  __syncthreads();
+  for (int r0 = 0; r0 < m; r0 += THREADS * ROWS) {
+    if (r0 > 0) load_cols(r0);
     // K loop in chunks of GU_KC with every W load of a chunk issued first
     for (int c0 = 0; c0 < w; c0 += GU_KC) {
-      double wr[GU_KC][ROWS];
-#pragma unroll
-      for (int cc = 0; cc < GU_KC; ++cc)
-#pragma unroll
-        for (int i = 0; i < ROWS; ++i) {
-          const int r = r0 + tid + THREADS * i;
-          wr[cc][i] = (r < m && c0 + cc < w) ? W[r + (long long)(c0 + cc) * m] : 0.0;
-        }
+      if (r0 > 0 || c0 > 0) load_w(r0, c0);
 #pragma unroll
       for (int cc = 0; cc < GU_KC; ++cc)
 #pragma unroll
@@ -535,7 +578,9 @@ int gj_step_launch(double* A, int m, int j0, int nbw, int* pos, int* piv, double
                    int* flag, long long batch, hipStream_t st, int cb, int cw) {
   if (cw <= 0) { cb = 0; cw = m; }
   const int nout = cw - wp - nbw;
-  dim3 grid((unsigned)(1 + (nout > 0 ? (nout + GU_COLS - 1) / GU_COLS : 0)), (unsigned)batch), block(PANEL_THREADS);
+  // the first panel (wp = 0) has no previous update to apply: panel workgroups only
+  const int nupd = (wp > 0 && nout > 0) ? (nout + GU_COLS - 1) / GU_COLS : 0;
+  dim3 grid((unsigned)(1 + nupd), (unsigned)batch), block(PANEL_THREADS);
   if (batch > 65535 || wp > PANEL_MAX_NB || j0 < wp || j0 - wp < cb || cb < 0 || cb + cw > m || j0 + nbw > cb + cw) {
     set_error("blocked Gauss-Jordan step: batch or panel layout out of range");
     return HPS_EINVAL;

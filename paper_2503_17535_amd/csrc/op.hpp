@@ -228,6 +228,10 @@ struct hps_op {
   double probe_inv_xmax = 1.0;
   bool info_ready = false;
   std::vector<hps_level_info_t> info;
+  // build status block (device): the 4 pivot-failure flags, then every merge
+  // level's probe residuals (rho_n doubles), so that one download checks a build
+  double* rho_all = nullptr;
+  long long rho_n = 0, rho_used = 0;
   std::vector<hps::Alloc> allocs;
   size_t resident = 0;
   std::vector<hps::TimedStage> stages;

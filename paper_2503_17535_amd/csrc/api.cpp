@@ -2493,6 +2493,11 @@ static hipStream_t side_stream() {
   return s;
 }
 
+// the fork follows the last merge level with at least this many nodes (a
+// fork after smaller levels measured no faster: the source solve's waves then
+// slow the root's Gauss-Jordan chain by about what they overlap)
+constexpr long long kForkNodes = 64;
+
 int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int flags, const double* bdry,
                     const double* src, double* u, int nrhs, void* stream, hps_op_t** out) {
   if (out) *out = nullptr;
@@ -2545,10 +2550,13 @@ int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int fla
   // do not split K (the split-K workspace is shared) go there.
   int fork = L;
   for (int lev = L - 1; lev >= 0; --lev)
-    if (op->levels[lev].nm >= 64) fork = lev;
+    if (op->levels[lev].nm >= kForkNodes) fork = lev;
+  // the side stream's upward pass covers levels up_lo .. L - 1: the built
+  // levels from the leaves up to the first one whose products split K
   bool overlap = op->gemmHleaf.nrblocks == 0 && (op->d == 2 || op->gemmVleaf.nrblocks == 0);
-  for (int lev = L - 1; lev >= fork; --lev)
-    overlap = overlap && op->levels[lev].gemmGt.nrblocks == 0 && op->levels[lev].gemmHp.nrblocks == 0;
+  int up_lo = L;
+  while (up_lo > fork && op->levels[up_lo - 1].gemmGt.nrblocks == 0 && op->levels[up_lo - 1].gemmHp.nrblocks == 0)
+    --up_lo;
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, side_ev = nullptr;
   if (overlap) {
@@ -2564,7 +2572,7 @@ int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int fla
     HPS_HIP_TRY(hipEventRecord(fork_ev, st));
     HPS_HIP_TRY(hipStreamWaitEvent(side, fork_ev, 0));
     HPS_TRY(run_solve_leaf_src(op, c, src, k, side));
-    if (fork < L) HPS_TRY(run_solve_levels_up(op, c, L - 1, fork, k, side));
+    if (up_lo < L) HPS_TRY(run_solve_levels_up(op, c, L - 1, up_lo, k, side));
     HPS_HIP_TRY(hipEventRecord(side_ev, side));
     forked = true;
     return HPS_OK;
@@ -2574,7 +2582,7 @@ int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int fla
     if (forked) {
       if (hipStreamWaitEvent(st, side_ev, 0) != hipSuccess) { set_error("stream wait failed"); rc = HPS_EDEVICE; }
       if (rc == HPS_OK) rc = run_copy(op, op->copyRoot, k, c.at(op->g[0]), 0, bdry, 0, nullptr, 0, 1, st);
-      if (rc == HPS_OK && fork > 0) rc = run_solve_levels_up(op, c, fork - 1, 0, k, st);
+      if (rc == HPS_OK && up_lo > 0) rc = run_solve_levels_up(op, c, up_lo - 1, 0, k, st);
       if (rc == HPS_OK) rc = run_solve_down(op, c, true, u, k, st);
     } else {
       rc = run_solve_chunk(op, c, bdry, src, u, k, false, st);

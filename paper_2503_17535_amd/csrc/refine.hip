@@ -56,134 +56,245 @@ int refine_init_launch(const double* bdry, const long long* bidx, int q, int nb0
   return HPS_OK;
 }
 
-// One workgroup per leaf, all right-hand sides at once (thread work items
-// are (rhs, point) pairs):
+// One wavefront per leaf and group of RG_R right-hand sides:
 //   u(I_e) = P gamma (written to u), r1 = f - L u at interior points,
 //   Qu = outgoing normal derivative at the Gauss points of every face.
 // D1, D2 row-major p x p (scaled to the leaf), P column-major n_e x n_b,
-// C2G row-major q x p, coef [leaf][6][p^2].  The mixed derivative is formed
-// separably: ux = D1 along x on the whole grid (LDS), then D1 along y of ux.
-// D1 and D2 are kept transposed (DxT[a * p + i] = D(i, a)) so that lanes of
-// consecutive x index read consecutive LDS words.
-struct RfShared {
-  double D1[RF_MAXP * RF_MAXP], D2[RF_MAXP * RF_MAXP], D1T[RF_MAXP * RF_MAXP], D2T[RF_MAXP * RF_MAXP];
-  double C2G[RF_MAXP * RF_MAXP];
-  double u[RF_MAXR][RF_MAXP * RF_MAXP];
-  double ux[RF_MAXR][RF_MAXP * RF_MAXP];
-  double uy[RF_MAXR][RF_MAXP * RF_MAXP];
-  double g[RF_MAXR][4 * RF_MAXP];
-  double P[(4 * RF_MAXP - 4) * 4 * (RF_MAXP - 2)];  // Gauss -> Chebyshev boundary interpolation
-};
+// C2G row-major q x p, coef [leaf][6][p^2] (terms xx, xy, yy, x, y, 1).
+// Tensor-product derivatives with lane = (rhs, x index): in the x pass a
+// lane keeps rows ix of D1 and D2 in registers and reads each grid row of u
+// as an LDS broadcast (ux, u_xx); in the y pass it keeps column ix of u and
+// of ux and reads the rows of D1 and D2 as broadcasts (uy, u_yy, u_xy =
+// D1 along y of ux), then forms the residual with the same sums in the same
+// order as the dense definition.  Every global access is coalesced over ix;
+// the leaf's inputs arrive in one batch of loads, staged in LDS (each
+// right-hand side's block offset by 8 doubles so that the 4 blocks fall on
+// different banks).
+constexpr int RG_R = 4;   // right-hand sides per workgroup
+constexpr int RG_T = 64;  // threads per workgroup: one per (rhs, x index)
 
-__global__ __launch_bounds__(RF_THREADS) void refine_residual_kernel(
+template <int P>
+__global__ __launch_bounds__(RG_T) void refine_residual_kernel(
     const double* __restrict__ coef, const double* __restrict__ src, const double* __restrict__ gam,
-    const double* __restrict__ D1g, const double* __restrict__ D2g, const double* __restrict__ P,
-    const double* __restrict__ C2G, const int* __restrict__ Ii, const int* __restrict__ Ie, int p, long long nl,
-    int nrhs, int NRcap, double* __restrict__ u, double* __restrict__ r1, double* __restrict__ Qu) {
-  extern __shared__ double smem[];
-  RfShared& S = *reinterpret_cast<RfShared*>(smem);
-  const int q = p - 2, npts = p * p, ni = q * q, ne = npts - ni, nb = 4 * q;
-  const long long leaf = blockIdx.x;
+    const double* __restrict__ D1g, const double* __restrict__ D2g, const double* __restrict__ Pg,
+    const double* __restrict__ C2G, const int* __restrict__ Ie, long long nl, int nrhs, int NRcap,
+    double* __restrict__ u, double* __restrict__ r1, double* __restrict__ Qu) {
+  constexpr int Q = P - 2, NPTS = P * P, NI = Q * Q, NE = NPTS - NI, NB = 4 * Q;
+  constexpr int LD = NPTS + 8;  // LDS stride between right-hand sides
+  static_assert(RG_R * P <= RG_T && NE <= RG_T, "one lane per (rhs, x index) and per exterior point");
+  __shared__ double su[RG_R * LD], sux[RG_R * LD], sdxx[RG_R * LD];
+  __shared__ double sD1[NPTS], sD2[NPTS], sc[6 * NPTS], sg[RG_R * NB];
+  __shared__ double sface[RG_R][4][P];  // normal derivative along faces S, E, N, W
+  const int ngrp = (nrhs + RG_R - 1) / RG_R;
+  const long long leaf = blockIdx.x / ngrp;
+  const int r0 = (int)(blockIdx.x % ngrp) * RG_R;
+  const int nr = min(RG_R, nrhs - r0);
   const int tid = threadIdx.x;
-  for (int i = tid; i < p * p; i += RF_THREADS) {
-    S.D1[i] = D1g[i];
-    S.D2[i] = D2g[i];
-    S.D1T[(i % p) * p + i / p] = D1g[i];
-    S.D2T[(i % p) * p + i / p] = D2g[i];
-  }
-  for (int i = tid; i < q * p; i += RF_THREADS) S.C2G[i] = C2G[i];
-  for (int i = tid; i < ne * nb; i += RF_THREADS) S.P[i] = P[i];
-  for (int e = tid; e < nrhs * nb; e += RF_THREADS) {
-    const int r = e / nb, k = e % nb;
-    S.g[r][k] = gam[(leaf * NRcap + r) * nb + k];
-  }
-  // point outer, rhs inner: one index load per point, then the rhs loads together
-  for (int k = tid; k < ni; k += RF_THREADS) {
-    const int pt = Ii[k];
-    double uv[RF_MAXR];
+  const long long fld = nl * NPTS;  // right-hand-side stride of u and src
+  double* ul = u + leaf * NPTS;
+  const double* cl = coef + leaf * 6 * NPTS;
+  const int rr = tid / P, ix = tid % P;  // lane's right-hand side in the group and x index
+  const bool act = tid < RG_R * P && rr < nr;
+
+  // ---- one batch of loads: u interior, D1, D2, gamma, coefficients, sources
+  {
+    constexpr int IU = (RG_R * NI + RG_T - 1) / RG_T, ID = (NPTS + RG_T - 1) / RG_T;
+    constexpr int IG = (RG_R * NB + RG_T - 1) / RG_T, IC = (6 * NPTS + RG_T - 1) / RG_T;
+    double vu[IU], vd1[ID], vd2[ID], vg[IG], vc[IC];
 #pragma unroll
-    for (int r = 0; r < RF_MAXR; ++r) uv[r] = u[((long long)(r < nrhs ? r : 0) * nl + leaf) * npts + pt];
-#pragma unroll
-    for (int r = 0; r < RF_MAXR; ++r)
-      if (r < nrhs) S.u[r][pt] = uv[r];
-  }
-  __syncthreads();
-  // exterior points: u = P gamma
-  for (int e = tid; e < nrhs * ne; e += RF_THREADS) {
-    const int r = e / ne, k = e % ne;
-    double v = 0.0;
-    for (int b = 0; b < nb; ++b) v += S.P[k + b * ne] * S.g[r][b];
-    S.u[r][Ie[k]] = v;
-    u[((long long)r * nl + leaf) * npts + Ie[k]] = v;
-  }
-  __syncthreads();
-  // ux and uy on the whole grid
-  for (int e = tid; e < nrhs * npts; e += RF_THREADS) {
-    const int r = e / npts, pt = e % npts, ix = pt % p, iy = pt / p;
-    double vx = 0.0, vy = 0.0;
-    for (int a = 0; a < p; ++a) {
-      vx += S.D1T[a * p + ix] * S.u[r][a + p * iy];
-      vy += S.D1[iy * p + a] * S.u[r][ix + p * a];
+    for (int i = 0; i < IU; ++i) {
+      const int e = tid + RG_T * i, r = e / NI, k = e % NI;
+      const int pt = (k % Q + 1) + P * (k / Q + 1);
+      vu[i] = (e < RG_R * NI && r < nr) ? ul[(long long)(r0 + r) * fld + pt] : 0.0;
     }
-    S.ux[r][pt] = vx;
-    S.uy[r][pt] = vy;
+#pragma unroll
+    for (int i = 0; i < ID; ++i) {
+      const int e = tid + RG_T * i;
+      vd1[i] = e < NPTS ? D1g[e] : 0.0;
+      vd2[i] = e < NPTS ? D2g[e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < IG; ++i) {
+      const int e = tid + RG_T * i, r = e / NB;
+      vg[i] = (e < RG_R * NB && r < nr) ? gam[(leaf * NRcap + r0) * NB + e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < IC; ++i) {
+      const int e = tid + RG_T * i;
+      vc[i] = e < 6 * NPTS ? cl[e] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < IU; ++i) {
+      const int e = tid + RG_T * i, r = e / NI, k = e % NI;
+      if (e < RG_R * NI) su[r * LD + (k % Q + 1) + P * (k / Q + 1)] = vu[i];
+    }
+#pragma unroll
+    for (int i = 0; i < ID; ++i) {
+      const int e = tid + RG_T * i;
+      if (e < NPTS) { sD1[e] = vd1[i]; sD2[e] = vd2[i]; }
+    }
+#pragma unroll
+    for (int i = 0; i < IG; ++i) {
+      const int e = tid + RG_T * i;
+      if (e < RG_R * NB) sg[e] = vg[i];
+    }
+#pragma unroll
+    for (int i = 0; i < IC; ++i) {
+      const int e = tid + RG_T * i;
+      if (e < 6 * NPTS) sc[e] = vc[i];
+    }
   }
+  // sources at this lane's column (used in the y pass)
+  double fcol[P];
+#pragma unroll
+  for (int iy = 0; iy < P; ++iy)
+    fcol[iy] = (act && src && iy > 0 && iy < P - 1 && ix > 0 && ix < P - 1)
+                   ? src[(long long)(r0 + rr) * fld + leaf * NPTS + ix + P * iy]
+                   : 0.0;
   __syncthreads();
-  // collocation residual at interior points: point outer (its coefficients
-  // loaded once), rhs inner (the sources loaded together)
-  const double* c = coef + leaf * 6 * (long long)npts;
-  for (int k = tid; k < ni; k += RF_THREADS) {
-    const int pt = Ii[k], ix = pt % p, iy = pt / p;
-    const double cxx = c[pt], cxy = c[npts + pt], cyy = c[2 * npts + pt], cx = c[3 * npts + pt],
-                 cy = c[4 * npts + pt], c0 = c[5 * npts + pt];
-    double fv[RF_MAXR];
+
+  // ---- exterior values u(I_e) = P gamma: lane k, every right-hand side of the
+  // group; P in chunks of 8 columns, the next chunk's loads issued before the
+  // current chunk's products
+  if (tid < NE) {
+    const int k = tid;
+    double acc[RG_R];
 #pragma unroll
-    for (int r = 0; r < RF_MAXR; ++r) fv[r] = src ? src[((long long)(r < nrhs ? r : 0) * nl + leaf) * npts + pt] : 0.0;
+    for (int r = 0; r < RG_R; ++r) acc[r] = 0.0;
+    constexpr int NCH = (NB + 7) / 8;
+    double pk[2][8];
 #pragma unroll
-    for (int r = 0; r < RF_MAXR; ++r) {
-      if (r >= nrhs) continue;
-      double dxx = 0.0, dyy = 0.0, dxy = 0.0;
-      for (int a = 0; a < p; ++a) {
-        dxx += S.D2T[a * p + ix] * S.u[r][a + p * iy];
-        dyy += S.D2[iy * p + a] * S.u[r][ix + p * a];
-        dxy += S.D1[iy * p + a] * S.ux[r][ix + p * a];
+    for (int bb = 0; bb < 8; ++bb) pk[0][bb] = bb < NB ? Pg[k + bb * NE] : 0.0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int cur = ch & 1;
+      if (ch + 1 < NCH) {
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+          const int b = (ch + 1) * 8 + bb;
+          pk[cur ^ 1][bb] = b < NB ? Pg[k + b * NE] : 0.0;
+        }
       }
-      const double Lu = cxx * dxx + cxy * dxy + cyy * dyy + cx * S.ux[r][pt] + cy * S.uy[r][pt] + c0 * S.u[r][pt];
-      r1[(leaf * NRcap + r) * ni + k] = fv[r] - Lu;
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb) {
+        const int b = ch * 8 + bb;
+        if (b >= NB) break;
+#pragma unroll
+        for (int r = 0; r < RG_R; ++r) acc[r] += pk[cur][bb] * sg[r * NB + b];
+      }
+    }
+    const int pt = Ie[k];
+#pragma unroll
+    for (int r = 0; r < RG_R; ++r) {
+      su[r * LD + pt] = acc[r];
+      if (r < nr) ul[(long long)(r0 + r) * fld + pt] = acc[r];
     }
   }
-  // outgoing fluxes: normal derivative at the face's Chebyshev points (faces
-  // S, E, N, W; tangential coordinate ascending), then Chebyshev -> Gauss
-  for (int e = tid; e < nrhs * nb; e += RF_THREADS) {
-    const int r = e / nb, cg = e % nb, f = cg / q, j = cg % q;
-    const int axis = (f == 1 || f == 3) ? 0 : 1;
-    const int side = (f == 1 || f == 2) ? 1 : 0;
-    const int in = side ? p - 1 : 0;
+  __syncthreads();
+
+  // ---- x pass: ux and u_xx at (ix, iy) for every iy
+  if (act) {
+    double d1[P], d2[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      d1[a] = sD1[ix * P + a];
+      d2[a] = sD2[ix * P + a];
+    }
+    const double* ur = su + rr * LD;
+#pragma unroll
+    for (int iy = 0; iy < P; ++iy) {
+      double vx = 0.0, vxx = 0.0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const double uv = ur[a + P * iy];  // the same address for the lanes of this rhs
+        vx += d1[a] * uv;
+        vxx += d2[a] * uv;
+      }
+      sux[rr * LD + ix + P * iy] = vx;
+      sdxx[rr * LD + ix + P * iy] = vxx;
+      if (ix == 0) sface[rr][3][iy] = vx;
+      if (ix == P - 1) sface[rr][1][iy] = vx;
+    }
+  }
+  __syncthreads();
+  // ---- y pass: uy, u_yy, u_xy at (ix, iy), then the residual
+  if (act) {
+    double uc[P], uxc[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      uc[a] = su[rr * LD + ix + P * a];
+      uxc[a] = sux[rr * LD + ix + P * a];
+    }
+    double* r1l = r1 + (leaf * NRcap + r0 + rr) * NI;
+    const bool icol = ix > 0 && ix < P - 1;
+#pragma unroll
+    for (int iy = 0; iy < P; ++iy) {
+      double vy = 0.0, vyy = 0.0, vxy = 0.0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const double e1 = sD1[iy * P + a], e2 = sD2[iy * P + a];  // broadcasts
+        vy += e1 * uc[a];
+        vyy += e2 * uc[a];
+        vxy += e1 * uxc[a];
+      }
+      if (iy == 0) sface[rr][0][ix] = vy;
+      if (iy == P - 1) sface[rr][2][ix] = vy;
+      if (icol && iy > 0 && iy < P - 1) {
+        const int pt = ix + P * iy;
+        const double Lu = sc[pt] * sdxx[rr * LD + pt] + sc[NPTS + pt] * vxy + sc[2 * NPTS + pt] * vyy +
+                          sc[3 * NPTS + pt] * uxc[iy] + sc[4 * NPTS + pt] * vy + sc[5 * NPTS + pt] * uc[iy];
+        r1l[(ix - 1) + Q * (iy - 1)] = fcol[iy] - Lu;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- outgoing fluxes: Chebyshev -> Gauss along each face, sign of the outward normal
+  for (int e = tid; e < RG_R * NB; e += RG_T) {
+    const int r = e / NB, cg = e % NB, f = cg / Q, j = cg % Q;
+    if (r >= nr) continue;
     double v = 0.0;
-    for (int t = 0; t < p; ++t) {
-      const double d = axis == 0 ? S.ux[r][in + p * t] : S.uy[r][t + p * in];
-      v += S.C2G[j * p + t] * d;
-    }
-    Qu[(leaf * NRcap + r) * nb + cg] = side ? v : -v;
+#pragma unroll
+    for (int t = 0; t < P; ++t) v += C2G[j * P + t] * sface[r][f][t];
+    Qu[(leaf * NRcap + r0 + r) * NB + cg] = (f == 1 || f == 2) ? v : -v;
   }
+}
+
+template <int P>
+static void launch_refine_residual(const double* coef, const double* src, const double* gam, const double* D1,
+                                   const double* D2, const double* Pm, const double* C2G, const int* Ie, long long nl,
+                                   int nrhs, int NRcap, double* u, double* r1, double* Qu, hipStream_t st) {
+  const long long ngrp = (nrhs + RG_R - 1) / RG_R;
+  hipLaunchKernelGGL(refine_residual_kernel<P>, dim3((unsigned)(nl * ngrp)), dim3(RG_T), 0, st, coef, src, gam, D1,
+                     D2, Pm, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu);
 }
 
 int refine_residual_launch(const double* coef, const double* src, const double* gam, const double* D1,
                            const double* D2, const double* P, const double* C2G, const int* Ii, const int* Ie, int p,
                            long long nl, int nrhs, int NRcap, double* u, double* r1, double* Qu, hipStream_t st) {
-  if (p > RF_MAXP || nrhs > RF_MAXR) {
-    set_error("refined solve: p <= 16 and at most 16 right-hand sides per pass");
+  (void)Ii;  // interior points are in scan order: k = (ix - 1) + q (iy - 1)
+  if (p < 4 || p > RF_MAXP || nrhs < 1 || nrhs > RF_MAXR || nrhs > NRcap) {
+    set_error("refined solve: 4 <= p <= 16 and 1 ... 16 right-hand sides per pass");
     return HPS_EUNSUPPORTED;
   }
-  const size_t shm = sizeof(RfShared);
-  static bool attr = false;
-  if (!attr) {
-    HPS_HIP_TRY(hipFuncSetAttribute((const void*)refine_residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)shm));
-    attr = true;
+  if (nl * ((nrhs + RG_R - 1) / RG_R) > 0x7fffffffLL) {
+    set_error("refined solve: too many leaves for one launch");
+    return HPS_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(refine_residual_kernel, dim3((unsigned)nl), dim3(RF_THREADS), shm, st, coef, src, gam, D1, D2, P,
-                     C2G, Ii, Ie, p, nl, nrhs, NRcap, u, r1, Qu);
+  switch (p) {
+    case 4: launch_refine_residual<4>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 5: launch_refine_residual<5>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 6: launch_refine_residual<6>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 7: launch_refine_residual<7>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 8: launch_refine_residual<8>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 9: launch_refine_residual<9>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 10: launch_refine_residual<10>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 11: launch_refine_residual<11>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 12: launch_refine_residual<12>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 13: launch_refine_residual<13>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 14: launch_refine_residual<14>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 15: launch_refine_residual<15>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+    case 16: launch_refine_residual<16>(coef, src, gam, D1, D2, P, C2G, Ie, nl, nrhs, NRcap, u, r1, Qu, st); break;
+  }
   HPS_HIP_TRY(hipGetLastError());
   return HPS_OK;
 }

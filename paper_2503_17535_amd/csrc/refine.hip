@@ -83,7 +83,7 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
   constexpr int LD = NPTS + 8;  // LDS stride between right-hand sides
   static_assert(RG_R * P <= RG_T && NE <= RG_T, "one lane per (rhs, x index) and per exterior point");
   __shared__ double su[RG_R * LD], sux[RG_R * LD], sdxx[RG_R * LD];
-  __shared__ double sD1[NPTS], sD2[NPTS], sc[6 * NPTS], sg[RG_R * NB];
+  __shared__ double sD1[NPTS], sD2[NPTS], sc[6 * NPTS], sg[RG_R * NB], sC2G[Q * P];
   __shared__ double sface[RG_R][4][P];  // normal derivative along faces S, E, N, W
   const int ngrp = (nrhs + RG_R - 1) / RG_R;
   const long long leaf = blockIdx.x / ngrp;
@@ -95,12 +95,22 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
   const double* cl = coef + leaf * 6 * NPTS;
   const int rr = tid / P, ix = tid % P;  // lane's right-hand side in the group and x index
   const bool act = tid < RG_R * P && rr < nr;
+  // P (column-major n_e x n_b) row k = tid and the point of exterior index k,
+  // loaded with the rest of the leaf's inputs
+  double pk[NB];
+  int ptk = 0;
+  if (tid < NE) {
+    ptk = Ie[tid];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pk[b] = Pg[tid + b * NE];
+  }
 
   // ---- one batch of loads: u interior, D1, D2, gamma, coefficients, sources
   {
     constexpr int IU = (RG_R * NI + RG_T - 1) / RG_T, ID = (NPTS + RG_T - 1) / RG_T;
     constexpr int IG = (RG_R * NB + RG_T - 1) / RG_T, IC = (6 * NPTS + RG_T - 1) / RG_T;
-    double vu[IU], vd1[ID], vd2[ID], vg[IG], vc[IC];
+    constexpr int IQ = (Q * P + RG_T - 1) / RG_T;
+    double vu[IU], vd1[ID], vd2[ID], vg[IG], vc[IC], vq[IQ];
 #pragma unroll
     for (int i = 0; i < IU; ++i) {
       const int e = tid + RG_T * i, r = e / NI, k = e % NI;
@@ -124,6 +134,11 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
       vc[i] = e < 6 * NPTS ? cl[e] : 0.0;
     }
 #pragma unroll
+    for (int i = 0; i < IQ; ++i) {
+      const int e = tid + RG_T * i;
+      vq[i] = e < Q * P ? C2G[e] : 0.0;
+    }
+#pragma unroll
     for (int i = 0; i < IU; ++i) {
       const int e = tid + RG_T * i, r = e / NI, k = e % NI;
       if (e < RG_R * NI) su[r * LD + (k % Q + 1) + P * (k / Q + 1)] = vu[i];
@@ -143,6 +158,11 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
       const int e = tid + RG_T * i;
       if (e < 6 * NPTS) sc[e] = vc[i];
     }
+#pragma unroll
+    for (int i = 0; i < IQ; ++i) {
+      const int e = tid + RG_T * i;
+      if (e < Q * P) sC2G[e] = vq[i];
+    }
   }
   // sources at this lane's column (used in the y pass)
   double fcol[P];
@@ -153,37 +173,16 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
                    : 0.0;
   __syncthreads();
 
-  // ---- exterior values u(I_e) = P gamma: lane k, every right-hand side of the
-  // group; P in chunks of 8 columns, the next chunk's loads issued before the
-  // current chunk's products
+  // ---- exterior values u(I_e) = P gamma: lane k, every right-hand side of the group
   if (tid < NE) {
-    const int k = tid;
     double acc[RG_R];
 #pragma unroll
     for (int r = 0; r < RG_R; ++r) acc[r] = 0.0;
-    constexpr int NCH = (NB + 7) / 8;
-    double pk[2][8];
 #pragma unroll
-    for (int bb = 0; bb < 8; ++bb) pk[0][bb] = bb < NB ? Pg[k + bb * NE] : 0.0;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      const int cur = ch & 1;
-      if (ch + 1 < NCH) {
-#pragma unroll
-        for (int bb = 0; bb < 8; ++bb) {
-          const int b = (ch + 1) * 8 + bb;
-          pk[cur ^ 1][bb] = b < NB ? Pg[k + b * NE] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const int b = ch * 8 + bb;
-        if (b >= NB) break;
-#pragma unroll
-        for (int r = 0; r < RG_R; ++r) acc[r] += pk[cur][bb] * sg[r * NB + b];
-      }
-    }
-    const int pt = Ie[k];
+      for (int r = 0; r < RG_R; ++r) acc[r] += pk[b] * sg[r * NB + b];
+    const int pt = ptk;
 #pragma unroll
     for (int r = 0; r < RG_R; ++r) {
       su[r * LD + pt] = acc[r];
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(RG_T) void refine_residual_kernel(
     if (r >= nr) continue;
     double v = 0.0;
 #pragma unroll
-    for (int t = 0; t < P; ++t) v += C2G[j * P + t] * sface[r][f][t];
+    for (int t = 0; t < P; ++t) v += sC2G[j * P + t] * sface[r][f][t];
     Qu[(leaf * NRcap + r0 + r) * NB + cg] = (f == 1 || f == 2) ? v : -v;
   }
 }

@@ -427,10 +427,18 @@ int add_gemm(hps_op* op, std::vector<GemmGroup> groups, GemmCall* call, bool ta 
 // of at most kWaveElems elements are collected in tasks of their own in which
 // each wavefront takes every fourth piece: a whole workgroup walking a small
 // block leaves most of its lanes idle.
-void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call) {
-  constexpr long long kTaskElems = 16384;
+// batch: the number of nodes the copy runs over (0: unknown).  Tasks hold up to
+// 16K elements; a copy over few nodes gets smaller ones (down to 1K), so that
+// a launch has about 1,024 workgroups where the work allows it
+void add_copy(hps_op* op, const std::vector<BlockOp>& ops, CopyCall* call, long long batch = 0) {
   constexpr long long kWaveElems = 1024;
   constexpr int kRtCols = 16;
+  long long kTaskElems = 16384;
+  if (batch > 0) {
+    long long total = 0;
+    for (const BlockOp& o : ops) total += (long long)std::max(1, o.rows) * (o.cols <= 0 ? kRtCols : o.cols);
+    kTaskElems = std::min<long long>(16384, std::max<long long>(kWaveElems, total * batch / 1024));
+  }
   const int op0 = (int)op->hops.size();
   op->hops.insert(op->hops.end(), ops.begin(), ops.end());
   call->first_task = (int)op->htasks.size();
@@ -721,7 +729,7 @@ int plan_schur(hps_op* op, LevelPlan& P, int schur_p) {
       op_src(o, 0, (long long)b * s + (long long)b * s * m, m);
       ops.push_back(o);
     }
-    add_copy(op, ops, &P.copyA);
+    add_copy(op, ops, &P.copyA, P.nm);
   }
   {  // X_b = A_b^{-1} D(P_b, R);  Y_b = D(R, P_b) A_b^{-1}
     std::vector<GemmGroup> gs;
@@ -756,7 +764,7 @@ int plan_schur(hps_op* op, LevelPlan& P, int schur_p) {
   {  // Z(R, R) = Sc^{-1}
     BlockOp o = make_op(2LL * s + 2LL * s * m, m, r, r);
     op_src(o, 0, 0, r);
-    add_copy(op, {o}, &P.copyScZ);
+    add_copy(op, {o}, &P.copyScZ, P.nm);
   }
   {  // Z(P_b, P_b') = delta_bb' A_b^{-1} - Z(P_b, R) Y_b'
     std::vector<GemmGroup> gs;
@@ -1166,7 +1174,7 @@ int plan_op(hps_op* op) {
           }
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.copyD);
+      add_copy(op, ops, &P.copyD, P.nm);
     }
     // --- S = -Z C, one group per parent boundary group (child c, face F)
     {
@@ -1197,7 +1205,7 @@ int plan_op(hps_op* op) {
             op_src(o, 0, c * childT + (long long)Fe * n + (long long)Fk * n * nbc, nbc);
             ops.push_back(o);
           }
-      add_copy(op, ops, &P.copyB);
+      add_copy(op, ops, &P.copyB, P.nm);
     }
     // --- parent T = A + B S: the product B S first, then A added in place on
     // its nonzero blocks (a child's exterior faces against its own), so T is
@@ -1215,7 +1223,7 @@ int plan_op(hps_op* op) {
           op_src(o, 1, off, nbp);
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.fillT);
+      add_copy(op, ops, &P.fillT, P.nm);
       std::vector<GemmGroup> gs;
       for (int gr = 0; gr < ngrp; ++gr) {
         const int c = G.group_child[gr], F = G.group_face[gr];
@@ -1242,7 +1250,7 @@ int plan_op(hps_op* op) {
         op_src(o, 0, G.iface[i][2] * hstride_c + (long long)G.iface[i][3] * n, nbc);
         ops.push_back(o);
       }
-      add_copy(op, ops, &P.copyHint);
+      add_copy(op, ops, &P.copyHint, P.nm);
     }
     // gt = -Z h_int
     add_gemm(op, {make_group(P.Z, (long long)m * m, m, P.hint, (long long)NR * m, m, P.gt, (long long)NR * m, m, m,
@@ -1287,7 +1295,7 @@ int plan_op(hps_op* op) {
           }
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.copyGchild);
+      add_copy(op, ops, &P.copyGchild, P.nm);
     }
     // --- adjoint: parent groups <- children's exterior faces
     {
@@ -1298,7 +1306,7 @@ int plan_op(hps_op* op) {
         op_src(o, 0, G.group_child[gi] * hstride_c + (long long)G.group_face[gi] * n, nbc);
         ops.push_back(o);
       }
-      add_copy(op, ops, &P.copyPext);
+      add_copy(op, ops, &P.copyPext, P.nm);
     }
     // g_parent += S^T g_int
     add_gemm(op, {make_group(P.S, (long long)m * nbp, m, P.gint, (long long)NR * m, m, op->g[lev], (long long)NR * nbp,
@@ -1832,7 +1840,7 @@ int plan_iti(hps_op* op) {
             op_src(o, 0, y * childT + (long long)kItiUnk[k][3] * n + (long long)kItiUnk[k2][1] * n * nbc, nbc);
           ops.push_back(o);
         }
-      add_copy(op, ops, half == 0 ? &P.copyD : &P.copyD21);
+      add_copy(op, ops, half == 0 ? &P.copyD : &P.copyD21, P.nm);
     }
     // W = I - D12 D21
     add_gemm(op, {make_group(P.D12, (long long)w * w, w, P.D21, (long long)w * w, w, P.Dbuf, (long long)w * w, w, w, w,
@@ -1843,7 +1851,7 @@ int plan_iti(hps_op* op) {
     {
       BlockOp o = make_op(0, mi, w, w);
       op_src(o, 0, 0, w);
-      add_copy(op, {o}, &P.copyZ11);
+      add_copy(op, {o}, &P.copyZ11, P.nm);
     }
     add_gemm(op, {make_group(P.Winv, (long long)w * w, w, P.D12, (long long)w * w, w, P.Z + (long long)w * mi,
                              (long long)mi * mi, mi, w, w, w, -1.0, 0.0, nm),
@@ -1865,7 +1873,7 @@ int plan_iti(hps_op* op) {
             op_src(o, 0, y * childT + (long long)kItiUnk[k][3] * n + (long long)G.group_face[gj] * n * nbc, nbc);
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.copyC);
+      add_copy(op, ops, &P.copyC, P.nm);
     }
     add_gemm(op, {make_group(P.Z, (long long)mi * mi, mi, P.Cm, (long long)mi * nbp, mi, P.S, (long long)mi * nbp, mi,
                              mi, nbp, mi, -1.0, 0.0, nm)},
@@ -1881,7 +1889,7 @@ int plan_iti(hps_op* op) {
             op_src(o, 0, c * childT + (long long)G.group_face[gi] * n + (long long)kItiUnk[k][1] * n * nbc, nbc);
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.copyB);
+      add_copy(op, ops, &P.copyB, P.nm);
     }
     if (P.Tp) {
       std::vector<BlockOp> ops;
@@ -1893,7 +1901,7 @@ int plan_iti(hps_op* op) {
             op_src(o, 0, c * childT + (long long)G.group_face[gi] * n + (long long)G.group_face[gj] * n * nbc, nbc);
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.fillT);
+      add_copy(op, ops, &P.fillT, P.nm);
       add_gemm(op, {make_group(P.Bnz, (long long)nbp * mi, nbp, P.S, (long long)mi * nbp, mi, P.Tp, (long long)nbp * nbp,
                                nbp, nbp, nbp, mi, 1.0, 1.0, nm, P.Tp, (long long)nbp * nbp, nbp)},
                &P.gemmT);
@@ -1907,7 +1915,7 @@ int plan_iti(hps_op* op) {
         op_src(o, 0, kItiUnk[k][2] * hstride_c + (long long)kItiUnk[k][3] * n, nbc);
         ops.push_back(o);
       }
-      add_copy(op, ops, &P.copyHint);
+      add_copy(op, ops, &P.copyHint, P.nm);
     }
     add_gemm(op, {make_group(P.Z, (long long)mi * mi, mi, P.hint, (long long)NR * mi, mi, P.gt, (long long)NR * mi, mi,
                              mi, NR, mi, -1.0, 0.0, nm)},
@@ -1919,7 +1927,7 @@ int plan_iti(hps_op* op) {
         op_src(o, 0, G.group_child[gi] * hstride_c + (long long)G.group_face[gi] * n, nbc);
         ops.push_back(o);
       }
-      add_copy(op, ops, &P.copyHext);
+      add_copy(op, ops, &P.copyHext, P.nm);
       add_gemm(op, {make_group(P.Bnz, (long long)nbp * mi, nbp, P.gt, (long long)NR * mi, mi, op->h[lev],
                                (long long)NR * nbp, nbp, nbp, NR, mi, 1.0, 1.0, nm, op->h[lev], (long long)NR * nbp,
                                nbp)},
@@ -1942,7 +1950,7 @@ int plan_iti(hps_op* op) {
           }
           ops.push_back(o);
         }
-      add_copy(op, ops, &P.copyGchild);
+      add_copy(op, ops, &P.copyGchild, P.nm);
     }
   }
   return finish_plan(op);

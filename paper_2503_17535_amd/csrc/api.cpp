@@ -85,7 +85,8 @@ int block_copy_launch(const BlockOp* dev_ops, const CopyItem* dev_items, const C
                       int ncols_rt, double* dst, long long dst_stride, const double* src0, long long s0_stride,
                       const double* src1, long long s1_stride, long long batch, hipStream_t st);
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
-                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride = 0);
+                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride = 0,
+                    int max_wg_per_cu = 0);
 int leaf_out_launch(const double* Y, const double* P, const double* g, const double* v, const int* Ii, const int* Ie,
                     int NI, int NE, int NB, int npts, long long nl, int nrhs, int NRcap, double* u, hipStream_t st,
                     long long rstride = 0);
@@ -1509,11 +1510,12 @@ int run_build(hps_op* op, const double* coeffs, hipStream_t st, bool reset_flags
 // interface data of every merge start at zero.  Operators whose leaves are
 // subtree roots take the leaf-level fluxes h[L] as already filled.
 // Source part of a solve at the leaves: v = L_ii^{-1} f_int and h = Q_i v.
-int run_solve_leaf_src(hps_op* op, const SolveCtx& c, const double* src, int nrhs, hipStream_t st) {
+int run_solve_leaf_src(hps_op* op, const SolveCtx& c, const double* src, int nrhs, hipStream_t st,
+                       int max_wg_per_cu = 0) {
   const int NR = op->NR;
   if (op->d == 2) {
     HPS_TRY(leaf_src_launch(op->LU, op->perm, op->pos, src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, c.at(op->v),
-                            NR, st, op->rstride));
+                            NR, st, op->rstride, max_wg_per_cu));
   } else {
     HPS_TRY(leaf_gather_int_launch(src, op->cst->Ii, op->ni, op->npts, op->nl, nrhs, NR, c.at(op->fint), st));
     HPS_TRY(run_gemm_ctx(c, op->gemmVleaf, st, nrhs));
@@ -2505,6 +2507,13 @@ static hipStream_t side_stream() {
 // fork after smaller levels measured no faster: the source solve's waves then
 // slow the root's Gauss-Jordan chain by about what they overlap)
 constexpr long long kForkNodes = 64;
+// the second stream's leaf solves keep at most this many workgroups on a CU:
+// at full occupancy they fill its registers for their whole run, and the
+// build's copies and products placed on that CU wait until they finish; the
+// Gauss-Jordan kernels raise their waves' issue priority, so that the chain
+// is not slowed by the leaf solves sharing its SIMDs (2 measured best: 1 makes
+// the leaf solves outlast the top levels, 3 slows the chain)
+constexpr int kSideWgPerCu = 2;
 
 int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int flags, const double* bdry,
                     const double* src, double* u, int nrhs, void* stream, hps_op_t** out) {
@@ -2579,7 +2588,7 @@ int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int fla
     if (!overlap || lev != fork) return HPS_OK;
     HPS_HIP_TRY(hipEventRecord(fork_ev, st));
     HPS_HIP_TRY(hipStreamWaitEvent(side, fork_ev, 0));
-    HPS_TRY(run_solve_leaf_src(op, c, src, k, side));
+    HPS_TRY(run_solve_leaf_src(op, c, src, k, side, kSideWgPerCu));
     if (up_lo < L) HPS_TRY(run_solve_levels_up(op, c, L - 1, up_lo, k, side));
     HPS_HIP_TRY(hipEventRecord(side_ev, side));
     forked = true;

@@ -35,6 +35,9 @@ template <int TR, int TC, int RI, int RJ>
 __global__ __launch_bounds__(TR* TC) void gj_small_kernel(const double* __restrict__ Din, double* __restrict__ Zout,
                                                            int m, int* __restrict__ flag) {
   constexpr int NT = TR * TC;
+  // the pivot chain is the critical path: its waves win instruction issue over
+  // other work resident on the same SIMD (another stream's kernels)
+  __builtin_amdgcn_s_setprio(3);
   static_assert(64 % TR == 0, "a column group of TR lanes lies inside one wavefront");
   static_assert(RI * TR <= 255, "row rank codes fit in the 8 low bits of a pivot key");
   __shared__ double s_lcol[2][RI * TR];
@@ -407,6 +410,7 @@ template <int RPT, int NB>
 __global__ __launch_bounds__(PANEL_THREADS) void gj_panel_kernel(double* __restrict__ Aall, int m, int j0, int nbw,
                                                                   int* __restrict__ posall, int* __restrict__ pivall,
                                                                   double* __restrict__ Wall, int* __restrict__ flag) {
+  __builtin_amdgcn_s_setprio(3);  // critical path (see gj_small_kernel)
   const long long b = blockIdx.x;
   gj_panel_body<RPT, NB>(Aall + b * (long long)m * m, m, j0, nbw, posall + b * (long long)m,
                          pivall + b * (long long)m, Wall + b * (long long)m * PANEL_MAX_NB, flag);
@@ -508,6 +512,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void gj_step_kernel(double* __restri
                                                                  int* __restrict__ posall, int* __restrict__ pivall,
                                                                  double* __restrict__ Wall, const double* __restrict__ Wpall,
                                                                  int wp, int* __restrict__ flag, int cb, int cw) {
+  __builtin_amdgcn_s_setprio(3);  // critical path (see gj_small_kernel)
   const long long b = blockIdx.y;
   double* A = Aall + b * (long long)m * m;
   int* piv = pivall + b * (long long)m;

@@ -362,9 +362,13 @@ __global__ __launch_bounds__(SRCW_THREADS) __attribute__((amdgpu_waves_per_eu(WP
 }
 
 // src[r] starts rstride doubles after src[r - 1] (nl * npts for a whole
-// operator's sources; larger when the leaves are a slice of a bigger field)
+// operator's sources; larger when the leaves are a slice of a bigger field).
+// max_wg_per_cu > 0 caps the workgroups resident per CU (by reserving unused
+// LDS), leaving registers and LDS on those CUs for work on another stream.
 int leaf_src_launch(const double* LU, const int* perm, const int* pos, const double* src, const int* Ii, int NI,
-                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride) {
+                    int npts, long long nl, int nrhs, double* v, int NRcap, hipStream_t st, long long rstride,
+                    int max_wg_per_cu) {
+  constexpr long long kLdsPerCu = 160 * 1024;
   if (rstride <= 0) rstride = nl * npts;
   if (nrhs > SRC_MAXR) {
     set_error("leaf_src: at most 16 right-hand sides per pass");
@@ -372,9 +376,17 @@ int leaf_src_launch(const double* LU, const int* perm, const int* pos, const dou
   }
   const int rpt = (NI + SRCW_THREADS - 1) / SRCW_THREADS;
   dim3 grid((unsigned)nl), block(SRCW_THREADS);
-#define HPS_SRC_LAUNCH(R, M, W)                                                                                       \
-  hipLaunchKernelGGL((leaf_src_kernel<R, M, W>), grid, block, 0, st, LU, perm, pos, src, Ii, NI, npts, rstride, nrhs, \
-                     v, NRcap)
+#define HPS_SRC_LAUNCH(R, M, W)                                                                              \
+  do {                                                                                                       \
+    size_t shm = 0;                                                                                          \
+    hipFuncAttributes fa;                                                                                    \
+    if (max_wg_per_cu > 0 && hipFuncGetAttributes(&fa, (const void*)leaf_src_kernel<R, M, W>) == hipSuccess) { \
+      const long long want = kLdsPerCu / (max_wg_per_cu + 1) + 256 - (long long)fa.sharedSizeBytes;         \
+      shm = want > 0 ? (size_t)want : 0;                                                                     \
+    }                                                                                                        \
+    hipLaunchKernelGGL((leaf_src_kernel<R, M, W>), grid, block, shm, st, LU, perm, pos, src, Ii, NI, npts,    \
+                       rstride, nrhs, v, NRcap);                                                             \
+  } while (0)
   if (rpt < 1 || rpt > 4) {
     set_error("leaf_src: too many interior points");
     return HPS_EUNSUPPORTED;

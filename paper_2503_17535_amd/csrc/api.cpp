@@ -2503,16 +2503,17 @@ static hipStream_t side_stream() {
   return s;
 }
 
-// the fork follows the last merge level with at least this many nodes (a
-// fork after smaller levels measured no faster: the source solve's waves then
-// slow the root's Gauss-Jordan chain by about what they overlap)
-constexpr long long kForkNodes = 64;
+// the fork follows the last merge level with at least this many nodes: the
+// root's children, so the leaf solves run beside the root merge, whose
+// Gauss-Jordan chains leave most of the GPU idle (forks after the 16- and
+// 64-node levels measured 0.25 ms slower)
+constexpr long long kForkNodes = 4;
 // the second stream's leaf solves keep at most this many workgroups on a CU:
 // at full occupancy they fill its registers for their whole run, and the
 // build's copies and products placed on that CU wait until they finish; the
 // Gauss-Jordan kernels raise their waves' issue priority, so that the chain
-// is not slowed by the leaf solves sharing its SIMDs (2 measured best: 1 makes
-// the leaf solves outlast the top levels, 3 slows the chain)
+// is not slowed by the leaf solves sharing its SIMDs (2 measured best; 4 slows
+// the chain, 1 makes the leaf solves outlast the window)
 constexpr int kSideWgPerCu = 2;
 
 int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int flags, const double* bdry,
@@ -2562,8 +2563,8 @@ int hps_build_solve(const hps_tree_t* tree, int p, const double* coeffs, int fla
   const int L = op->tree.depth, k = std::min(op->NR, nrhs);
   // The source's leaf part (and the upward pass through the levels already
   // built) goes to a second stream once the build has passed the last level
-  // with at least 64 nodes: the levels above it are Gauss-Jordan chains on a
-  // few large matrices that leave most of the GPU idle.  Only products that
+  // with at least kForkNodes nodes: the levels above it are Gauss-Jordan
+  // chains on a few large matrices that leave most of the GPU idle.  Only products that
   // do not split K (the split-K workspace is shared) go there.
   int fork = L;
   for (int lev = L - 1; lev >= 0; --lev)
